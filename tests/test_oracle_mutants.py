@@ -1,0 +1,60 @@
+"""The oracle's pins must fail when a plausible mistake is planted in the oracle.
+
+Each case copies the oracle's C source, makes one small edit (a dropped dt, a
+flipped sign, a wrong exponent or index, a non-conservative update), builds it
+into a temporary library and runs the pin tests against it in a subprocess.
+The pins pass on the real oracle (test_oracle_pins.py); here every mutant must
+make at least one of them fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "flood_oracle.c")
+
+MUTANTS = {
+    "dt_dropped_from_gravity_term": ("double num = q - ((g * hf) * dt) * grad;",
+                                     "double num = q - (g * hf) * grad;"),
+    "gravity_sign_flipped": ("double num = q - ((g * hf) * dt) * grad;",
+                             "double num = q + ((g * hf) * dt) * grad;"),
+    "friction_exponent_4_3": ("/ ((hf * hf) * cbrt(hf));", "/ (hf * cbrt(hf));"),
+    "hf_min_bed": ("double hf = fmax(etaL, etaR) - fmax(zL, zR);",
+                   "double hf = fmax(etaL, etaR) - fmin(zL, zR);"),
+    "face_roughness_one_sided": ("double nf = 0.5 * (nL + nR);", "double nf = nL;"),
+    "boundary_exponent_2_3": ("return x * (c * c);", "return c * c;"),
+    "depth_update_sign": ("h[j * nx + i] + (dt * ((qW - qE) + (qS - qN))) / dx;",
+                          "h[j * nx + i] + (dt * ((qW - qE) + (qN - qS))) / dx;"),
+    "y_faces_use_x_neighbour": ("int64_t L = (j - 1) * nx + i, R = j * nx + i;",
+                                "int64_t L = j * nx + i - (i > 0), R = j * nx + i;"),
+    "donor_wrong_cell": ("if (*q > 0.0 && i >= 1) *q *= r[j * nx + i - 1];",
+                         "if (*q > 0.0 && i < nx) *q *= r[j * nx + i];"),
+    "budget_uses_unscaled_outflow": ("clk->v_out += dt * dx * sum_out;",
+                                     "clk->v_out += 1.0001 * dt * dx * sum_out;"),
+    "cfl_uses_sqrt_h_not_gh": ("dt = fmin(p->dt_max, p->alpha * dx / sqrt(g * hmax));",
+                               "dt = fmin(p->dt_max, p->alpha * dx / sqrt(hmax));"),
+    "inflow_bisection_direction": ("if (F < 0.0) lo = mid; else hi = mid;",
+                                   "if (F > 0.0) lo = mid; else hi = mid;"),
+    "last_step_not_shortened": ("if (dt >= rem) { dt = rem; last = 1; }",
+                                "if (dt >= rem) { last = 1; }"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                    "-shared", "-o", str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, FLOOD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "--timeout", "60",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, f"mutant {name} survived the pins:\n{res.stdout[-2000:]}"
