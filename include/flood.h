@@ -1,0 +1,214 @@
+/*
+ * flood.h -- C interface of libflood, the MI355X (gfx950) library for the
+ * explicit local-inertial shallow-water flood step of Pierce et al.,
+ * "Accelerating Physics Simulations with TPUs: An Inundation Modeling
+ * Example" (arXiv 2204.10323).
+ *
+ * What one step computes (Methods, "Shallow Water Equations"):
+ *   1. dt: a fixed step (the paper's results use 0.1 s at 1 m) or the
+ *      CFL-limited step min(dt_max, alpha*dx/sqrt(g*h_max)), shortened so the
+ *      run ends exactly at t_end (Appendix, DynamicStepUpdater).
+ *   2. boundary faces (eq. 5, 6): the inflow section receives Q_in(t) split
+ *      over its cells by solving for the water level W of eq. (6); each outflow
+ *      cell passes the Manning discharge of its own depth; every other border
+ *      face is a closed wall.
+ *   3. interior faces, eq. (3): semi-implicit update of the discharge per unit
+ *      width from the water-surface gradient with Manning friction, using the
+ *      flow depth h_f = max(eta_L, eta_R) - max(z_L, z_R) of the face.
+ *   4. donor-cell scaling of outgoing discharges so that no cell sends out more
+ *      water than it holds (keeps depths non-negative, conserves volume).
+ *   5. depth update, eq. (4), from the discharge divergence.
+ *   6. the deepest cell of the new state (for the next CFL step) and the FP64
+ *      volume budget of the applied boundary discharges.
+ *
+ * Conventions
+ *   Grids are nx columns (x, contiguous in memory) by ny rows (y), square
+ *   cells of side dx metres.  Cell (i, j) is row j, column i.  Discharges are
+ *   per unit width (m^2/s), positive toward +x / +y.  Discharge arrays
+ *   exchanged through this interface include the border faces:
+ *     qx: ny rows of nx+1 faces, qx[j][i] between cells i-1 and i
+ *         (i = 0 is the west border, i = nx the east border);
+ *     qy: ny+1 rows of nx faces, qy[j][i] between rows j-1 and j
+ *         (j = 0 is the south border, j = ny the north border).
+ *   Element type of every field is float for FL_F32 contexts and double for
+ *   FL_F64 contexts.  Row strides are in elements.
+ *
+ * Ownership: every fl_set_* call copies its input; the caller keeps its
+ * buffers.  Device memory of a context belongs to the context and is freed by
+ * fl_destroy.  A batch borrows its member contexts, which must outlive it.
+ *
+ * Asynchrony: fl_step, fl_advance's launches and fl_batch_run enqueue work on
+ * the context's stream and return.  fl_get_* and fl_get_report synchronise
+ * that stream.
+ *
+ * Errors: every call returns a status; nothing aborts, exits or throws across
+ * the interface.  fl_last_error gives a message for the last failure on a
+ * context (or, for a NULL context, the last failure of fl_create on the
+ * calling thread).  A context is not thread-safe; distinct contexts are
+ * independent.
+ */
+#ifndef FLOOD_H
+#define FLOOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_ctx fl_ctx;
+typedef struct fl_batch fl_batch;
+
+typedef enum {
+    FL_OK = 0,
+    FL_EINVAL = 1,      /* an argument is out of range (see each call) */
+    FL_ENOMEM = 2,      /* device or host allocation failed */
+    FL_EHIP = 3,        /* a HIP runtime call failed; message has hipGetErrorString */
+    FL_ESTATE = 4,      /* call out of order (e.g. stepping before fl_commit) */
+    FL_ENONFINITE = 5   /* a depth became NaN or infinite; the clock has stopped */
+} fl_status;
+
+typedef enum { FL_F32 = 0, FL_F64 = 1 } fl_precision;
+
+/* Boundary side of the grid ("BoundarySide" input of the paper's Appendix). */
+typedef enum { FL_WEST = 0, FL_EAST = 1, FL_SOUTH = 2, FL_NORTH = 3 } fl_side;
+
+/*
+ * Run parameters (Appendix "Inputs": dt, start time, num_secs).
+ *   g          gravitational acceleration, m/s^2 (> 0; 9.81 by default)
+ *   alpha      CFL number of the variable step, in (0, 1]
+ *   dt_max     largest step, s (> 0); used when the grid is dry
+ *   h_eps      a face with flow depth h_f <= h_eps is dry (>= 0, metres)
+ *   dt_fixed   > 0: use this constant step (the paper's mode); 0: CFL step
+ *   t_end      absolute end time, s; +inf for none.  Steps after t_end have
+ *              dt = 0 and leave the state unchanged.
+ *   steps_per_graph  steps captured per HIP graph replay (rounded up to a
+ *              multiple of 6; 0 selects 60)
+ *   positivity 1: donor-cell scaling on (default); 0: off
+ */
+typedef struct {
+    double g, alpha, dt_max, h_eps, dt_fixed, t_end;
+    int32_t steps_per_graph;
+    int32_t positivity;
+} fl_params;
+
+/* State of the clock and the FP64 volume budget (m^3). */
+typedef struct {
+    double t;            /* simulated time, s */
+    double last_dt;      /* dt of the last step taken, s */
+    int64_t steps;       /* steps taken with dt > 0 */
+    double v0;           /* volume at commit */
+    double v_in;         /* inflow volume applied since commit */
+    double v_out;        /* outflow volume applied since commit */
+    double v_now;        /* current volume, dx^2 * sum(h), summed in FP64 */
+    int32_t done;        /* 1 once t reached t_end */
+    int32_t nonfinite;   /* 1 if a depth became NaN/inf (steps stop) */
+} fl_report;
+
+/* Fill *p with the defaults: g 9.81, alpha 0.7, dt_max 0.1, h_eps 1e-4,
+ * dt_fixed 0, t_end +inf, steps_per_graph 60, positivity 1. */
+void fl_default_params(fl_params *p);
+
+/*
+ * Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (for example PyTorch's current stream) or NULL to have the
+ * context create its own.  EINVAL: bad device or precision.  EHIP: HIP error.
+ */
+fl_status fl_create(fl_ctx **ctx, int device, void *hip_stream, fl_precision prec);
+
+/* Grid of nx x ny cells of side dx metres.  EINVAL: nx or ny < 1, dx <= 0 or
+ * not finite, or more than 2^31 cells per row pitch.  Resets everything set
+ * before (DEM, roughness, boundaries, state). */
+fl_status fl_init_grid(fl_ctx *ctx, int32_t nx, int32_t ny, double dx);
+
+/* Bed elevation z (metres, "unpadded_dem"), ny rows of row_stride elements,
+ * host or device memory (on_device = 1).  EINVAL: NULL, row_stride < nx, or a
+ * non-finite value. */
+fl_status fl_set_dem(fl_ctx *ctx, const void *z, int64_t row_stride, int on_device);
+
+/* Per-cell Manning coefficient n (s m^-1/3), same layout.  EINVAL: n <= 0 or
+ * not finite. */
+fl_status fl_set_manning(fl_ctx *ctx, const void *n, int64_t row_stride, int on_device);
+
+/*
+ * Inflow section (eq. 6): cells first .. first+count-1 along `side`
+ * (rows for west/east, columns for south/north), channel slope `slope` and
+ * the hydrograph Q_in(t) as nsamples pairs (t_s seconds, q_m3s m^3/s), host
+ * memory.  Q_in is piecewise linear between samples and constant outside.
+ * count = 0 removes the inflow.  EINVAL: section outside the side, slope <= 0,
+ * Q < 0 or not finite, times not strictly increasing, nsamples < 1 or > 4096.
+ */
+fl_status fl_set_inflow(fl_ctx *ctx, fl_side side, int32_t first, int32_t count, double slope,
+                        const double *t_s, const double *q_m3s, int32_t nsamples);
+
+/* Outflow section: each cell passes the Manning discharge of its own depth
+ * with slope `slope`, outward only.  count = 0 removes it.  EINVAL: section
+ * outside the side, slope <= 0, or overlap with the inflow section. */
+fl_status fl_set_outflow(fl_ctx *ctx, fl_side side, int32_t first, int32_t count, double slope);
+
+/* EINVAL: g <= 0, alpha outside (0, 1], dt_max <= 0, h_eps < 0, dt_fixed < 0,
+ * t_end NaN. */
+fl_status fl_set_params(fl_ctx *ctx, const fl_params *p);
+
+/*
+ * Initial state: depth h (ny x nx, row stride nx), discharges qx (ny x (nx+1))
+ * and qy ((ny+1) x nx) in the layout described above (NULL = zero), and the
+ * time t.  Border-face discharges are accepted but recomputed by the boundary
+ * conditions each step.  EINVAL: h < 0 or any value not finite.
+ * Without this call the grid starts dry and still at t = 0.
+ */
+fl_status fl_set_state(fl_ctx *ctx, const void *h, const void *qx, const void *qy, double t,
+                       int on_device);
+
+/* Validate, allocate device memory, upload, reset clock and budget, capture
+ * the multi-step graph.  Must follow fl_init_grid, fl_set_dem and
+ * fl_set_manning (ESTATE otherwise).  Any fl_set_* after commit needs a new
+ * commit before stepping. */
+fl_status fl_commit(fl_ctx *ctx);
+
+/* Enqueue nsteps steps (graph replays plus single launches).  ESTATE before
+ * commit.  EINVAL: nsteps < 0. */
+fl_status fl_step(fl_ctx *ctx, int64_t nsteps);
+
+/* Advance the simulated time by `seconds` (the last step shortened to land on
+ * it), like the paper's DynamicStepUpdater.  Synchronises periodically to
+ * watch the clock; returns when the target time is reached (or a non-finite
+ * depth stopped the clock: ENONFINITE). */
+fl_status fl_advance(fl_ctx *ctx, double seconds);
+
+/* Copy the current depth into dst (ny rows of row_stride elements). */
+fl_status fl_get_depth(fl_ctx *ctx, void *dst, int64_t row_stride, int on_device);
+
+/* Copy the current discharges, border faces included (layout above). */
+fl_status fl_get_discharge(fl_ctx *ctx, void *qx, void *qy, int on_device);
+
+/* Clock and volume budget.  Synchronises.  ENONFINITE if a depth became
+ * non-finite (the report is still filled). */
+fl_status fl_get_report(fl_ctx *ctx, fl_report *r);
+
+/* Message of the last failure on ctx (ctx NULL: last fl_create failure on
+ * this thread).  Never NULL. */
+const char *fl_last_error(const fl_ctx *ctx);
+
+/* Free the context and its device memory (synchronises first).  NULL is a no-op. */
+void fl_destroy(fl_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Timing helper used by the benchmark: enqueue nsteps steps exactly as
+ * fl_step does, bracketed by HIP events recorded on the context's stream, and
+ * return the elapsed milliseconds (synchronises).  */
+fl_status fl_time_steps(fl_ctx *ctx, int64_t nsteps, double *elapsed_ms);
+
+/* Launch configuration of the step kernel: cells per lane along x (1, 2, 4)
+ * and rows per work item (>= 1).  Takes effect at the next fl_commit. 0 keeps
+ * the default.  EINVAL: unsupported value. */
+fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_item);
+
+/* Bytes of device memory the context holds after commit. */
+size_t fl_device_bytes(const fl_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLOOD_H */

@@ -1,0 +1,279 @@
+"""Python binding of libflood (include/flood.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libflood.so; this module
+only converts arrays and calls the C functions of the same names.  Importing
+works without a GPU; loading the library raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflood.so")
+
+FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ESTATE, FL_ENONFINITE = range(6)
+FL_F32, FL_F64 = 0, 1
+FL_WEST, FL_EAST, FL_SOUTH, FL_NORTH = range(4)
+STATUS_NAMES = {0: "FL_OK", 1: "FL_EINVAL", 2: "FL_ENOMEM", 3: "FL_EHIP", 4: "FL_ESTATE",
+                5: "FL_ENONFINITE"}
+
+# Every symbol include/flood.h declares.
+EXPORTS = [
+    "fl_default_params", "fl_create", "fl_init_grid", "fl_set_dem", "fl_set_manning",
+    "fl_set_inflow", "fl_set_outflow", "fl_set_params", "fl_set_state", "fl_commit", "fl_step",
+    "fl_advance", "fl_get_depth", "fl_get_discharge", "fl_get_report", "fl_last_error",
+    "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes",
+]
+
+
+class FloodError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class fl_params(C.Structure):
+    _fields_ = [("g", C.c_double), ("alpha", C.c_double), ("dt_max", C.c_double),
+                ("h_eps", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
+                ("steps_per_graph", C.c_int32), ("positivity", C.c_int32)]
+
+
+class fl_report(C.Structure):
+    _fields_ = [("t", C.c_double), ("last_dt", C.c_double), ("steps", C.c_int64),
+                ("v0", C.c_double), ("v_in", C.c_double), ("v_out", C.c_double),
+                ("v_now", C.c_double), ("done", C.c_int32), ("nonfinite", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+    def budget_error(self) -> float:
+        return abs(self.v_now - self.v0 - self.v_in + self.v_out) / max(self.v0 + self.v_in, 1e-300)
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libflood.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "fl_default_params": (None, [C.POINTER(fl_params)]),
+            "fl_create": (C.c_int, [C.POINTER(vp), C.c_int, vp, C.c_int]),
+            "fl_init_grid": (C.c_int, [vp, i32, i32, dbl]),
+            "fl_set_dem": (C.c_int, [vp, vp, i64, C.c_int]),
+            "fl_set_manning": (C.c_int, [vp, vp, i64, C.c_int]),
+            "fl_set_inflow": (C.c_int, [vp, C.c_int, i32, i32, dbl, C.POINTER(dbl),
+                                        C.POINTER(dbl), i32]),
+            "fl_set_outflow": (C.c_int, [vp, C.c_int, i32, i32, dbl]),
+            "fl_set_params": (C.c_int, [vp, C.POINTER(fl_params)]),
+            "fl_set_state": (C.c_int, [vp, vp, vp, vp, dbl, C.c_int]),
+            "fl_commit": (C.c_int, [vp]),
+            "fl_step": (C.c_int, [vp, i64]),
+            "fl_advance": (C.c_int, [vp, dbl]),
+            "fl_get_depth": (C.c_int, [vp, vp, i64, C.c_int]),
+            "fl_get_discharge": (C.c_int, [vp, vp, vp, C.c_int]),
+            "fl_get_report": (C.c_int, [vp, C.POINTER(fl_report)]),
+            "fl_last_error": (C.c_char_p, [vp]),
+            "fl_destroy": (None, [vp]),
+            "fl_time_steps": (C.c_int, [vp, i64, C.POINTER(dbl)]),
+            "fl_set_tiling": (C.c_int, [vp, i32, i32]),
+            "fl_device_bytes": (C.c_size_t, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status: int):
+    if status != FL_OK:
+        msg = lib().fl_last_error(ctx)
+        raise FloodError(status, msg.decode() if msg else "")
+
+
+def default_params(**over) -> fl_params:
+    p = fl_params()
+    lib().fl_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def _np_dtype(prec: int):
+    return np.float64 if prec == FL_F64 else np.float32
+
+
+def _torch_stream_ptr():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def _as_input(a, dtype):
+    """(pointer, row_stride, on_device, keepalive) for a 2-D numpy array or torch tensor."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            tdt = torch.float64 if dtype == np.float64 else torch.float32
+            if a.is_cuda:
+                t = a.to(tdt)
+                if t.stride(1) != 1:
+                    t = t.contiguous()
+                return C.c_void_p(t.data_ptr()), t.stride(0), 1, t
+            a = a.detach().cpu().numpy()
+    except ImportError:
+        pass
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return C.c_void_p(arr.ctypes.data), arr.shape[-1] if arr.ndim > 1 else arr.size, 0, arr
+
+
+class Flood:
+    """One flood context (fl_ctx): a grid, its inputs, and its device state.
+
+    Methods map one-to-one onto the C functions fl_<name>; arrays may be numpy
+    (host) or torch CUDA tensors (device).
+    """
+
+    def __init__(self, nx: int, ny: int, dx: float, precision: str = "f32", device: int = 0,
+                 stream=None):
+        self.prec = FL_F64 if precision in ("f64", "fp64", "double") else FL_F32
+        self.dtype = _np_dtype(self.prec)
+        self.nx, self.ny, self.dx = int(nx), int(ny), float(dx)
+        h = C.c_void_p()
+        s = stream if stream is not None else _torch_stream_ptr()
+        st = lib().fl_create(C.byref(h), device, s, self.prec)
+        if st != FL_OK:
+            raise FloodError(st, lib().fl_last_error(None).decode())
+        self.ctx = h
+        _check(self.ctx, lib().fl_init_grid(self.ctx, self.nx, self.ny, self.dx))
+
+    # -- inputs
+    def set_dem(self, z):
+        p, stride, dev, keep = _as_input(z, self.dtype)
+        _check(self.ctx, lib().fl_set_dem(self.ctx, p, stride, dev))
+
+    def set_manning(self, n):
+        p, stride, dev, keep = _as_input(n, self.dtype)
+        _check(self.ctx, lib().fl_set_manning(self.ctx, p, stride, dev))
+
+    def set_inflow(self, side: int, first: int, count: int, slope: float, t_s, q_m3s):
+        ts = np.ascontiguousarray(t_s, dtype=np.float64)
+        qs = np.ascontiguousarray(q_m3s, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        _check(self.ctx, lib().fl_set_inflow(self.ctx, side, first, count, slope,
+                                             ts.ctypes.data_as(dp), qs.ctypes.data_as(dp),
+                                             len(ts)))
+
+    def set_outflow(self, side: int, first: int, count: int, slope: float):
+        _check(self.ctx, lib().fl_set_outflow(self.ctx, side, first, count, slope))
+
+    def set_params(self, **kw):
+        p = default_params(**kw)
+        _check(self.ctx, lib().fl_set_params(self.ctx, C.byref(p)))
+
+    def set_state(self, h, qx=None, qy=None, t: float = 0.0):
+        ph, _, dev, k1 = _as_input(h, self.dtype)
+        px = py = None
+        k2 = k3 = None
+        if qx is not None:
+            px, _, d2, k2 = _as_input(qx, self.dtype)
+        if qy is not None:
+            py, _, d3, k3 = _as_input(qy, self.dtype)
+        _check(self.ctx, lib().fl_set_state(self.ctx, ph, px, py, float(t), dev))
+
+    def set_tiling(self, cells_per_lane: int = 0, rows_per_item: int = 0):
+        _check(self.ctx, lib().fl_set_tiling(self.ctx, cells_per_lane, rows_per_item))
+
+    def commit(self):
+        _check(self.ctx, lib().fl_commit(self.ctx))
+
+    # -- stepping
+    def step(self, nsteps: int):
+        _check(self.ctx, lib().fl_step(self.ctx, int(nsteps)))
+
+    def advance(self, seconds: float):
+        _check(self.ctx, lib().fl_advance(self.ctx, float(seconds)))
+
+    def time_steps(self, nsteps: int) -> float:
+        ms = C.c_double()
+        _check(self.ctx, lib().fl_time_steps(self.ctx, int(nsteps), C.byref(ms)))
+        return ms.value
+
+    # -- outputs
+    def get_depth(self, out=None) -> np.ndarray:
+        if out is not None:
+            p, stride, dev, keep = _as_input(out, self.dtype)
+            _check(self.ctx, lib().fl_get_depth(self.ctx, p, stride, dev))
+            return out
+        h = np.empty((self.ny, self.nx), dtype=self.dtype)
+        _check(self.ctx, lib().fl_get_depth(self.ctx, C.c_void_p(h.ctypes.data), self.nx, 0))
+        return h
+
+    def get_discharge(self) -> Tuple[np.ndarray, np.ndarray]:
+        qx = np.empty((self.ny, self.nx + 1), dtype=self.dtype)
+        qy = np.empty((self.ny + 1, self.nx), dtype=self.dtype)
+        _check(self.ctx, lib().fl_get_discharge(self.ctx, C.c_void_p(qx.ctypes.data),
+                                                C.c_void_p(qy.ctypes.data), 0))
+        return qx, qy
+
+    def get_report(self, check: bool = True) -> fl_report:
+        r = fl_report()
+        st = lib().fl_get_report(self.ctx, C.byref(r))
+        if check:
+            _check(self.ctx, st)
+        return r
+
+    def device_bytes(self) -> int:
+        return int(lib().fl_device_bytes(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().fl_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,
+                  cells_per_lane: int = 0, rows_per_item: int = 0, **param_over) -> Flood:
+    """A committed context for a synthetic scenario (see the `synth` module)."""
+    f = Flood(sc.nx, sc.ny, sc.dx, precision, device, stream)
+    f.set_dem(sc.z)
+    f.set_manning(sc.n)
+    if sc.inflow is not None:
+        side, first, count, slope, ts, qs = sc.inflow
+        f.set_inflow(side, first, count, slope, ts, qs)
+    if sc.outflow is not None:
+        f.set_outflow(*sc.outflow)
+    params = dict(g=sc.g, alpha=sc.alpha, dt_max=sc.dt_max, h_eps=sc.h_eps,
+                  dt_fixed=sc.dt_fixed, t_end=sc.t_end)
+    params.update(param_over)
+    f.set_params(**params)
+    qx0, qy0 = sc.extra.get("qx0"), sc.extra.get("qy0")
+    if qx0 is not None or qy0 is not None or np.any(sc.h0):
+        f.set_state(sc.h0, qx0, qy0, 0.0)
+    if cells_per_lane or rows_per_item:
+        f.set_tiling(cells_per_lane, rows_per_item)
+    if commit:
+        f.commit()
+    return f

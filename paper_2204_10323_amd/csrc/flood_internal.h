@@ -1,0 +1,84 @@
+// Internal declarations shared by the runtime and the kernels of libflood.
+// Not part of the public interface (include/flood.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flood {
+
+// Padded device layout of every cell or face field: two halo rows above and
+// below, two halo columns on the left, row pitch `pitch` elements (a multiple
+// of 256 bytes, at least nx + 8).  Cell (i, j) lives at (j + 2) * pitch + i + 2.
+// qx holds the face east of each cell, qy the face north of each cell; the
+// west and south border faces live in the edge arrays edge_w[ny], edge_s[nx].
+constexpr int kHalo = 2;
+
+// One slot of the double-buffered device clock.
+struct ClockSlot {
+    double t;          // simulated time at the start of the step that reads it
+    double dt_prev;    // dt of the step that produced this state
+    double v_in;       // inflow volume applied so far (FP64)
+    double v_out;      // outflow volume applied so far, up to the step before dt_prev's
+    long long steps;   // steps taken with dt > 0
+    int done;          // t reached t_end
+    int nonfinite;     // a depth became NaN or infinite
+};
+
+// Device control block of one context.
+struct DevCtl {
+    ClockSlot clk[2];            // read clk[n % 2], written clk[(n + 1) % 2] by step n
+    unsigned long long hmax[3];  // deepest cell as ordered bits: read [n%3], max into [(n+1)%3]
+    double t_end;                // effective end time (host may lower it between launches)
+    double report[8];            // filled by the flush kernel
+};
+
+template <typename T>
+struct StepArgs {
+    const T* h_in;
+    const T* qx_in;
+    const T* qy_in;
+    T* h_out;
+    T* qx_out;
+    T* qy_out;
+    const T* z;
+    const T* n;
+    T* edge_w;          // west border face values of the new state [ny]
+    T* edge_s;          // south border face values of the new state [nx]
+    const T* kout;      // outflow coefficient sqrt(S_out)/n_c along the outflow side (0 elsewhere)
+    const T* qin;       // inflow face magnitudes applied this step, along the inflow side
+    T* qin_next;        // written by the clock block for the next step
+    const double* in_z; // inflow-section bed elevations (FP64)
+    const double* in_k; // inflow-section sqrt(S_in)/n_c (FP64)
+    const double* ts;   // hydrograph times
+    const double* qs;   // hydrograph discharges
+    double* part_cur;   // outflow partial sums written by this step [npart]
+    const double* part_prev;  // partial sums of the previous step
+    DevCtl* ctl;
+    long long pitch;
+    int nx, ny;
+    int in_side, in_first, in_count, nsamp;
+    int out_side, out_first, out_count, npart;
+    int positivity;
+    int nstrips, nchunks, rows;   // tiling: strips along x, chunks of `rows` rows along y
+    int phase;                    // step index modulo 6
+    double dx, g, alpha, dt_max, h_eps, dt_fixed;
+};
+
+// Host-side launchers (flood_kernels.hip).
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s);
+template <typename T>
+hipError_t launch_prime(const StepArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_flush(const StepArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl* ctl,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* partials,
+                         int nparts, double* out, hipStream_t s);
+
+int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
+constexpr int kVolumeParts = 1024;
+
+}  // namespace flood

@@ -1,0 +1,630 @@
+// Kernels of libflood: the fused flood step for gfx950 (wave64), its device
+// clock, and the FP64 reductions.
+//
+// One step (Methods, "Shallow Water Equations", eqs. 3-6) is ONE launch:
+//   * block 0 is the clock block: it closes the volume budget of the previous
+//     step, advances the FP64 clock and solves eq. (6) for the next step's
+//     inflow, concurrently with the tiles;
+//   * every other wave marches up one work item: a strip of 64*CPT loaded
+//     columns (64*CPT - 4 output columns) over `rows` output rows.  The wave
+//     keeps a rolling window of the last rows in registers; left/right
+//     neighbours come from the adjacent lanes by cross-lane moves, so each
+//     value is read from HBM once per strip.  The 2 halo columns at each strip
+//     edge are recomputed redundantly by both strips with the same code, so a
+//     face shared by two strips gets bit-identical values.
+// Per cell and step the kernel reads h, z, n, qx, qy and writes h, qx, qy:
+// 32 bytes in FP32, 64 in FP64.  Nothing here is a dense contraction, so there
+// is no MFMA; the bound is HBM bandwidth.
+#include <math.h>
+
+#include "flood_internal.h"
+
+namespace flood {
+
+enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
+
+// ------------------------------------------------------------------ helpers
+// Ordered bits of a depth for the max-reduction: negative -> 0, NaN above +inf.
+template <typename T> struct Ord;
+template <> struct Ord<float> {
+    static __device__ __forceinline__ unsigned long long bits(float h) {
+        if (h >= 0.0f) return (unsigned long long)__float_as_uint(h);
+        if (h < 0.0f) return 0ull;
+        return 0x7fc00000ull;
+    }
+    static __device__ __forceinline__ double value(unsigned long long b) {
+        return (double)__uint_as_float((unsigned)b);
+    }
+    static __device__ __forceinline__ bool nonfinite(unsigned long long b) { return b >= 0x7f800000ull; }
+};
+template <> struct Ord<double> {
+    static __device__ __forceinline__ unsigned long long bits(double h) {
+        if (h >= 0.0) return (unsigned long long)__double_as_longlong(h);
+        if (h < 0.0) return 0ull;
+        return 0x7ff8000000000000ull;
+    }
+    static __device__ __forceinline__ double value(unsigned long long b) {
+        return __longlong_as_double((long long)b);
+    }
+    static __device__ __forceinline__ bool nonfinite(unsigned long long b) {
+        return b >= 0x7ff0000000000000ull;
+    }
+};
+
+__device__ __forceinline__ float cbrt_t(float x) { return cbrtf(x); }
+__device__ __forceinline__ double cbrt_t(double x) { return cbrt(x); }
+
+// x^(5/3) for x > 0, else 0.
+template <typename T>
+__device__ __forceinline__ T pow53(T x) {
+    if (!(x > T(0))) return T(0);
+    T c = cbrt_t(x);
+    return x * (c * c);
+}
+
+template <typename T>
+__device__ __forceinline__ T from_next(T v) { return __shfl_down(v, 1, 64); }
+template <typename T>
+__device__ __forceinline__ T from_prev(T v) { return __shfl_up(v, 1, 64); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), o, 64);
+        unsigned hi = __shfl_xor((unsigned)(v >> 32), o, 64);
+        unsigned long long w = ((unsigned long long)hi << 32) | lo;
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecT { T v[N]; };
+
+template <typename T, int N>
+__device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
+    VecT<T, N> t = *reinterpret_cast<const VecT<T, N>*>(p);
+#pragma unroll
+    for (int m = 0; m < N; ++m) o[m] = t.v[m];
+}
+template <typename T, int N>
+__device__ __forceinline__ void stv(T* p, const T (&o)[N]) {
+    VecT<T, N> t;
+#pragma unroll
+    for (int m = 0; m < N; ++m) t.v[m] = o[m];
+    *reinterpret_cast<VecT<T, N>*>(p) = t;
+}
+
+// ------------------------------------------------------------ the physics
+// Eq. (3) on one face between cells L and R (R on the +axis side).  q is the
+// face discharge at the start of the step; gdt = g*dt.  Flow depth h_f is the
+// higher water surface minus the higher bed; a face with h_f <= h_eps is dry.
+// Friction uses the face's own |q| (per-axis 1-D form) and n_f = (n_L+n_R)/2.
+template <typename T>
+__device__ __forceinline__ T face_q(T etaL, T etaR, T zL, T zR, T nL, T nR, T q, T gdt,
+                                    T inv_dx, T h_eps) {
+    T hf = fmax(etaL, etaR) - fmax(zL, zR);
+    if (hf <= h_eps) return T(0);
+    T nf = T(0.5) * (nL + nR);
+    T grad = (etaR - etaL) * inv_dx;
+    T num = q - (gdt * hf) * grad;
+    T den = T(1) + ((gdt * (nf * nf)) * fabs(q)) / ((hf * hf) * cbrt_t(hf));
+    return num / den;
+}
+
+// Border face value (eq. 5, 6), signed toward +axis.  Inflow magnitudes come
+// from the clock block's solve; outflow is the Manning discharge of the edge
+// cell's own depth; everything else is a closed wall.
+template <typename T>
+__device__ __forceinline__ T border_q(const StepArgs<T>& a, int side, int p, T h_edge) {
+    T v = T(0);
+    if (a.in_side == side) v = a.qin[p];
+    if (a.out_side == side) v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
+    return (side == SIDE_W || side == SIDE_S) ? v : -v;
+}
+
+// dt of this step from the clock slot and the deepest cell of the current
+// state: the fixed step, or min(dt_max, alpha dx / sqrt(g h_max)); shortened to
+// land on t_end; 0 once done or non-finite.  Rounded to T (the step uses it).
+template <typename T>
+__device__ __forceinline__ double step_dt(const StepArgs<T>& a, const ClockSlot& ck,
+                                          unsigned long long hb, double t_end, int& last,
+                                          int& done, int& nonfin) {
+    last = 0;
+    done = 0;
+    nonfin = ck.nonfinite || Ord<T>::nonfinite(hb);
+    if (nonfin) return 0.0;
+    double dt;
+    if (a.dt_fixed > 0.0) {
+        dt = a.dt_fixed;
+    } else {
+        double hm = Ord<T>::value(hb);
+        dt = hm > 0.0 ? fmin(a.dt_max, a.alpha * a.dx / sqrt(a.g * hm)) : a.dt_max;
+    }
+    double rem = t_end - ck.t;
+    if (!(rem > 0.0)) {
+        done = 1;
+        return 0.0;
+    }
+    if (dt >= rem) {
+        dt = rem;
+        last = 1;
+    }
+    return (double)(T)dt;
+}
+
+// Q_in(t): piecewise linear between samples, constant outside.
+template <typename T>
+__device__ double hydrograph(const StepArgs<T>& a, double t) {
+    const int ns = a.nsamp;
+    if (ns <= 0) return 0.0;
+    if (t <= a.ts[0]) return a.qs[0];
+    if (t >= a.ts[ns - 1]) return a.qs[ns - 1];
+    int lo = 0, hi = ns - 1;  // ts[lo] <= t < ts[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (a.ts[mid] <= t) lo = mid; else hi = mid;
+    }
+    return a.qs[lo] + (a.qs[hi] - a.qs[lo]) * ((t - a.ts[lo]) / (a.ts[hi] - a.ts[lo]));
+}
+
+// Eq. (6) on one wave: water level W with sum_c dx k_c (W - z_c)_+^{5/3} = Q,
+// bracketed and bisected 64 times in FP64; writes the per-cell face
+// discharges (per unit width) into dst[first .. first+count).
+template <typename T>
+__device__ void inflow_solve(const StepArgs<T>& a, double Q, T* dst) {
+    const int lane = threadIdx.x & 63;
+    const int nc = a.in_count;
+    if (nc <= 0) return;
+    if (!(Q > 0.0)) {
+        for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = T(0);
+        return;
+    }
+    double lo = 1e300, hi = -1e300, ks = 0.0;
+    for (int p = lane; p < nc; p += 64) {
+        lo = fmin(lo, a.in_z[p]);
+        hi = fmax(hi, a.in_z[p]);
+        ks += a.in_k[p];
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    ks = wave_sum(ks);
+    hi += pow(Q / (a.dx * ks), 0.6);
+    for (int it = 0; it < 64; ++it) {
+        double mid = 0.5 * (lo + hi), F = 0.0;
+        for (int p = lane; p < nc; p += 64) F += a.dx * a.in_k[p] * pow53(mid - a.in_z[p]);
+        F = wave_sum(F) - Q;
+        if (F < 0.0) lo = mid; else hi = mid;
+    }
+    const double W = 0.5 * (lo + hi);
+    for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = (T)(a.in_k[p] * pow53(W - a.in_z[p]));
+}
+
+// The clock block (one wave of block 0): closes the budget of the previous
+// step, advances the clock to the end of this step and prepares the inflow of
+// the next step.  Runs concurrently with the tiles of this step, which only
+// read the current clock slot.
+template <typename T>
+__device__ void clock_block(const StepArgs<T>& a) {
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    DevCtl* ctl = a.ctl;
+    const int cur = a.phase & 1, nxt = cur ^ 1;
+    const ClockSlot ck = ctl->clk[cur];
+    const double t_end = ctl->t_end;
+    int last, done, nonfin;
+    const double dt = step_dt<T>(a, ck, ctl->hmax[a.phase % 3], t_end, last, done, nonfin);
+
+    double so = 0.0;
+    for (int p = lane; p < a.npart; p += 64) so += a.part_prev[p];
+    so = wave_sum(so);
+    double si = 0.0;
+    for (int p = lane; p < a.in_count; p += 64) si += (double)a.qin[a.in_first + p];
+    si = wave_sum(si);
+
+    ClockSlot nk = ck;
+    nk.t = last ? t_end : ck.t + dt;
+    nk.dt_prev = dt;
+    nk.v_in = ck.v_in + dt * a.dx * si;
+    nk.v_out = ck.v_out + ck.dt_prev * a.dx * so;
+    nk.steps = ck.steps + (dt > 0.0 ? 1 : 0);
+    nk.done = (done || last) ? 1 : 0;
+    nk.nonfinite = nonfin ? 1 : 0;
+
+    inflow_solve<T>(a, hydrograph<T>(a, nk.t), a.qin_next);
+    if (lane == 0) {
+        ctl->hmax[(a.phase + 2) % 3] = 0ull;
+        ctl->clk[nxt] = nk;
+    }
+}
+
+// One work item: strip s (columns), chunk c (rows).  Accumulates the ordered
+// bits of the deepest new depth and the outflow discharge leaving the grid.
+template <typename T, int CPT>
+__device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned long long& hbits,
+                          double& outacc) {
+    constexpr int WL = 64 * CPT;  // loaded columns
+    constexpr int WO = WL - 4;    // output columns
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx, ny = a.ny;
+    const long long P = a.pitch;
+    const int pcol = s * WO + lane * CPT;  // padded column of my first cell
+    const int i0 = pcol - kHalo;           // its real column
+    const bool loads = pcol < nx + 2 * kHalo;
+    const int j0 = c * a.rows;
+    const int j1 = min(j0 + a.rows, ny);
+    const T inv_dx = T(1) / T(a.dx);
+    const T gdt = T(a.g) * dt;
+    const T h_eps = T(a.h_eps);
+    // Strips whose loaded columns include a border face apply its boundary
+    // condition (the east border can sit in the halo of the second-last strip).
+    const bool west_strip = (s == 0);
+    const bool east_strip = (nx - 1 >= s * WO - kHalo) && (nx - 1 < s * WO - kHalo + WL);
+    const bool south_chunk = (j0 == 0);
+
+    bool outside[CPT], west_face[CPT], east_face[CPT], store_col[CPT];
+    bool all_store = true;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int i = i0 + m, l = lane * CPT + m;
+        outside[m] = (i < 0 || i >= nx);
+        west_face[m] = (i == -1);
+        east_face[m] = (i == nx - 1);
+        store_col[m] = (l >= kHalo && l < WL - kHalo && i < nx);
+        all_store = all_store && store_col[m];
+    }
+    bool any_store = false;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) any_store = any_store || store_col[m];
+
+    T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
+    auto load_row = [&](int k) {
+        if (loads) {
+            const long long o = (long long)(k + kHalo) * P + pcol;
+            ldv<T, CPT>(a.h_in + o, hN);
+            ldv<T, CPT>(a.z + o, zN);
+            ldv<T, CPT>(a.n + o, nN);
+            ldv<T, CPT>(a.qx_in + o, qxN);
+            ldv<T, CPT>(a.qy_in + o, qyN);
+        } else {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
+        }
+    };
+
+    // Rolling window (row index relative to the row k just loaded).
+    T eta1[CPT], z1[CPT], n1[CPT], qy1[CPT], h1[CPT], h2[CPT];
+    T qsx1[CPT], qsy2[CPT], r2[CPT], qnx2[CPT], qny3[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        eta1[m] = z1[m] = n1[m] = qy1[m] = h1[m] = h2[m] = T(0);
+        qsx1[m] = qsy2[m] = qnx2[m] = qny3[m] = T(0);
+        r2[m] = T(1);
+    }
+
+    load_row(j0 - 2);
+    for (int k = j0 - 2; k <= j1 + 1; ++k) {
+        T h0[CPT], z0[CPT], n0[CPT], qx0[CPT], qy0[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
+        }
+        if (k < j1 + 1) load_row(k + 1);
+        const bool row_real = (k >= 0 && k < ny);
+
+        // A: x-faces of row k (eq. 3), border faces from the boundary conditions.
+        T eta0[CPT], qsx0[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) eta0[m] = h0[m] + z0[m];
+        const T etaRn = from_next(eta0[0]), zRn = from_next(z0[0]), nRn = from_next(n0[0]);
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const T eR = (m + 1 < CPT) ? eta0[(m + 1) % CPT] : etaRn;
+            const T zR = (m + 1 < CPT) ? z0[(m + 1) % CPT] : zRn;
+            const T nR = (m + 1 < CPT) ? n0[(m + 1) % CPT] : nRn;
+            qsx0[m] = face_q<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], gdt, inv_dx, h_eps);
+        }
+        if (west_strip) {
+            const T hRn = from_next(h0[0]);
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (west_face[m]) {
+                    const T hR = (m + 1 < CPT) ? h0[(m + 1) % CPT] : hRn;
+                    qsx0[m] = row_real ? border_q<T>(a, SIDE_W, k, hR) : T(0);
+                }
+        }
+        if (east_strip) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (east_face[m]) qsx0[m] = row_real ? border_q<T>(a, SIDE_E, k, h0[m]) : T(0);
+        }
+
+        // B: y-faces between rows k-1 and k.
+        T qsy1[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m)
+            qsy1[m] = face_q<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], gdt, inv_dx,
+                                h_eps);
+        if (k - 1 == -1) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                qsy1[m] = outside[m] ? T(0) : border_q<T>(a, SIDE_S, i0 + m, h0[m]);
+        } else if (k - 1 == ny - 1) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                qsy1[m] = outside[m] ? T(0) : border_q<T>(a, SIDE_N, i0 + m, h1[m]);
+        }
+
+        // C: donor scaling factor of row k-1.
+        const bool row1_real = (k - 1 >= 0 && k - 1 < ny);
+        const T qWn = from_prev(qsx1[CPT - 1]);
+        T r1[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const T qW = (m > 0) ? qsx1[(m + CPT - 1) % CPT] : qWn;
+            T out = fmax(T(0), -qW);
+            out += fmax(T(0), qsx1[m]);
+            out += fmax(T(0), -qsy2[m]);
+            out += fmax(T(0), qsy1[m]);
+            const T O = (dt * out) * inv_dx;
+            const T hp = fmax(h1[m], T(0));
+            const T rr = (O > hp) ? hp / O : T(1);
+            r1[m] = (a.positivity && row1_real && !outside[m]) ? rr : T(1);
+        }
+
+        // D: applied discharges: x-faces of row k-1 and y-faces between rows k-2 and k-1.
+        const T rRn = from_next(r1[0]);
+        T qnx1[CPT], qny2[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            const T rR = (m + 1 < CPT) ? r1[(m + 1) % CPT] : rRn;
+            qnx1[m] = qsx1[m] * (qsx1[m] > T(0) ? r1[m] : rR);
+            qny2[m] = qsy2[m] * (qsy2[m] > T(0) ? r2[m] : r1[m]);
+        }
+
+        // E: depth of row k-2 (eq. 4) and the stores of the new state.
+        const T qnWn = from_prev(qnx2[CPT - 1]);
+        const int ko = k - 2;
+        if (ko >= j0 && ko < j1) {
+            T hn[CPT];
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                const T qW = (m > 0) ? qnx2[(m + CPT - 1) % CPT] : qnWn;
+                hn[m] = h2[m] + (dt * ((qW - qnx2[m]) + (qny3[m] - qny2[m]))) * inv_dx;
+            }
+            const long long o = (long long)(ko + kHalo) * P + pcol;
+            if (all_store) {
+                stv<T, CPT>(a.h_out + o, hn);
+                stv<T, CPT>(a.qx_out + o, qnx2);
+                stv<T, CPT>(a.qy_out + o, qny2);
+            } else if (any_store) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    if (store_col[m]) {
+                        a.h_out[o + m] = hn[m];
+                        a.qx_out[o + m] = qnx2[m];
+                        a.qy_out[o + m] = qny2[m];
+                    }
+            }
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (store_col[m]) {
+                    const unsigned long long b = Ord<T>::bits(hn[m]);
+                    hbits = b > hbits ? b : hbits;
+                }
+            if (west_strip) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    if (west_face[m]) {
+                        a.edge_w[ko] = qnx2[m];
+                        if (a.out_side == SIDE_W && a.kout[ko] > T(0)) outacc -= (double)qnx2[m];
+                    }
+            }
+            if (east_strip && a.out_side == SIDE_E) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    if (east_face[m] && store_col[m] && a.kout[ko] > T(0)) outacc += (double)qnx2[m];
+            }
+            if (ko == ny - 1 && a.out_side == SIDE_N) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    if (store_col[m] && a.kout[i0 + m] > T(0)) outacc += (double)qny2[m];
+            }
+        } else if (ko == -1 && south_chunk) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (store_col[m]) {
+                    a.edge_s[i0 + m] = qny2[m];
+                    if (a.out_side == SIDE_S && a.kout[i0 + m] > T(0)) outacc -= (double)qny2[m];
+                }
+        }
+
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            h2[m] = h1[m]; h1[m] = h0[m];
+            eta1[m] = eta0[m]; z1[m] = z0[m]; n1[m] = n0[m]; qy1[m] = qy0[m];
+            qsx1[m] = qsx0[m]; qsy2[m] = qsy1[m]; r2[m] = r1[m];
+            qnx2[m] = qnx1[m]; qny3[m] = qny2[m];
+        }
+    }
+}
+
+// Outflow partial-sum slot of a work item, or -1 if it has no outflow face.
+template <typename T>
+__device__ __forceinline__ int part_slot(const StepArgs<T>& a, int s, int c) {
+    switch (a.out_side) {
+    case SIDE_W: return s == 0 ? c : -1;
+    case SIDE_E: return s == a.nstrips - 1 ? c : -1;
+    case SIDE_S: return c == 0 ? s : -1;
+    case SIDE_N: return c == a.nchunks - 1 ? s : -1;
+    default: return -1;
+    }
+}
+
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
+    if (blockIdx.x == 0) {
+        clock_block<T>(a);
+        return;
+    }
+    const int wave = (blockIdx.x - 1) * 4 + (threadIdx.x >> 6);
+    if (wave >= a.nstrips * a.nchunks) return;
+    const ClockSlot ck = a.ctl->clk[a.phase & 1];
+    int last, done, nonfin;
+    const double dt64 = step_dt<T>(a, ck, a.ctl->hmax[a.phase % 3], a.ctl->t_end, last, done, nonfin);
+    const int s = wave % a.nstrips, c = wave / a.nstrips;
+    unsigned long long hb = 0;
+    double outacc = 0.0;
+    step_item<T, CPT>(a, s, c, (T)dt64, hb, outacc);
+    hb = wave_max_u64(hb);
+    const int slot = part_slot<T>(a, s, c);
+    if (slot >= 0) outacc = wave_sum(outacc);
+    if ((threadIdx.x & 63) == 0) {
+        if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], hb);
+        if (slot >= 0) a.part_cur[slot] = outacc;
+    }
+}
+
+// Inflow applied by the first step after commit (the clock slot is set by the
+// host): written into the buffer that step reads.
+template <typename T>
+__global__ void k_prime(StepArgs<T> a) {
+    inflow_solve<T>(a, hydrograph<T>(a, a.ctl->clk[a.phase & 1].t), const_cast<T*>(a.qin));
+}
+
+// Clock and budget as of now: report[] = {t, last_dt, steps, v_in, v_out, done, nonfinite}.
+template <typename T>
+__global__ void k_flush(StepArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    DevCtl* ctl = a.ctl;
+    const ClockSlot ck = ctl->clk[a.phase & 1];
+    double so = 0.0;
+    for (int p = lane; p < a.npart; p += 64) so += a.part_prev[p];
+    so = wave_sum(so);
+    if (lane == 0) {
+        const unsigned long long hb = ctl->hmax[a.phase % 3];
+        ctl->report[0] = ck.t;
+        ctl->report[1] = ck.dt_prev;
+        ctl->report[2] = (double)ck.steps;
+        ctl->report[3] = ck.v_in;
+        ctl->report[4] = ck.v_out + ck.dt_prev * a.dx * so;
+        ctl->report[5] = !(ctl->t_end - ck.t > 0.0) ? 1.0 : 0.0;
+        ctl->report[6] = (ck.nonfinite || Ord<T>::nonfinite(hb)) ? 1.0 : 0.0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hmax_init(const T* h, long long pitch, int nx, int ny,
+                                                   DevCtl* ctl) {
+    unsigned long long b = 0;
+    const long long ncell = (long long)nx * ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long j = idx / nx, i = idx - j * nx;
+        const unsigned long long v = Ord<T>::bits(h[(j + kHalo) * pitch + i + kHalo]);
+        b = v > b ? v : b;
+    }
+    b = wave_max_u64(b);
+    if ((threadIdx.x & 63) == 0 && b) atomicMax(&ctl->hmax[0], b);
+}
+
+// FP64 volume: fixed grid, fixed-order block partials, then one block sums
+// them in order -- deterministic.
+template <typename T>
+__global__ __launch_bounds__(256) void k_volume_part(const T* h, long long pitch, int nx, int ny,
+                                                     double* part) {
+    __shared__ double red[4];
+    double s = 0.0;
+    const long long ncell = (long long)nx * ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < ncell;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long j = idx / nx, i = idx - j * nx;
+        s += (double)h[(j + kHalo) * pitch + i + kHalo];
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ void k_volume_sum(const double* part, int nparts, double* out) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int p = lane; p < nparts; p += 64) s += part[p];
+    s = wave_sum(s);
+    if (lane == 0) *out = s;
+}
+
+// ----------------------------------------------------------------- launchers
+int strip_width(int cpt) { return 64 * cpt - 4; }
+
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s) {
+    const int items = a.nstrips * a.nchunks;
+    const int blocks = 1 + (items + 3) / 4;
+    switch (cpt) {
+    case 1: hipLaunchKernelGGL((k_step<T, 1>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<T, 2>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<T, 4>), dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prime(const StepArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_prime<T>), dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_flush(const StepArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_flush<T>), dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl* ctl,
+                            hipStream_t s) {
+    const long long ncell = (long long)nx * ny;
+    int blocks = (int)((ncell + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_hmax_init<T>), dim3(blocks), dim3(256), 0, s, h, pitch, nx, ny, ctl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* partials, int nparts,
+                         double* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_volume_part<T>), dim3(nparts), dim3(256), 0, s, h, pitch, nx, ny,
+                       partials);
+    hipLaunchKernelGGL(k_volume_sum, dim3(1), dim3(64), 0, s, partials, nparts, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step<float>(const StepArgs<float>&, int, hipStream_t);
+template hipError_t launch_step<double>(const StepArgs<double>&, int, hipStream_t);
+template hipError_t launch_prime<float>(const StepArgs<float>&, hipStream_t);
+template hipError_t launch_prime<double>(const StepArgs<double>&, hipStream_t);
+template hipError_t launch_flush<float>(const StepArgs<float>&, hipStream_t);
+template hipError_t launch_flush<double>(const StepArgs<double>&, hipStream_t);
+template hipError_t launch_hmax_init<float>(const float*, long long, int, int, DevCtl*, hipStream_t);
+template hipError_t launch_hmax_init<double>(const double*, long long, int, int, DevCtl*,
+                                             hipStream_t);
+template hipError_t launch_volume<float>(const float*, long long, int, int, double*, int, double*,
+                                         hipStream_t);
+template hipError_t launch_volume<double>(const double*, long long, int, int, double*, int,
+                                          double*, hipStream_t);
+
+}  // namespace flood

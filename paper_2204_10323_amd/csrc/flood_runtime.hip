@@ -1,0 +1,802 @@
+// Host runtime of libflood: contexts, input validation, device buffers, the
+// captured multi-step graph and the C interface declared in include/flood.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/flood.h"
+#include "flood_internal.h"
+
+using namespace flood;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t elem_size(fl_precision p) { return p == FL_F64 ? sizeof(double) : sizeof(float); }
+
+}  // namespace
+
+struct fl_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    fl_precision prec = FL_F32;
+    std::string err;
+
+    // grid and inputs (host copies, element type of the context, row stride nx)
+    int nx = 0, ny = 0;
+    double dx = 0.0;
+    bool have_grid = false, have_z = false, have_n = false, have_state = false;
+    std::vector<unsigned char> z, n, h0, qx0, qy0;
+    double t0 = 0.0;
+    int in_side = -1, in_first = 0, in_count = 0;
+    double in_slope = 0.0;
+    std::vector<double> ts, qs;
+    int out_side = -1, out_first = 0, out_count = 0;
+    double out_slope = 0.0;
+    fl_params params{};
+
+    // launch configuration
+    int cpt = 0, rows = 0;
+
+    // device state
+    bool committed = false;
+    long long pitch = 0;
+    int nstrips = 0, nchunks = 0, npart = 0;
+    void *d_h[2] = {nullptr, nullptr}, *d_qx[2] = {nullptr, nullptr}, *d_qy[2] = {nullptr, nullptr};
+    void *d_z = nullptr, *d_n = nullptr, *d_edge_w = nullptr, *d_edge_s = nullptr;
+    void *d_kout = nullptr, *d_qin[2] = {nullptr, nullptr};
+    double *d_in_z = nullptr, *d_in_k = nullptr, *d_ts = nullptr, *d_qs = nullptr;
+    double *d_part[2] = {nullptr, nullptr}, *d_vol_part = nullptr, *d_vol = nullptr;
+    DevCtl* d_ctl = nullptr;
+    std::vector<void*> allocs;
+    size_t dev_bytes = 0;
+    long long nstep = 0;  // steps enqueued since commit
+    double v0 = 0.0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_k = 0;
+};
+
+namespace {
+
+fl_status fail(fl_ctx* c, fl_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+fl_status hip_fail(fl_ctx* c, hipError_t e, const char* what) {
+    return fail(c, FL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, call)                                                  \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call);            \
+    } while (0)
+
+size_t esz(const fl_ctx* c) { return elem_size(c->prec); }
+
+double get_elem(const fl_ctx* c, const unsigned char* base, size_t idx) {
+    if (c->prec == FL_F64) {
+        double v;
+        std::memcpy(&v, base + idx * sizeof(double), sizeof(double));
+        return v;
+    }
+    float v;
+    std::memcpy(&v, base + idx * sizeof(float), sizeof(float));
+    return v;
+}
+
+// Copy ny rows of `cols` elements with stride `stride` from host or device
+// memory into a dense host vector.
+fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int cols, int on_device,
+                     std::vector<unsigned char>& out) {
+    const size_t es = esz(c);
+    out.resize((size_t)rows_ * cols * es);
+    if (on_device) {
+        HIP_TRY(c, hipSetDevice(c->device));
+        HIP_TRY(c, hipMemcpy2D(out.data(), cols * es, src, (size_t)stride * es, cols * es, rows_,
+                               hipMemcpyDeviceToHost));
+    } else {
+        for (int j = 0; j < rows_; ++j)
+            std::memcpy(out.data() + (size_t)j * cols * es,
+                        static_cast<const unsigned char*>(src) + (size_t)j * stride * es, cols * es);
+    }
+    return FL_OK;
+}
+
+void invalidate(fl_ctx* c) { c->committed = false; }
+
+void free_device(fl_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_k = 0;
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    c->dev_bytes = 0;
+    c->d_h[0] = c->d_h[1] = c->d_qx[0] = c->d_qx[1] = c->d_qy[0] = c->d_qy[1] = nullptr;
+    c->d_z = c->d_n = c->d_edge_w = c->d_edge_s = c->d_kout = nullptr;
+    c->d_qin[0] = c->d_qin[1] = nullptr;
+    c->d_in_z = c->d_in_k = c->d_ts = c->d_qs = nullptr;
+    c->d_part[0] = c->d_part[1] = c->d_vol_part = c->d_vol = nullptr;
+    c->d_ctl = nullptr;
+    c->committed = false;
+}
+
+fl_status dalloc(fl_ctx* c, void** p, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? FL_ENOMEM : FL_EHIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    c->allocs.push_back(*p);
+    c->dev_bytes += bytes;
+    return hipMemsetAsync(*p, 0, bytes, c->stream) == hipSuccess
+               ? FL_OK
+               : fail(c, FL_EHIP, "hipMemsetAsync failed");
+}
+
+int side_len(const fl_ctx* c, int side) { return (side == FL_WEST || side == FL_EAST) ? c->ny : c->nx; }
+
+void side_cell(const fl_ctx* c, int side, int k, int* i, int* j) {
+    switch (side) {
+    case FL_WEST: *i = 0; *j = k; break;
+    case FL_EAST: *i = c->nx - 1; *j = k; break;
+    case FL_SOUTH: *i = k; *j = 0; break;
+    default: *i = k; *j = c->ny - 1; break;
+    }
+}
+
+template <typename T>
+StepArgs<T> make_args(const fl_ctx* c, long long n) {
+    StepArgs<T> a{};
+    const int p = (int)(n & 1), q = p ^ 1;
+    a.h_in = (const T*)c->d_h[p];
+    a.qx_in = (const T*)c->d_qx[p];
+    a.qy_in = (const T*)c->d_qy[p];
+    a.h_out = (T*)c->d_h[q];
+    a.qx_out = (T*)c->d_qx[q];
+    a.qy_out = (T*)c->d_qy[q];
+    a.z = (const T*)c->d_z;
+    a.n = (const T*)c->d_n;
+    a.edge_w = (T*)c->d_edge_w;
+    a.edge_s = (T*)c->d_edge_s;
+    a.kout = (const T*)c->d_kout;
+    a.qin = (const T*)c->d_qin[p];
+    a.qin_next = (T*)c->d_qin[q];
+    a.in_z = c->d_in_z;
+    a.in_k = c->d_in_k;
+    a.ts = c->d_ts;
+    a.qs = c->d_qs;
+    a.part_cur = c->d_part[p];
+    a.part_prev = c->d_part[q];
+    a.ctl = c->d_ctl;
+    a.pitch = c->pitch;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.in_side = c->in_count > 0 ? c->in_side : -1;
+    a.in_first = c->in_first;
+    a.in_count = c->in_count;
+    a.nsamp = (int)c->ts.size();
+    a.out_side = c->out_count > 0 ? c->out_side : -1;
+    a.out_first = c->out_first;
+    a.out_count = c->out_count;
+    a.npart = c->npart;
+    a.positivity = c->params.positivity;
+    a.nstrips = c->nstrips;
+    a.nchunks = c->nchunks;
+    a.rows = c->rows;
+    a.phase = (int)(n % 6);
+    a.dx = c->dx;
+    a.g = c->params.g;
+    a.alpha = c->params.alpha;
+    a.dt_max = c->params.dt_max;
+    a.h_eps = c->params.h_eps;
+    a.dt_fixed = c->params.dt_fixed;
+    return a;
+}
+
+hipError_t enqueue_one(fl_ctx* c, long long n, hipStream_t s) {
+    if (c->prec == FL_F64) return launch_step<double>(make_args<double>(c, n), c->cpt, s);
+    return launch_step<float>(make_args<float>(c, n), c->cpt, s);
+}
+
+fl_status capture_graph(fl_ctx* c) {
+    int K = c->params.steps_per_graph > 0 ? c->params.steps_per_graph : 60;
+    K = ((K + 5) / 6) * 6;
+    hipStream_t cs;
+    HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_one(c, k, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+            c->graph = g;
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+    c->graph_k = K;
+    return FL_OK;
+}
+
+fl_status upload_field(fl_ctx* c, void* dst, const std::vector<unsigned char>& src, int rows_,
+                       int cols, long long dst_row0, long long dst_col0) {
+    const size_t es = esz(c);
+    unsigned char* d = static_cast<unsigned char*>(dst) + ((dst_row0)*c->pitch + dst_col0) * es;
+    HIP_TRY(c, hipMemcpy2DAsync(d, c->pitch * es, src.data(), cols * es, cols * es, rows_,
+                                hipMemcpyHostToDevice, c->stream));
+    return FL_OK;
+}
+
+template <typename T>
+void fill_host(std::vector<unsigned char>& v, size_t count, const std::vector<double>& vals) {
+    v.resize(count * sizeof(T));
+    T* p = reinterpret_cast<T*>(v.data());
+    for (size_t k = 0; k < count; ++k) p[k] = (T)vals[k];
+}
+
+fl_status do_commit(fl_ctx* c) {
+    if (!c->have_grid || !c->have_z || !c->have_n)
+        return fail(c, FL_ESTATE, "fl_commit needs fl_init_grid, fl_set_dem and fl_set_manning");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_device(c);
+    const size_t es = esz(c);
+    const int nx = c->nx, ny = c->ny;
+    if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
+    if (c->rows == 0) c->rows = 256;
+    const long long align = 256 / (long long)es;
+    c->pitch = ((nx + 8 + align - 1) / align) * align;
+    c->nstrips = (nx + strip_width(c->cpt) - 1) / strip_width(c->cpt);
+    c->nchunks = (ny + c->rows - 1) / c->rows;
+    if (c->out_count > 0)
+        c->npart = (c->out_side == FL_WEST || c->out_side == FL_EAST) ? c->nchunks : c->nstrips;
+    else
+        c->npart = 0;
+    const size_t field = (size_t)c->pitch * (ny + 2 * kHalo) * es;
+    fl_status st;
+    for (int p = 0; p < 2; ++p) {
+        if ((st = dalloc(c, &c->d_h[p], field))) return st;
+        if ((st = dalloc(c, &c->d_qx[p], field))) return st;
+        if ((st = dalloc(c, &c->d_qy[p], field))) return st;
+        if ((st = dalloc(c, &c->d_qin[p], (size_t)std::max(nx, ny) * es))) return st;
+        if ((st = dalloc(c, (void**)&c->d_part[p], sizeof(double) * std::max(1, c->npart))))
+            return st;
+    }
+    if ((st = dalloc(c, &c->d_z, field))) return st;
+    if ((st = dalloc(c, &c->d_n, field))) return st;
+    if ((st = dalloc(c, &c->d_edge_w, (size_t)ny * es))) return st;
+    if ((st = dalloc(c, &c->d_edge_s, (size_t)nx * es))) return st;
+    if ((st = dalloc(c, &c->d_kout, (size_t)std::max(nx, ny) * es))) return st;
+    if ((st = dalloc(c, (void**)&c->d_in_z, sizeof(double) * std::max(1, c->in_count)))) return st;
+    if ((st = dalloc(c, (void**)&c->d_in_k, sizeof(double) * std::max(1, c->in_count)))) return st;
+    if ((st = dalloc(c, (void**)&c->d_ts, sizeof(double) * std::max<size_t>(1, c->ts.size()))))
+        return st;
+    if ((st = dalloc(c, (void**)&c->d_qs, sizeof(double) * std::max<size_t>(1, c->qs.size()))))
+        return st;
+    if ((st = dalloc(c, (void**)&c->d_vol_part, sizeof(double) * kVolumeParts))) return st;
+    if ((st = dalloc(c, (void**)&c->d_vol, sizeof(double)))) return st;
+    if ((st = dalloc(c, (void**)&c->d_ctl, sizeof(DevCtl)))) return st;
+
+    // cell fields
+    if ((st = upload_field(c, c->d_z, c->z, ny, nx, kHalo, kHalo))) return st;
+    if ((st = upload_field(c, c->d_n, c->n, ny, nx, kHalo, kHalo))) return st;
+    if (c->have_state) {
+        if ((st = upload_field(c, c->d_h[0], c->h0, ny, nx, kHalo, kHalo))) return st;
+        // qx (ny x (nx+1)): column 0 is the west border, columns 1..nx the east faces.
+        std::vector<unsigned char> east((size_t)ny * nx * es), west((size_t)ny * es);
+        for (int j = 0; j < ny; ++j) {
+            std::memcpy(east.data() + (size_t)j * nx * es, c->qx0.data() + ((size_t)j * (nx + 1) + 1) * es,
+                        nx * es);
+            std::memcpy(west.data() + (size_t)j * es, c->qx0.data() + (size_t)j * (nx + 1) * es, es);
+        }
+        if ((st = upload_field(c, c->d_qx[0], east, ny, nx, kHalo, kHalo))) return st;
+        HIP_TRY(c, hipMemcpyAsync(c->d_edge_w, west.data(), west.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+        // qy ((ny+1) x nx): row 0 is the south border, rows 1..ny the north faces.
+        std::vector<unsigned char> north(c->qy0.begin() + (size_t)nx * es, c->qy0.end());
+        if ((st = upload_field(c, c->d_qy[0], north, ny, nx, kHalo, kHalo))) return st;
+        HIP_TRY(c, hipMemcpyAsync(c->d_edge_s, c->qy0.data(), (size_t)nx * es, hipMemcpyHostToDevice,
+                                  c->stream));
+    }
+    // boundary data
+    if (c->out_count > 0) {
+        std::vector<double> k(side_len(c, c->out_side), 0.0);
+        for (int p = 0; p < c->out_count; ++p) {
+            int i, j;
+            side_cell(c, c->out_side, c->out_first + p, &i, &j);
+            k[c->out_first + p] = std::sqrt(c->out_slope) / get_elem(c, c->n.data(), (size_t)j * nx + i);
+        }
+        std::vector<unsigned char> kb;
+        if (c->prec == FL_F64) fill_host<double>(kb, k.size(), k); else fill_host<float>(kb, k.size(), k);
+        HIP_TRY(c, hipMemcpyAsync(c->d_kout, kb.data(), kb.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    std::vector<double> iz(std::max(1, c->in_count), 0.0), ik(std::max(1, c->in_count), 0.0);
+    for (int p = 0; p < c->in_count; ++p) {
+        int i, j;
+        side_cell(c, c->in_side, c->in_first + p, &i, &j);
+        iz[p] = get_elem(c, c->z.data(), (size_t)j * nx + i);
+        ik[p] = std::sqrt(c->in_slope) / get_elem(c, c->n.data(), (size_t)j * nx + i);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->d_in_z, iz.data(), iz.size() * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->d_in_k, ik.data(), ik.size() * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    if (!c->ts.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(c->d_ts, c->ts.data(), c->ts.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_qs, c->qs.data(), c->qs.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    // clock
+    DevCtl ctl{};
+    ctl.clk[0].t = c->t0;
+    ctl.t_end = c->params.t_end;
+    HIP_TRY(c, hipMemcpyAsync(c->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, c->stream));
+    c->nstep = 0;
+    if (c->prec == FL_F64) {
+        HIP_TRY(c, launch_hmax_init<double>((const double*)c->d_h[0], c->pitch, nx, ny, c->d_ctl, c->stream));
+        HIP_TRY(c, launch_prime<double>(make_args<double>(c, 0), c->stream));
+        HIP_TRY(c, launch_volume<double>((const double*)c->d_h[0], c->pitch, nx, ny, c->d_vol_part,
+                                         kVolumeParts, c->d_vol, c->stream));
+    } else {
+        HIP_TRY(c, launch_hmax_init<float>((const float*)c->d_h[0], c->pitch, nx, ny, c->d_ctl, c->stream));
+        HIP_TRY(c, launch_prime<float>(make_args<float>(c, 0), c->stream));
+        HIP_TRY(c, launch_volume<float>((const float*)c->d_h[0], c->pitch, nx, ny, c->d_vol_part,
+                                        kVolumeParts, c->d_vol, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(&c->v0, c->d_vol, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->v0 *= c->dx * c->dx;
+    if ((st = capture_graph(c))) return st;
+    c->committed = true;
+    return FL_OK;
+}
+
+fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
+    while (nsteps > 0) {
+        if (c->graph_exec && c->nstep % 6 == 0 && nsteps >= c->graph_k) {
+            HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+            c->nstep += c->graph_k;
+            nsteps -= c->graph_k;
+        } else {
+            HIP_TRY(c, enqueue_one(c, c->nstep, c->stream));
+            c->nstep += 1;
+            nsteps -= 1;
+        }
+    }
+    return FL_OK;
+}
+
+struct HostReport {
+    double r[8];
+};
+
+fl_status read_report(fl_ctx* c, fl_report* out, bool with_volume) {
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->prec == FL_F64) {
+        HIP_TRY(c, launch_flush<double>(make_args<double>(c, c->nstep), c->stream));
+        if (with_volume)
+            HIP_TRY(c, launch_volume<double>((const double*)c->d_h[c->nstep & 1], c->pitch, c->nx, c->ny,
+                                             c->d_vol_part, kVolumeParts, c->d_vol, c->stream));
+    } else {
+        HIP_TRY(c, launch_flush<float>(make_args<float>(c, c->nstep), c->stream));
+        if (with_volume)
+            HIP_TRY(c, launch_volume<float>((const float*)c->d_h[c->nstep & 1], c->pitch, c->nx, c->ny,
+                                            c->d_vol_part, kVolumeParts, c->d_vol, c->stream));
+    }
+    HostReport hr{};
+    double vol = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(hr.r, c->d_ctl->report, sizeof(hr.r), hipMemcpyDeviceToHost, c->stream));
+    if (with_volume)
+        HIP_TRY(c, hipMemcpyAsync(&vol, c->d_vol, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->t = hr.r[0];
+    out->last_dt = hr.r[1];
+    out->steps = (int64_t)hr.r[2];
+    out->v0 = c->v0;
+    out->v_in = hr.r[3];
+    out->v_out = hr.r[4];
+    out->v_now = vol * c->dx * c->dx;
+    out->done = hr.r[5] != 0.0;
+    out->nonfinite = hr.r[6] != 0.0;
+    return out->nonfinite ? fail(c, FL_ENONFINITE, "a depth became non-finite; the clock stopped")
+                          : FL_OK;
+}
+
+bool check_side(int side) { return side >= FL_WEST && side <= FL_NORTH; }
+
+}  // namespace
+
+extern "C" {
+
+void fl_default_params(fl_params* p) {
+    if (!p) return;
+    p->g = 9.81;
+    p->alpha = 0.7;
+    p->dt_max = 0.1;
+    p->h_eps = 1e-4;
+    p->dt_fixed = 0.0;
+    p->t_end = std::numeric_limits<double>::infinity();
+    p->steps_per_graph = 60;
+    p->positivity = 1;
+}
+
+fl_status fl_create(fl_ctx** out, int device, void* hip_stream, fl_precision prec) {
+    if (!out) {
+        g_create_error = "fl_create: NULL output pointer";
+        return FL_EINVAL;
+    }
+    *out = nullptr;
+    if (prec != FL_F32 && prec != FL_F64) {
+        g_create_error = "fl_create: precision must be FL_F32 or FL_F64";
+        return FL_EINVAL;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+        return FL_EHIP;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_error = "fl_create: no such device";
+        return FL_EINVAL;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return FL_EHIP;
+    }
+    fl_ctx* c = new (std::nothrow) fl_ctx();
+    if (!c) {
+        g_create_error = "fl_create: out of host memory";
+        return FL_ENOMEM;
+    }
+    c->device = device;
+    c->prec = prec;
+    fl_default_params(&c->params);
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            delete c;
+            return FL_EHIP;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return FL_OK;
+}
+
+fl_status fl_init_grid(fl_ctx* c, int32_t nx, int32_t ny, double dx) {
+    if (!c) return FL_EINVAL;
+    if (nx < 1 || ny < 1) return fail(c, FL_EINVAL, "fl_init_grid: nx and ny must be >= 1");
+    if (!(dx > 0.0) || !std::isfinite(dx)) return fail(c, FL_EINVAL, "fl_init_grid: dx must be finite and > 0");
+    if ((long long)nx + 8 > (1LL << 30) || (long long)ny + 8 > (1LL << 30))
+        return fail(c, FL_EINVAL, "fl_init_grid: grid too large");
+    invalidate(c);
+    c->nx = nx;
+    c->ny = ny;
+    c->dx = dx;
+    c->have_grid = true;
+    c->have_z = c->have_n = c->have_state = false;
+    c->in_count = c->out_count = 0;
+    c->in_side = c->out_side = -1;
+    c->ts.clear();
+    c->qs.clear();
+    c->t0 = 0.0;
+    return FL_OK;
+}
+
+fl_status fl_set_dem(fl_ctx* c, const void* z, int64_t row_stride, int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_set_dem before fl_init_grid");
+    if (!z || row_stride < c->nx) return fail(c, FL_EINVAL, "fl_set_dem: NULL or row_stride < nx");
+    std::vector<unsigned char> tmp;
+    fl_status st = fetch_rows(c, z, row_stride, c->ny, c->nx, on_device, tmp);
+    if (st) return st;
+    const size_t cnt = (size_t)c->nx * c->ny;
+    for (size_t k = 0; k < cnt; ++k)
+        if (!std::isfinite(get_elem(c, tmp.data(), k)))
+            return fail(c, FL_EINVAL, "fl_set_dem: non-finite elevation");
+    c->z.swap(tmp);
+    c->have_z = true;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_manning(fl_ctx* c, const void* n, int64_t row_stride, int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_set_manning before fl_init_grid");
+    if (!n || row_stride < c->nx) return fail(c, FL_EINVAL, "fl_set_manning: NULL or row_stride < nx");
+    std::vector<unsigned char> tmp;
+    fl_status st = fetch_rows(c, n, row_stride, c->ny, c->nx, on_device, tmp);
+    if (st) return st;
+    const size_t cnt = (size_t)c->nx * c->ny;
+    for (size_t k = 0; k < cnt; ++k) {
+        double v = get_elem(c, tmp.data(), k);
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(c, FL_EINVAL, "fl_set_manning: Manning n must be finite and > 0");
+    }
+    c->n.swap(tmp);
+    c->have_n = true;
+    invalidate(c);
+    return FL_OK;
+}
+
+static bool overlaps(int s1, int f1, int c1, int s2, int f2, int c2) {
+    if (c1 <= 0 || c2 <= 0 || s1 != s2) return false;
+    return f1 < f2 + c2 && f2 < f1 + c1;
+}
+
+fl_status fl_set_inflow(fl_ctx* c, fl_side side, int32_t first, int32_t count, double slope,
+                        const double* t_s, const double* q_m3s, int32_t nsamples) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_set_inflow before fl_init_grid");
+    if (count == 0) {
+        c->in_count = 0;
+        c->in_side = -1;
+        c->ts.clear();
+        c->qs.clear();
+        invalidate(c);
+        return FL_OK;
+    }
+    if (!check_side(side)) return fail(c, FL_EINVAL, "fl_set_inflow: bad side");
+    if (count < 0 || first < 0 || first + (long long)count > side_len(c, side))
+        return fail(c, FL_EINVAL, "fl_set_inflow: section outside the side");
+    if (!(slope > 0.0) || !std::isfinite(slope)) return fail(c, FL_EINVAL, "fl_set_inflow: slope must be > 0");
+    if (!t_s || !q_m3s || nsamples < 1 || nsamples > 4096)
+        return fail(c, FL_EINVAL, "fl_set_inflow: need 1..4096 hydrograph samples");
+    for (int k = 0; k < nsamples; ++k) {
+        if (!std::isfinite(t_s[k]) || !std::isfinite(q_m3s[k]) || q_m3s[k] < 0.0)
+            return fail(c, FL_EINVAL, "fl_set_inflow: samples must be finite with Q >= 0");
+        if (k > 0 && !(t_s[k] > t_s[k - 1]))
+            return fail(c, FL_EINVAL, "fl_set_inflow: sample times must increase strictly");
+    }
+    if (overlaps(side, first, count, c->out_side, c->out_first, c->out_count))
+        return fail(c, FL_EINVAL, "fl_set_inflow: overlaps the outflow section");
+    c->in_side = side;
+    c->in_first = first;
+    c->in_count = count;
+    c->in_slope = slope;
+    c->ts.assign(t_s, t_s + nsamples);
+    c->qs.assign(q_m3s, q_m3s + nsamples);
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_outflow(fl_ctx* c, fl_side side, int32_t first, int32_t count, double slope) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_set_outflow before fl_init_grid");
+    if (count == 0) {
+        c->out_count = 0;
+        c->out_side = -1;
+        invalidate(c);
+        return FL_OK;
+    }
+    if (!check_side(side)) return fail(c, FL_EINVAL, "fl_set_outflow: bad side");
+    if (count < 0 || first < 0 || first + (long long)count > side_len(c, side))
+        return fail(c, FL_EINVAL, "fl_set_outflow: section outside the side");
+    if (!(slope > 0.0) || !std::isfinite(slope)) return fail(c, FL_EINVAL, "fl_set_outflow: slope must be > 0");
+    if (overlaps(side, first, count, c->in_side, c->in_first, c->in_count))
+        return fail(c, FL_EINVAL, "fl_set_outflow: overlaps the inflow section");
+    c->out_side = side;
+    c->out_first = first;
+    c->out_count = count;
+    c->out_slope = slope;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_params(fl_ctx* c, const fl_params* p) {
+    if (!c) return FL_EINVAL;
+    if (!p) return fail(c, FL_EINVAL, "fl_set_params: NULL");
+    if (!(p->g > 0.0) || !std::isfinite(p->g)) return fail(c, FL_EINVAL, "fl_set_params: g must be > 0");
+    if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return fail(c, FL_EINVAL, "fl_set_params: alpha must be in (0, 1]");
+    if (!(p->dt_max > 0.0) || !std::isfinite(p->dt_max)) return fail(c, FL_EINVAL, "fl_set_params: dt_max must be > 0");
+    if (!(p->h_eps >= 0.0) || !std::isfinite(p->h_eps)) return fail(c, FL_EINVAL, "fl_set_params: h_eps must be >= 0");
+    if (!(p->dt_fixed >= 0.0) || !std::isfinite(p->dt_fixed)) return fail(c, FL_EINVAL, "fl_set_params: dt_fixed must be >= 0");
+    if (std::isnan(p->t_end)) return fail(c, FL_EINVAL, "fl_set_params: t_end is NaN");
+    if (p->steps_per_graph < 0) return fail(c, FL_EINVAL, "fl_set_params: steps_per_graph < 0");
+    if (p->positivity != 0 && p->positivity != 1) return fail(c, FL_EINVAL, "fl_set_params: positivity must be 0 or 1");
+    c->params = *p;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_state(fl_ctx* c, const void* h, const void* qx, const void* qy, double t,
+                       int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_set_state before fl_init_grid");
+    if (!h) return fail(c, FL_EINVAL, "fl_set_state: NULL depth");
+    if (!std::isfinite(t)) return fail(c, FL_EINVAL, "fl_set_state: t must be finite");
+    const int nx = c->nx, ny = c->ny;
+    const size_t es = esz(c);
+    std::vector<unsigned char> hh, qxx, qyy;
+    fl_status st = fetch_rows(c, h, nx, ny, nx, on_device, hh);
+    if (st) return st;
+    for (size_t k = 0; k < (size_t)nx * ny; ++k) {
+        double v = get_elem(c, hh.data(), k);
+        if (!(v >= 0.0) || !std::isfinite(v)) return fail(c, FL_EINVAL, "fl_set_state: depth must be finite and >= 0");
+    }
+    if (qx) {
+        if ((st = fetch_rows(c, qx, nx + 1, ny, nx + 1, on_device, qxx))) return st;
+    } else {
+        qxx.assign((size_t)ny * (nx + 1) * es, 0);
+    }
+    if (qy) {
+        if ((st = fetch_rows(c, qy, nx, ny + 1, nx, on_device, qyy))) return st;
+    } else {
+        qyy.assign((size_t)(ny + 1) * nx * es, 0);
+    }
+    for (size_t k = 0; k < qxx.size() / es; ++k)
+        if (!std::isfinite(get_elem(c, qxx.data(), k))) return fail(c, FL_EINVAL, "fl_set_state: non-finite qx");
+    for (size_t k = 0; k < qyy.size() / es; ++k)
+        if (!std::isfinite(get_elem(c, qyy.data(), k))) return fail(c, FL_EINVAL, "fl_set_state: non-finite qy");
+    c->h0.swap(hh);
+    c->qx0.swap(qxx);
+    c->qy0.swap(qyy);
+    c->t0 = t;
+    c->have_state = true;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_tiling(fl_ctx* c, int32_t cells_per_lane, int32_t rows_per_item) {
+    if (!c) return FL_EINVAL;
+    if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
+        return fail(c, FL_EINVAL, "fl_set_tiling: cells_per_lane must be 1, 2 or 4");
+    if (c->prec == FL_F64 && cells_per_lane == 4)
+        return fail(c, FL_EINVAL, "fl_set_tiling: FP64 supports 1 or 2 cells per lane");
+    if (rows_per_item < 0) return fail(c, FL_EINVAL, "fl_set_tiling: rows_per_item < 0");
+    if (cells_per_lane) c->cpt = cells_per_lane;
+    if (rows_per_item) c->rows = rows_per_item;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_commit(fl_ctx* c) {
+    if (!c) return FL_EINVAL;
+    fl_status st = do_commit(c);
+    if (st) free_device(c);
+    return st;
+}
+
+fl_status fl_step(fl_ctx* c, int64_t nsteps) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_step before fl_commit");
+    if (nsteps < 0) return fail(c, FL_EINVAL, "fl_step: nsteps < 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return enqueue_steps(c, nsteps);
+}
+
+fl_status fl_time_steps(fl_ctx* c, int64_t nsteps, double* elapsed_ms) {
+    if (!c || !elapsed_ms) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_time_steps before fl_commit");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    fl_status st = enqueue_steps(c, nsteps);
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *elapsed_ms = ms;
+    return st;
+}
+
+fl_status fl_advance(fl_ctx* c, double seconds) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_advance before fl_commit");
+    if (!(seconds >= 0.0) || !std::isfinite(seconds)) return fail(c, FL_EINVAL, "fl_advance: seconds must be finite and >= 0");
+    fl_report r{};
+    fl_status st = read_report(c, &r, false);
+    if (st) return st;
+    const double target = std::min(c->params.t_end, r.t + seconds);
+    HIP_TRY(c, hipMemcpyAsync(&c->d_ctl->t_end, &target, sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+    double t = r.t;
+    double dt_guess = r.last_dt > 0.0 ? r.last_dt : c->params.dt_max;
+    if (c->params.dt_fixed > 0.0) dt_guess = c->params.dt_fixed;
+    while (t < target) {
+        long long want = (long long)std::ceil((target - t) / std::max(dt_guess, 1e-9));
+        want = std::max<long long>(6, std::min<long long>(want + 6, 20000));
+        if ((st = enqueue_steps(c, want))) break;
+        if ((st = read_report(c, &r, false))) break;
+        if (r.steps == 0 && r.t <= t) break;
+        t = r.t;
+        if (r.done) break;
+        dt_guess = r.last_dt > 0.0 ? r.last_dt : dt_guess;
+    }
+    const double tend = c->params.t_end;
+    hipError_t e = hipMemcpyAsync(&c->d_ctl->t_end, &tend, sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(c, e, "restore t_end");
+    return FL_OK;
+}
+
+fl_status fl_get_depth(fl_ctx* c, void* dst, int64_t row_stride, int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_get_depth before fl_commit");
+    if (!dst || row_stride < c->nx) return fail(c, FL_EINVAL, "fl_get_depth: NULL or row_stride < nx");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t es = esz(c);
+    const unsigned char* src = static_cast<const unsigned char*>(c->d_h[c->nstep & 1]) +
+                               ((size_t)kHalo * c->pitch + kHalo) * es;
+    HIP_TRY(c, hipMemcpy2DAsync(dst, row_stride * es, src, c->pitch * es, c->nx * es, c->ny,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FL_OK;
+}
+
+fl_status fl_get_discharge(fl_ctx* c, void* qx, void* qy, int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_get_discharge before fl_commit");
+    if (!qx || !qy) return fail(c, FL_EINVAL, "fl_get_discharge: NULL output");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t es = esz(c);
+    const int nx = c->nx, ny = c->ny;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int p = c->nstep & 1;
+    const size_t off = ((size_t)kHalo * c->pitch + kHalo) * es;
+    unsigned char* dqx = static_cast<unsigned char*>(qx);
+    unsigned char* dqy = static_cast<unsigned char*>(qy);
+    HIP_TRY(c, hipMemcpy2DAsync(dqx + es, (nx + 1) * es, static_cast<unsigned char*>(c->d_qx[p]) + off,
+                                c->pitch * es, nx * es, ny, kind, c->stream));
+    HIP_TRY(c, hipMemcpy2DAsync(dqx, (nx + 1) * es, c->d_edge_w, es, es, ny, kind, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dqy, c->d_edge_s, nx * es, kind, c->stream));
+    HIP_TRY(c, hipMemcpy2DAsync(dqy + nx * es, nx * es, static_cast<unsigned char*>(c->d_qy[p]) + off,
+                                c->pitch * es, nx * es, ny, kind, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FL_OK;
+}
+
+fl_status fl_get_report(fl_ctx* c, fl_report* r) {
+    if (!c || !r) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_get_report before fl_commit");
+    return read_report(c, r, true);
+}
+
+size_t fl_device_bytes(const fl_ctx* c) { return c ? c->dev_bytes : 0; }
+
+const char* fl_last_error(const fl_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+void fl_destroy(fl_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_device(c);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"
