@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the flood step on one MI355X.
+
+Default workload: the 16384 x 16384 synthetic valley at dx = 1 m (268 M cells),
+dry start, CFL time step, FP32 state -- one "step" is one full time step of
+the method (device clock, boundary conditions, eq. 3 face update, donor
+scaling, eq. 4 depth update, deepest-cell reduction), captured in HIP graphs.
+Prints one JSON line: Gcell-updates/s, the HBM roofline of the step kernel,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
+BYTES_PER_CELL = {"f32": 32, "f64": 64}   # read h z n qx qy, write h qx qy
+KERNEL_SRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc", "flood_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(cells: int):
+    """HBM bytes per step-kernel launch from the committed PMC summary, if it was
+    taken on the current kernel source; else None."""
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", txt, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_sha256_16") != kernel_hash() or d.get("cells") != cells:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def build_workload(name: str):
+    import synth
+    if name == "valley16384":
+        return synth.config_d3(16384, wet=False), "valley_16384x16384_dx1m_dry_start"
+    if name == "valley16384_wet":
+        return synth.config_d3(16384, wet=True), "valley_16384x16384_dx1m_prewetted"
+    if name == "valley2048":
+        return synth.config_d2(), "valley_2048x2048_dx5m_dry_start"
+    if name == "valley256":
+        return synth.config_d1(), "valley_256x256_dx10m_dry_start"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(sc, budget_s: float = 20.0):
+    """The FP64 oracle on the same workload, from the same initial state, for as
+    many whole steps as fit in about `budget_s` seconds (at least one)."""
+    import numpy as np
+    import oracle
+    o = oracle.Run(sc, nthreads=0)
+    cores = oracle.threads_used(0)
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    nmore = max(0, min(int(budget_s / max(one, 1e-6)) - 1, 50))
+    if nmore:
+        o.step(nmore)
+    el = time.perf_counter() - t0
+    steps = 1 + nmore
+    val = sc.nx * sc.ny * steps / el / 1e9
+    del o
+    return {"value": round(val, 5), "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, first {steps} step(s) of the same {sc.nx}x{sc.ny} workload "
+                      f"from the same initial state, {el:.1f} s wall on {cores} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="valley16384")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--cells-per-lane", type=int, default=0)
+    ap.add_argument("--rows-per-item", type=int, default=0)
+    ap.add_argument("--steps-per-graph", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--extra-wet", action="store_true",
+                    help="also time the pre-wetted start of the same grid")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="also run the plain streaming copy of this many GiB (roofline "
+                         "calibration: practical ceiling and PMC scale)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2204_10323_amd as fl
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    sc, wname = build_workload(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    cells = sc.nx * sc.ny
+
+    def run_timed(scn):
+        f = fl.from_scenario(scn, args.precision, device=0,
+                             stream=torch.cuda.current_stream().cuda_stream,
+                             cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item,
+                             steps_per_graph=args.steps_per_graph)
+        f.step(args.warmup)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev_ms = f.time_steps(args.steps)     # HIP events on the stream the kernel runs on
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        rep = f.get_report()
+        dev_bytes = f.device_bytes()
+        f.close()
+        return ev_ms, wall, rep, dev_bytes
+
+    ev_ms, wall, rep, dev_bytes = run_timed(sc)
+    ms_step = ev_ms / args.steps
+    value = cells * args.steps / (ev_ms / 1e3) / 1e9
+    bpc = BYTES_PER_CELL[args.precision]
+    achieved = bpc * cells / (ms_step / 1e3) / 1e9
+    traffic = measured_traffic(cells) if args.precision == "f32" else None
+    out = {
+        "metric": "Gcell-updates/s + % of HBM BW; batched & adjoint vs plain step, same GPU",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": wname, "grid": f"{sc.nx}x{sc.ny}", "dx_m": sc.dx,
+                   "cells": cells, "dt": "CFL alpha 0.7, device-side", "dt_max_s": sc.dt_max,
+                   "inflow_cells": sc.inflow[2], "outflow": "east edge",
+                   "steps_in_run": args.warmup + args.steps, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+    extras = {"wall_s_timed_region": round(wall, 4), "input_generation_s": round(t_gen, 1),
+              "device_bytes": dev_bytes, "budget_error": rep.budget_error(),
+              "sim_time_s": rep.t, "kernel_sha256_16": kernel_hash()}
+    if args.extra_wet and args.workload == "valley16384":
+        import synth
+        del sc
+        scw = synth.config_d3(16384, wet=True)
+        ev2, _, rep2, _ = run_timed(scw)
+        extras["prewetted_gcell_s"] = round(cells * args.steps / (ev2 / 1e3) / 1e9, 3)
+        extras["prewetted_hbm_frac"] = round(bpc * cells / (ev2 / args.steps / 1e3) / 1e9 /
+                                             HBM_PEAK_GBS, 4)
+        sc = scw
+    if args.copy_probe_gib > 0:
+        nbytes = int(args.copy_probe_gib * (1 << 30))
+        extras["copy_probe_bytes"] = nbytes
+        extras["copy_probe_gbs"] = {v: round(fl.copy_probe(nbytes, 10, v), 1) for v in (1, 3)}
+    if not args.no_cpu_baseline:
+        if args.extra_wet and args.workload == "valley16384":
+            sc, _ = build_workload(args.workload)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
+    out["extras"] = extras
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

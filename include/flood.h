@@ -208,6 +208,15 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
 /* Bytes of device memory the context holds after commit. */
 size_t fl_device_bytes(const fl_ctx *ctx);
 
+/* Roofline calibration: a plain streaming copy of `bytes` bytes (16-byte
+ * vectors, grid-stride) repeated `reps` times on device `device`; returns the
+ * achieved bandwidth in GB/s (bytes read + bytes written per second).
+ * variant: 0 copy, 1 copy unrolled x4, 2 non-temporal copy, 3 non-temporal
+ * copy unrolled x4, 4 read-only stream, 5 write-only stream, 6 copy unrolled
+ * x4 with 4x more workgroups.  Allocates and frees its own two buffers.
+ * EINVAL: bytes < 4096, reps < 1 or bad variant. */
+fl_status fl_copy_probe(int device, size_t bytes, int reps, int variant, double *gbps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libflood.so")
+LIB_PATH = os.environ.get("FLOOD_LIB") or os.path.join(_HERE, "libflood.so")
 
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ESTATE, FL_ENONFINITE = range(6)
 FL_F32, FL_F64 = 0, 1
@@ -27,7 +27,7 @@ EXPORTS = [
     "fl_default_params", "fl_create", "fl_init_grid", "fl_set_dem", "fl_set_manning",
     "fl_set_inflow", "fl_set_outflow", "fl_set_params", "fl_set_state", "fl_commit", "fl_step",
     "fl_advance", "fl_get_depth", "fl_get_discharge", "fl_get_report", "fl_last_error",
-    "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes",
+    "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
 ]
 
 
@@ -65,6 +65,14 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise FileNotFoundError(
                 f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        # PyTorch ships its own HIP runtime (soname libamdhip64.so.7, linked by
+        # torch as libamdhip64.so).  Load it first so that libflood binds to
+        # that same runtime instead of mapping a second one from /opt/rocm:
+        # two HIP/HSA runtimes in one process cannot share the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         sig = {
@@ -89,6 +97,7 @@ def lib() -> C.CDLL:
             "fl_time_steps": (C.c_int, [vp, i64, C.POINTER(dbl)]),
             "fl_set_tiling": (C.c_int, [vp, i32, i32]),
             "fl_device_bytes": (C.c_size_t, [vp]),
+            "fl_copy_probe": (C.c_int, [C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -252,6 +261,15 @@ class Flood:
             self.close()
         except Exception:
             pass
+
+
+def copy_probe(nbytes: int, reps: int = 20, variant: int = 1, device: int = 0) -> float:
+    """Achieved GB/s (read + write) of a plain streaming copy of nbytes (fl_copy_probe)."""
+    g = C.c_double()
+    st = lib().fl_copy_probe(device, int(nbytes), int(reps), int(variant), C.byref(g))
+    if st != FL_OK:
+        raise FloodError(st, "fl_copy_probe failed")
+    return g.value
 
 
 def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,

@@ -16,7 +16,8 @@ constexpr int kHalo = 2;
 // One slot of the double-buffered device clock.
 struct ClockSlot {
     double t;          // simulated time at the start of the step that reads it
-    double dt_prev;    // dt of the step that produced this state
+    double dt_prev;    // dt of the step that produced this state (0 for a no-op step)
+    double last_dt;    // dt of the last step with dt > 0
     double v_in;       // inflow volume applied so far (FP64)
     double v_out;      // outflow volume applied so far, up to the step before dt_prev's
     long long steps;   // steps taken with dt > 0

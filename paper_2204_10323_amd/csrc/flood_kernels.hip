@@ -98,12 +98,16 @@ __device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
 #pragma unroll
     for (int m = 0; m < N; ++m) o[m] = t.v[m];
 }
+// Non-temporal vector store: the new state is not read again in this step,
+// so it should not displace the halo rows and columns other waves still read.
+template <typename T, int N>
+struct NVec { typedef T type __attribute__((ext_vector_type(N))); };
 template <typename T, int N>
 __device__ __forceinline__ void stv(T* p, const T (&o)[N]) {
-    VecT<T, N> t;
+    typename NVec<T, N>::type t;
 #pragma unroll
-    for (int m = 0; m < N; ++m) t.v[m] = o[m];
-    *reinterpret_cast<VecT<T, N>*>(p) = t;
+    for (int m = 0; m < N; ++m) t[m] = o[m];
+    __builtin_nontemporal_store(t, reinterpret_cast<typename NVec<T, N>::type*>(p));
 }
 
 // ------------------------------------------------------------ the physics
@@ -236,6 +240,7 @@ __device__ void clock_block(const StepArgs<T>& a) {
     ClockSlot nk = ck;
     nk.t = last ? t_end : ck.t + dt;
     nk.dt_prev = dt;
+    nk.last_dt = dt > 0.0 ? dt : ck.last_dt;
     nk.v_in = ck.v_in + dt * a.dx * si;
     nk.v_out = ck.v_out + ck.dt_prev * a.dx * so;
     nk.steps = ck.steps + (dt > 0.0 ? 1 : 0);
@@ -478,7 +483,15 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
         clock_block<T>(a);
         return;
     }
-    const int wave = (blockIdx.x - 1) * 4 + (threadIdx.x >> 6);
+    // XCD-aware order: workgroups go round-robin to the 8 XCDs, so XCD x runs
+    // blocks b with b % 8 == x.  Give each XCD one contiguous run of the
+    // raster order (strip fastest), i.e. a horizontal band of the grid: the
+    // strips that share boundary cache lines and the chunks that share halo
+    // rows then meet in the same L2.
+    const int nblk = gridDim.x - 1, b = blockIdx.x - 1;
+    const int xcd = b & 7, q8 = nblk >> 3, r8 = nblk & 7;
+    const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int wave = lin * 4 + (threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
     const ClockSlot ck = a.ctl->clk[a.phase & 1];
     int last, done, nonfin;
@@ -515,7 +528,7 @@ __global__ void k_flush(StepArgs<T> a) {
     if (lane == 0) {
         const unsigned long long hb = ctl->hmax[a.phase % 3];
         ctl->report[0] = ck.t;
-        ctl->report[1] = ck.dt_prev;
+        ctl->report[1] = ck.last_dt;
         ctl->report[2] = (double)ck.steps;
         ctl->report[3] = ck.v_in;
         ctl->report[4] = ck.v_out + ck.dt_prev * a.dx * so;

@@ -43,8 +43,8 @@ struct fl_ctx {
     double out_slope = 0.0;
     fl_params params{};
 
-    // launch configuration
-    int cpt = 0, rows = 0;
+    // launch configuration (rows_req 0 = automatic)
+    int cpt = 0, rows = 0, rows_req = 0;
 
     // device state
     bool committed = false;
@@ -262,7 +262,15 @@ fl_status do_commit(fl_ctx* c) {
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
-    if (c->rows == 0) c->rows = 256;
+    c->rows = c->rows_req;
+    if (c->rows == 0) {
+        // 32 rows per work item on large grids (measured best on MI355X at
+        // 16384^2); fewer on small grids so that there are at least ~6000
+        // waves (two rounds of resident waves) to spread over the 256 CUs.
+        const long long strips = (nx + strip_width(c->cpt) - 1) / strip_width(c->cpt);
+        long long r = (long long)ny * strips / 6144;
+        c->rows = (int)std::max<long long>(8, std::min<long long>(32, r));
+    }
     const long long align = 256 / (long long)es;
     c->pitch = ((nx + 8 + align - 1) / align) * align;
     c->nstrips = (nx + strip_width(c->cpt) - 1) / strip_width(c->cpt);
@@ -670,7 +678,7 @@ fl_status fl_set_tiling(fl_ctx* c, int32_t cells_per_lane, int32_t rows_per_item
         return fail(c, FL_EINVAL, "fl_set_tiling: FP64 supports 1 or 2 cells per lane");
     if (rows_per_item < 0) return fail(c, FL_EINVAL, "fl_set_tiling: rows_per_item < 0");
     if (cells_per_lane) c->cpt = cells_per_lane;
-    if (rows_per_item) c->rows = rows_per_item;
+    if (rows_per_item) c->rows_req = rows_per_item;
     invalidate(c);
     return FL_OK;
 }
@@ -723,8 +731,10 @@ fl_status fl_advance(fl_ctx* c, double seconds) {
     double dt_guess = r.last_dt > 0.0 ? r.last_dt : c->params.dt_max;
     if (c->params.dt_fixed > 0.0) dt_guess = c->params.dt_fixed;
     while (t < target) {
+        // Steps past the target are no-ops that still stream the state, so
+        // launch no more than the remaining time needs at the last dt.
         long long want = (long long)std::ceil((target - t) / std::max(dt_guess, 1e-9));
-        want = std::max<long long>(6, std::min<long long>(want + 6, 20000));
+        want = std::max<long long>(1, std::min<long long>(want, 20000));
         if ((st = enqueue_steps(c, want))) break;
         if ((st = read_report(c, &r, false))) break;
         if (r.steps == 0 && r.t <= t) break;

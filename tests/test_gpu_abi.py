@@ -1,0 +1,219 @@
+"""The C interface on the GPU: argument validation, call order, ownership,
+non-finite detection, resume, fl_advance and graph replays."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2204_10323_amd as fl
+from gpu_util import max_abs, run_gpu
+from synth import EAST, NORTH, SOUTH, WEST, Scenario, config_d1, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(nx=8, ny=6, prec="f32"):
+    f = fl.Flood(nx, ny, 1.0, prec)
+    return f
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_einval_cases():
+    L = fl.lib()
+    f = _ctx()
+    c = f.ctx
+    assert L.fl_init_grid(c, 0, 4, 1.0) == fl.FL_EINVAL
+    assert L.fl_init_grid(c, 4, 4, -1.0) == fl.FL_EINVAL
+    assert L.fl_init_grid(c, 4, 4, float("nan")) == fl.FL_EINVAL
+    assert L.fl_init_grid(c, 8, 6, 1.0) == fl.FL_OK
+    z = np.zeros((6, 8), np.float32)
+    assert L.fl_set_dem(c, C.c_void_p(z.ctypes.data), 4, 0) == fl.FL_EINVAL      # stride < nx
+    zb = z.copy(); zb[2, 2] = np.inf
+    assert L.fl_set_dem(c, C.c_void_p(zb.ctypes.data), 8, 0) == fl.FL_EINVAL
+    n = np.full((6, 8), 0.03, np.float32); nb = n.copy(); nb[1, 1] = 0.0
+    assert L.fl_set_manning(c, C.c_void_p(nb.ctypes.data), 8, 0) == fl.FL_EINVAL
+    assert b"Manning" in L.fl_last_error(c)
+    dp = C.POINTER(C.c_double)
+    ts = np.array([0.0, 1.0]); qs = np.array([1.0, 2.0]); bad_t = np.array([1.0, 1.0])
+    neg = np.array([1.0, -2.0])
+    P = lambda a: a.ctypes.data_as(dp)
+    assert L.fl_set_inflow(c, WEST, 4, 4, 1e-3, P(ts), P(qs), 2) == fl.FL_EINVAL   # outside
+    assert L.fl_set_inflow(c, WEST, 0, 2, 0.0, P(ts), P(qs), 2) == fl.FL_EINVAL    # slope
+    assert L.fl_set_inflow(c, WEST, 0, 2, 1e-3, P(bad_t), P(qs), 2) == fl.FL_EINVAL
+    assert L.fl_set_inflow(c, WEST, 0, 2, 1e-3, P(ts), P(neg), 2) == fl.FL_EINVAL
+    assert L.fl_set_inflow(c, 9, 0, 2, 1e-3, P(ts), P(qs), 2) == fl.FL_EINVAL
+    assert L.fl_set_inflow(c, WEST, 0, 3, 1e-3, P(ts), P(qs), 2) == fl.FL_OK
+    assert L.fl_set_outflow(c, WEST, 2, 2, 1e-3) == fl.FL_EINVAL                    # overlap
+    assert L.fl_set_outflow(c, EAST, 0, 7, 1e-3) == fl.FL_EINVAL                    # outside
+    assert L.fl_set_outflow(c, EAST, 0, 6, 1e-3) == fl.FL_OK
+    p = fl.default_params()
+    for field, val in (("alpha", 0.0), ("alpha", 1.5), ("g", 0.0), ("dt_max", -1.0),
+                       ("h_eps", -1e-3), ("dt_fixed", -0.1), ("t_end", float("nan"))):
+        q = fl.default_params(**{field: val})
+        assert L.fl_set_params(c, C.byref(q)) == fl.FL_EINVAL, field
+    h = np.zeros((6, 8), np.float32); h[0, 0] = -1.0
+    assert L.fl_set_state(c, C.c_void_p(h.ctypes.data), None, None, 0.0, 0) == fl.FL_EINVAL
+    assert L.fl_set_tiling(c, 3, 0) == fl.FL_EINVAL
+    f.close()
+
+
+def test_estate_order():
+    L = fl.lib()
+    f = _ctx()
+    c = f.ctx
+    assert L.fl_step(c, 1) == fl.FL_ESTATE
+    assert L.fl_commit(c) == fl.FL_ESTATE              # no DEM / roughness yet
+    f.set_dem(np.zeros((6, 8), np.float32))
+    f.set_manning(np.full((6, 8), 0.03, np.float32))
+    f.commit()
+    f.step(3)
+    f.set_params(dt_max=0.05)                          # any set after commit needs a new commit
+    assert L.fl_step(c, 1) == fl.FL_ESTATE
+    r = fl.fl_report()
+    assert L.fl_get_report(c, C.byref(r)) == fl.FL_ESTATE
+    f.commit()
+    f.step(1)
+    assert L.fl_step(c, -1) == fl.FL_EINVAL
+    f.close()
+
+
+def test_inputs_are_copied():
+    """fl_set_* copy their inputs: changing the caller's arrays afterwards has no effect."""
+    sc = random_tiny(20, 13, 4)
+    f = fl.Flood(sc.nx, sc.ny, sc.dx, "f64")
+    z = sc.z.astype(np.float64).copy()
+    n = sc.n.astype(np.float64).copy()
+    f.set_dem(z)
+    f.set_manning(n)
+    side, first, count, slope, ts, qs = sc.inflow
+    f.set_inflow(side, first, count, slope, ts, qs)
+    f.set_outflow(*sc.outflow)
+    f.set_params(dt_max=sc.dt_max)
+    f.set_state(sc.h0, sc.extra["qx0"], sc.extra["qy0"])
+    z[:] = 99.0
+    n[:] = 1.0
+    f.commit()
+    f.step(20)
+    h = f.get_depth()
+    f.close()
+    o = oracle.Run(sc)
+    o.step(20)
+    assert max_abs(h, o.h) <= 1e-12 * max(1.0, np.abs(o.h).max())
+
+
+def test_device_inputs_and_outputs():
+    """Device (torch) inputs and outputs give the same result as host ones."""
+    import torch
+    sc = random_tiny(33, 17, 8)
+    h_host, *_ = run_gpu(sc, 15, "f32")
+    f = fl.Flood(sc.nx, sc.ny, sc.dx, "f32")
+    f.set_dem(torch.from_numpy(sc.z).cuda())
+    f.set_manning(torch.from_numpy(sc.n).cuda())
+    side, first, count, slope, ts, qs = sc.inflow
+    f.set_inflow(side, first, count, slope, ts, qs)
+    f.set_outflow(*sc.outflow)
+    f.set_params(dt_max=sc.dt_max)
+    f.set_state(torch.from_numpy(sc.h0).cuda(), torch.from_numpy(sc.extra["qx0"]).cuda(),
+                torch.from_numpy(sc.extra["qy0"]).cuda())
+    f.commit()
+    f.step(15)
+    out = torch.empty((sc.ny, sc.nx), device="cuda", dtype=torch.float32)
+    f.get_depth(out)
+    torch.cuda.synchronize()
+    f.close()
+    assert np.array_equal(out.cpu().numpy(), h_host)
+
+
+def test_nonfinite_is_detected_and_stops_the_clock():
+    """An inflow of 1e38 m^3/s overflows the depth: the sentinel trips, the report
+    says ENONFINITE and later steps do not advance the clock."""
+    nx, ny = 12, 6
+    z = np.zeros((ny, nx), np.float32)
+    n = np.full((ny, nx), 0.03, np.float32)
+    sc = Scenario("blowup", nx, ny, 1.0, z, n, np.zeros_like(z),
+                  (WEST, 0, ny, 1e-3, np.array([0.0]), np.array([1e38])), None, dt_max=0.1)
+    f = fl.from_scenario(sc, "f32")
+    f.step(12)
+    r = f.get_report(check=False)
+    assert r.nonfinite == 1
+    with pytest.raises(fl.FloodError) as ei:
+        f.get_report()
+    assert ei.value.status == fl.FL_ENONFINITE
+    steps, t = r.steps, r.t
+    f.step(6)
+    r2 = f.get_report(check=False)
+    assert r2.steps == steps and r2.t == t
+    f.close()
+
+
+def test_resume_is_bitwise_identical():
+    """State read back and set into a new context continues exactly like an uninterrupted run."""
+    sc = config_d1()
+    for prec in ("f32", "f64"):
+        h_ref, qx_ref, qy_ref, r_ref = run_gpu(sc, 300, prec)
+        f = fl.from_scenario(sc, prec)
+        f.step(170)
+        h = f.get_depth()
+        qx, qy = f.get_discharge()
+        t = f.get_report().t
+        f.close()
+        g = fl.from_scenario(sc, prec, commit=False)
+        g.set_state(h, qx, qy, t)
+        g.commit()
+        g.step(130)
+        h2 = g.get_depth()
+        qx2, qy2 = g.get_discharge()
+        r2 = g.get_report()
+        g.close()
+        assert np.array_equal(h2, h_ref), prec
+        assert np.array_equal(qx2, qx_ref) and np.array_equal(qy2, qy_ref), prec
+        assert r2.t == r_ref.t
+
+
+def test_advance_lands_on_target_time():
+    """fl_advance runs until the clock reaches t + seconds, the last step shortened."""
+    sc = config_d1()
+    f = fl.from_scenario(sc, "f64")
+    f.advance(123.4)
+    r = f.get_report()
+    assert r.t == pytest.approx(123.4, abs=1e-9)
+    assert 0 < r.last_dt <= sc.dt_max
+    f.advance(50.0)
+    r2 = f.get_report()
+    assert r2.t == pytest.approx(173.4, abs=1e-9)
+    f.step(5)                      # plain steps continue past the advance target
+    assert f.get_report().t > r2.t
+    f.close()
+    o = oracle.Run(sc)
+    o.s.t_end = 123.4
+    o.p.t_end = 123.4
+    o.step(100000)
+    assert o.clock.t == 123.4
+
+
+def test_t_end_stops_steps():
+    sc = config_d1()
+    f = fl.from_scenario(sc, "f32", t_end=10.0)
+    f.step(50)
+    r = f.get_report()
+    assert r.t == 10.0 and r.done == 1 and r.steps == 10
+    f.close()
+
+
+@pytest.mark.parametrize("spg", [6, 60, 600])
+def test_graph_replay_matches_single_launches(spg):
+    """Steps replayed from a captured graph equal steps launched one by one."""
+    sc = config_d1()
+    h1, qx1, qy1, r1 = run_gpu(sc, 611, "f32", steps_per_graph=spg)
+    f = fl.from_scenario(sc, "f32", steps_per_graph=spg)
+    for _ in range(611):
+        f.step(1)
+    h2 = f.get_depth()
+    r2 = f.get_report()
+    f.close()
+    assert np.array_equal(h1, h2) and r1.t == r2.t and r1.v_out == r2.v_out
