@@ -208,6 +208,46 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
 /* Bytes of device memory the context holds after commit. */
 size_t fl_device_bytes(const fl_ctx *ctx);
 
+/* ---------------------------------------------------------------------- */
+/* Batched ensemble: many independent committed contexts (same device and
+ * precision, any sizes) stepped together by ONE persistent launch.  Members
+ * run the same kernels as fl_step, so each member's result is bitwise the
+ * result of stepping it alone; a member's step k waits only for its own step
+ * k-1, never for the other members.  The batch borrows its members: they
+ * must outlive it and stay committed.  Motivated by the what-if and
+ * parameter-space ensembles the paper points to (Broader Impacts, Future
+ * Work). */
+
+/* Create a batch of nmembers committed contexts.  EINVAL: no members,
+ * mixed devices or precisions, a context listed twice.  ESTATE: a member not
+ * committed. */
+fl_status fl_batch_create(fl_batch **batch, int32_t nmembers, fl_ctx *const *members);
+
+/* Work decomposition of the batch launch: cells per lane along x (1, 2, 4;
+ * FP64: 1, 2) and rows per work item (>= 1).  Default 4 (FP64 2) and 16. */
+fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t rows_per_item);
+
+/* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
+ * trial_steps frozen steps (dt = 0: the state is streamed like a real step
+ * but left unchanged) and keep the fastest.  best[2] receives it, *best_ms
+ * its time per step.  The members' states and clocks are unchanged. */
+fl_status fl_batch_autotune(fl_batch *batch, const int32_t *candidates, int32_t ncand,
+                            int32_t trial_steps, int32_t *best, double *best_ms);
+
+/* Advance every member by nsteps steps in one launch.  Synchronises the
+ * members' streams first and the batch's stream at the end.  EHIP if the
+ * launch fails or a wait ran into its limit. */
+fl_status fl_batch_run(fl_batch *batch, int64_t nsteps);
+
+/* fl_batch_run bracketed by HIP events; returns the launch's milliseconds. */
+fl_status fl_batch_time(fl_batch *batch, int64_t nsteps, double *elapsed_ms);
+
+/* Message of the last failure on the batch (NULL: last fl_batch_create failure). */
+const char *fl_batch_last_error(const fl_batch *batch);
+
+/* Free the batch (not its members).  NULL is a no-op. */
+void fl_batch_destroy(fl_batch *batch);
+
 /* Roofline calibration: a plain streaming copy of `bytes` bytes (16-byte
  * vectors, grid-stride) repeated `reps` times on device `device`; returns the
  * achieved bandwidth in GB/s (bytes read + bytes written per second).

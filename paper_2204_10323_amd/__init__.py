@@ -28,6 +28,8 @@ EXPORTS = [
     "fl_set_inflow", "fl_set_outflow", "fl_set_params", "fl_set_state", "fl_commit", "fl_step",
     "fl_advance", "fl_get_depth", "fl_get_discharge", "fl_get_report", "fl_last_error",
     "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
+    "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
+    "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
 ]
 
 
@@ -98,6 +100,14 @@ def lib() -> C.CDLL:
             "fl_set_tiling": (C.c_int, [vp, i32, i32]),
             "fl_device_bytes": (C.c_size_t, [vp]),
             "fl_copy_probe": (C.c_int, [C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(dbl)]),
+            "fl_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
+            "fl_batch_set_tiling": (C.c_int, [vp, i32, i32]),
+            "fl_batch_autotune": (C.c_int, [vp, C.POINTER(i32), i32, i32, C.POINTER(i32),
+                                            C.POINTER(dbl)]),
+            "fl_batch_run": (C.c_int, [vp, i64]),
+            "fl_batch_time": (C.c_int, [vp, i64, C.POINTER(dbl)]),
+            "fl_batch_last_error": (C.c_char_p, [vp]),
+            "fl_batch_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -255,6 +265,54 @@ class Flood:
         if getattr(self, "ctx", None):
             lib().fl_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batched ensemble (fl_batch) of committed Flood contexts stepped by one launch."""
+
+    def __init__(self, members):
+        self.members = list(members)
+        arr = (C.c_void_p * len(self.members))(*[m.ctx for m in self.members])
+        h = C.c_void_p()
+        st = lib().fl_batch_create(C.byref(h), len(self.members), arr)
+        if st != FL_OK:
+            raise FloodError(st, lib().fl_batch_last_error(None).decode())
+        self.b = h
+
+    def _check(self, st):
+        if st != FL_OK:
+            raise FloodError(st, lib().fl_batch_last_error(self.b).decode())
+
+    def set_tiling(self, cells_per_lane: int, rows_per_item: int):
+        self._check(lib().fl_batch_set_tiling(self.b, cells_per_lane, rows_per_item))
+
+    def autotune(self, candidates, trial_steps: int = 20):
+        flat = [int(v) for pair in candidates for v in pair]
+        arr = (C.c_int32 * len(flat))(*flat)
+        best = (C.c_int32 * 2)()
+        ms = C.c_double()
+        self._check(lib().fl_batch_autotune(self.b, arr, len(candidates), trial_steps, best,
+                                            C.byref(ms)))
+        return (best[0], best[1]), ms.value
+
+    def run(self, nsteps: int):
+        self._check(lib().fl_batch_run(self.b, int(nsteps)))
+
+    def time(self, nsteps: int) -> float:
+        ms = C.c_double()
+        self._check(lib().fl_batch_time(self.b, int(nsteps), C.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().fl_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -60,9 +60,33 @@ struct StepArgs {
     int in_side, in_first, in_count, nsamp;
     int out_side, out_first, out_count, npart;
     int positivity;
+    int freeze;                   // 1: dt forced to 0 (exact no-op steps, for tiling trials)
     int nstrips, nchunks, rows;   // tiling: strips along x, chunks of `rows` rows along y
     int phase;                    // step index modulo 6
     double dx, g, alpha, dt_max, h_eps, dt_fixed;
+};
+
+// One member of a batch: its step arguments for each step counter modulo 6
+// (buffer parity and slot indices), the step counter at the start of the run,
+// and its work.
+template <typename T>
+struct BatchScen {
+    StepArgs<T> a[6];
+    long long n0;       // member's step counter when the run starts
+    int items;          // tile work items per step
+    int first;          // offset of this member's (1 + items) queue entries within a step
+};
+
+template <typename T>
+struct BatchArgs {
+    const BatchScen<T>* scen;
+    int nscen;
+    int per_step;                 // sum over members of (1 + items)
+    long long nsteps;
+    unsigned long long* next;     // work-queue head
+    unsigned long long* done;     // per member: queue entries completed (monotone)
+    int* error;                   // set when a wait exceeds its spin limit
+    long long spin_limit;
 };
 
 // Host-side launchers (flood_kernels.hip).
@@ -72,6 +96,10 @@ template <typename T>
 hipError_t launch_prime(const StepArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_flush(const StepArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_fold(const StepArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out);
 template <typename T>
 hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl* ctl,
                             hipStream_t s);

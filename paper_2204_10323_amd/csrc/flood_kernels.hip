@@ -17,6 +17,8 @@
 // is no MFMA; the bound is HBM bandwidth.
 #include <math.h>
 
+#include <algorithm>
+
 #include "flood_internal.h"
 
 namespace flood {
@@ -148,7 +150,7 @@ __device__ __forceinline__ double step_dt(const StepArgs<T>& a, const ClockSlot&
     last = 0;
     done = 0;
     nonfin = ck.nonfinite || Ord<T>::nonfinite(hb);
-    if (nonfin) return 0.0;
+    if (nonfin || a.freeze) return 0.0;
     double dt;
     if (a.dt_fixed > 0.0) {
         dt = a.dt_fixed;
@@ -215,14 +217,13 @@ __device__ void inflow_solve(const StepArgs<T>& a, double Q, T* dst) {
     for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = (T)(a.in_k[p] * pow53(W - a.in_z[p]));
 }
 
-// The clock block (one wave of block 0): closes the budget of the previous
-// step, advances the clock to the end of this step and prepares the inflow of
-// the next step.  Runs concurrently with the tiles of this step, which only
-// read the current clock slot.
+// The clock (one full wave): closes the budget of the previous step, advances
+// the clock to the end of this step and prepares the inflow of the next step.
+// Runs concurrently with the tiles of this step, which only read the current
+// clock slot.
 template <typename T>
-__device__ void clock_block(const StepArgs<T>& a) {
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
+__device__ void clock_wave(const StepArgs<T>& a) {
+    const int lane = threadIdx.x & 63;
     DevCtl* ctl = a.ctl;
     const int cur = a.phase & 1, nxt = cur ^ 1;
     const ClockSlot ck = ctl->clk[cur];
@@ -477,10 +478,30 @@ __device__ __forceinline__ int part_slot(const StepArgs<T>& a, int s, int c) {
     }
 }
 
+// Work item `item` of one step (strip fastest): the marching tile, then the
+// wave's deepest cell into the next max slot and its outflow partial sum.
+template <typename T, int CPT>
+__device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
+    const ClockSlot ck = a.ctl->clk[a.phase & 1];
+    int last, done, nonfin;
+    const double dt64 = step_dt<T>(a, ck, a.ctl->hmax[a.phase % 3], a.ctl->t_end, last, done, nonfin);
+    const int s = item % a.nstrips, c = item / a.nstrips;
+    unsigned long long hb = 0;
+    double outacc = 0.0;
+    step_item<T, CPT>(a, s, c, (T)dt64, hb, outacc);
+    hb = wave_max_u64(hb);
+    const int slot = part_slot<T>(a, s, c);
+    if (slot >= 0) outacc = wave_sum(outacc);
+    if ((threadIdx.x & 63) == 0) {
+        if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], hb);
+        if (slot >= 0) a.part_cur[slot] = outacc;
+    }
+}
+
 template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     if (blockIdx.x == 0) {
-        clock_block<T>(a);
+        if (threadIdx.x < 64) clock_wave<T>(a);
         return;
     }
     // XCD-aware order: workgroups go round-robin to the 8 XCDs, so XCD x runs
@@ -493,19 +514,60 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
     const int wave = lin * 4 + (threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
-    const ClockSlot ck = a.ctl->clk[a.phase & 1];
-    int last, done, nonfin;
-    const double dt64 = step_dt<T>(a, ck, a.ctl->hmax[a.phase % 3], a.ctl->t_end, last, done, nonfin);
-    const int s = wave % a.nstrips, c = wave / a.nstrips;
-    unsigned long long hb = 0;
-    double outacc = 0.0;
-    step_item<T, CPT>(a, s, c, (T)dt64, hb, outacc);
-    hb = wave_max_u64(hb);
-    const int slot = part_slot<T>(a, s, c);
-    if (slot >= 0) outacc = wave_sum(outacc);
-    if ((threadIdx.x & 63) == 0) {
-        if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], hb);
-        if (slot >= 0) a.part_cur[slot] = outacc;
+    tile_item<T, CPT>(a, wave);
+}
+
+// Persistent batch of independent members, one launch for many steps.  The
+// queue holds, step after step, for each member one clock entry and its tile
+// items.  Entries of step k of a member wait only until that member's step
+// k-1 is complete (its depth maximum and clock then exist), so members do not
+// wait for each other and no grid-wide barrier is needed.  Every entry that
+// is waited on was dequeued earlier by a running wave (the launch is
+// cooperative: all waves are resident), so the lowest unfinished entry can
+// always run.  A wait longer than spin_limit sleeps sets *error and exits.
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long total = (unsigned long long)B.per_step * (unsigned long long)B.nsteps;
+    for (;;) {
+        unsigned long long q = 0;
+        if (lane == 0) q = atomicAdd(B.next, 1ull);
+        // wave-uniform from here on: scalar registers, scalar loads of the arguments
+        q = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(q >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((unsigned)q);
+        if (q >= total) break;
+        const long long k = (long long)(q / (unsigned long long)B.per_step);
+        const int r = (int)(q - (unsigned long long)k * B.per_step);
+        int lo = 0, hi = B.nscen - 1;      // member with first <= r, largest such
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.scen[mid].first <= r) lo = mid; else hi = mid - 1;
+        }
+        const int m = lo;
+        const BatchScen<T>& S = B.scen[m];
+        const int e = r - S.first;
+        if (k > 0) {
+            const unsigned long long need = (unsigned long long)k * (unsigned long long)(S.items + 1);
+            int ok = 1;
+            if (lane == 0) {
+                long long spins = 0;
+                while (__hip_atomic_load(&B.done[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > B.spin_limit) { ok = 0; break; }
+                }
+            }
+            ok = __builtin_amdgcn_readfirstlane(ok);
+            if (!ok) {
+                if (lane == 0) atomicExch(B.error, 1);
+                break;
+            }
+            __threadfence();
+        }
+        const StepArgs<T>& a = S.a[(int)((S.n0 + k) % 6)];
+        if (e == 0) clock_wave<T>(a);
+        else tile_item<T, CPT>(a, e - 1);
+        __threadfence();
+        if (lane == 0) atomicAdd(&B.done[m], 1ull);
     }
 }
 
@@ -535,6 +597,23 @@ __global__ void k_flush(StepArgs<T> a) {
         ctl->report[5] = !(ctl->t_end - ck.t > 0.0) ? 1.0 : 0.0;
         ctl->report[6] = (ck.nonfinite || Ord<T>::nonfinite(hb)) ? 1.0 : 0.0;
     }
+}
+
+// Fold the outflow partial sums of the last step into the clock slot and clear
+// them, so the work decomposition (and with it the partial-sum slots) can
+// change before the next step.
+template <typename T>
+__global__ void k_fold(StepArgs<T> a) {
+    const int lane = threadIdx.x & 63;
+    ClockSlot* ck = &a.ctl->clk[a.phase & 1];
+    double so = 0.0;
+    for (int p = lane; p < a.npart; p += 64) so += a.part_prev[p];
+    so = wave_sum(so);
+    if (lane == 0) {
+        ck->v_out = ck->v_out + ck->dt_prev * a.dx * so;
+        ck->dt_prev = 0.0;
+    }
+    for (int p = lane; p < a.npart; p += 64) const_cast<double*>(a.part_prev)[p] = 0.0;
 }
 
 template <typename T>
@@ -608,6 +687,36 @@ hipError_t launch_flush(const StepArgs<T>& a, hipStream_t s) {
 }
 
 template <typename T>
+hipError_t launch_fold(const StepArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fold<T>), dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int CPT>
+hipError_t launch_batch_cpt(const BatchArgs<T>& b, int device, hipStream_t s, int* blocks_out) {
+    int per_cu = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<T, CPT>, 256, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    const int blocks = std::max(1, per_cu) * ncu;
+    if (blocks_out) *blocks_out = blocks;
+    BatchArgs<T> bb = b;
+    void* args[] = {&bb};
+    return hipLaunchCooperativeKernel((const void*)k_batch<T, CPT>, dim3(blocks), dim3(256), args, 0, s);
+}
+
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out) {
+    switch (cpt) {
+    case 1: return launch_batch_cpt<T, 1>(b, device, s, blocks_out);
+    case 2: return launch_batch_cpt<T, 2>(b, device, s, blocks_out);
+    case 4: return launch_batch_cpt<T, 4>(b, device, s, blocks_out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
 hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl* ctl,
                             hipStream_t s) {
     const long long ncell = (long long)nx * ny;
@@ -632,6 +741,10 @@ template hipError_t launch_prime<float>(const StepArgs<float>&, hipStream_t);
 template hipError_t launch_prime<double>(const StepArgs<double>&, hipStream_t);
 template hipError_t launch_flush<float>(const StepArgs<float>&, hipStream_t);
 template hipError_t launch_flush<double>(const StepArgs<double>&, hipStream_t);
+template hipError_t launch_fold<float>(const StepArgs<float>&, hipStream_t);
+template hipError_t launch_fold<double>(const StepArgs<double>&, hipStream_t);
+template hipError_t launch_batch<float>(const BatchArgs<float>&, int, int, hipStream_t, int*);
+template hipError_t launch_batch<double>(const BatchArgs<double>&, int, int, hipStream_t, int*);
 template hipError_t launch_hmax_init<float>(const float*, long long, int, int, DevCtl*, hipStream_t);
 template hipError_t launch_hmax_init<double>(const double*, long long, int, int, DevCtl*,
                                              hipStream_t);

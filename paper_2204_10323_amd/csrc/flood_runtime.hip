@@ -159,8 +159,30 @@ void side_cell(const fl_ctx* c, int side, int k, int* i, int* j) {
     }
 }
 
+struct Tiling {
+    int cpt, rows, nstrips, nchunks, npart;
+};
+
+Tiling tiling_of(const fl_ctx* c, int cpt, int rows) {
+    Tiling t{cpt, rows, 0, 0, 0};
+    t.nstrips = (c->nx + strip_width(cpt) - 1) / strip_width(cpt);
+    t.nchunks = (c->ny + rows - 1) / rows;
+    if (c->out_count > 0)
+        t.npart = (c->out_side == FL_WEST || c->out_side == FL_EAST) ? t.nchunks : t.nstrips;
+    return t;
+}
+
+template <typename T>
+StepArgs<T> make_args(const fl_ctx* c, long long n, const Tiling& tl, int freeze = 0);
+
 template <typename T>
 StepArgs<T> make_args(const fl_ctx* c, long long n) {
+    Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+    return make_args<T>(c, n, tl, 0);
+}
+
+template <typename T>
+StepArgs<T> make_args(const fl_ctx* c, long long n, const Tiling& tl, int freeze) {
     StepArgs<T> a{};
     const int p = (int)(n & 1), q = p ^ 1;
     a.h_in = (const T*)c->d_h[p];
@@ -193,11 +215,12 @@ StepArgs<T> make_args(const fl_ctx* c, long long n) {
     a.out_side = c->out_count > 0 ? c->out_side : -1;
     a.out_first = c->out_first;
     a.out_count = c->out_count;
-    a.npart = c->npart;
+    a.npart = tl.npart;
     a.positivity = c->params.positivity;
-    a.nstrips = c->nstrips;
-    a.nchunks = c->nchunks;
-    a.rows = c->rows;
+    a.freeze = freeze;
+    a.nstrips = tl.nstrips;
+    a.nchunks = tl.nchunks;
+    a.rows = tl.rows;
     a.phase = (int)(n % 6);
     a.dx = c->dx;
     a.g = c->params.g;
@@ -253,6 +276,24 @@ void fill_host(std::vector<unsigned char>& v, size_t count, const std::vector<do
     for (size_t k = 0; k < count; ++k) p[k] = (T)vals[k];
 }
 
+// 32 rows per work item on large grids (measured best on MI355X at 16384^2);
+// fewer on small grids so that there are at least ~6000 waves (two rounds of
+// resident waves) to spread over the 256 CUs.
+int default_rows(int nx, int ny, int cpt) {
+    const long long strips = (nx + strip_width(cpt) - 1) / strip_width(cpt);
+    const long long r = (long long)ny * strips / 6144;
+    return (int)std::max<long long>(8, std::min<long long>(32, r));
+}
+
+// Fold the last step's outflow partial sums into the clock (see k_fold).
+fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
+    if (c->prec == FL_F64)
+        HIP_TRY(c, launch_fold<double>(make_args<double>(c, c->nstep, tl, 0), c->stream));
+    else
+        HIP_TRY(c, launch_fold<float>(make_args<float>(c, c->nstep, tl, 0), c->stream));
+    return FL_OK;
+}
+
 fl_status do_commit(fl_ctx* c) {
     if (!c->have_grid || !c->have_z || !c->have_n)
         return fail(c, FL_ESTATE, "fl_commit needs fl_init_grid, fl_set_dem and fl_set_manning");
@@ -262,23 +303,15 @@ fl_status do_commit(fl_ctx* c) {
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
-    c->rows = c->rows_req;
-    if (c->rows == 0) {
-        // 32 rows per work item on large grids (measured best on MI355X at
-        // 16384^2); fewer on small grids so that there are at least ~6000
-        // waves (two rounds of resident waves) to spread over the 256 CUs.
-        const long long strips = (nx + strip_width(c->cpt) - 1) / strip_width(c->cpt);
-        long long r = (long long)ny * strips / 6144;
-        c->rows = (int)std::max<long long>(8, std::min<long long>(32, r));
-    }
+    c->rows = c->rows_req ? c->rows_req : default_rows(nx, ny, c->cpt);
     const long long align = 256 / (long long)es;
     c->pitch = ((nx + 8 + align - 1) / align) * align;
-    c->nstrips = (nx + strip_width(c->cpt) - 1) / strip_width(c->cpt);
-    c->nchunks = (ny + c->rows - 1) / c->rows;
-    if (c->out_count > 0)
-        c->npart = (c->out_side == FL_WEST || c->out_side == FL_EAST) ? c->nchunks : c->nstrips;
-    else
-        c->npart = 0;
+    {
+        const Tiling tl = tiling_of(c, c->cpt, c->rows);
+        c->nstrips = tl.nstrips;
+        c->nchunks = tl.nchunks;
+        c->npart = tl.npart;
+    }
     const size_t field = (size_t)c->pitch * (ny + 2 * kHalo) * es;
     fl_status st;
     for (int p = 0; p < 2; ++p) {
@@ -286,7 +319,8 @@ fl_status do_commit(fl_ctx* c) {
         if ((st = dalloc(c, &c->d_qx[p], field))) return st;
         if ((st = dalloc(c, &c->d_qy[p], field))) return st;
         if ((st = dalloc(c, &c->d_qin[p], (size_t)std::max(nx, ny) * es))) return st;
-        if ((st = dalloc(c, (void**)&c->d_part[p], sizeof(double) * std::max(1, c->npart))))
+        // sized for any work decomposition (a batch may use another tiling)
+        if ((st = dalloc(c, (void**)&c->d_part[p], sizeof(double) * std::max(nx, ny))))
             return st;
     }
     if ((st = dalloc(c, &c->d_z, field))) return st;
@@ -794,6 +828,253 @@ fl_status fl_get_report(fl_ctx* c, fl_report* r) {
 }
 
 size_t fl_device_bytes(const fl_ctx* c) { return c ? c->dev_bytes : 0; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct fl_batch {
+    std::vector<fl_ctx*> members;   // in the caller's order
+    std::vector<int> order;         // queue order: members by decreasing work
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fl_precision prec = FL_F32;
+    int cpt = 0, rows = 0;
+    void* d_scen = nullptr;
+    size_t scen_bytes = 0;
+    unsigned long long* d_sync = nullptr;   // [0] queue head, [1..] per-member done counts
+    int* d_error = nullptr;
+    int last_blocks = 0;
+    std::string err;
+};
+
+namespace {
+
+fl_status bfail(fl_batch* b, fl_status s, const std::string& msg) {
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIP_TRY(b, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return bfail((b), FL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+fl_status batch_check_members(fl_batch* b) {
+    for (fl_ctx* c : b->members)
+        if (!c->committed)
+            return bfail(b, FL_ESTATE, "fl_batch: a member is not committed (re-commit after fl_set_*)");
+    return FL_OK;
+}
+
+template <typename T>
+fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
+    const int S = (int)b->members.size();
+    std::vector<BatchScen<T>> scen(S);
+    int first = 0;
+    for (int k = 0; k < S; ++k) {
+        fl_ctx* c = b->members[b->order[k]];
+        const Tiling tl = tiling_of(c, b->cpt, b->rows);
+        for (int r = 0; r < 6; ++r) scen[k].a[r] = make_args<T>(c, r, tl, freeze);
+        scen[k].n0 = c->nstep;
+        scen[k].items = tl.nstrips * tl.nchunks;
+        scen[k].first = first;
+        first += 1 + scen[k].items;
+    }
+    const size_t bytes = sizeof(BatchScen<T>) * S;
+    if (bytes > b->scen_bytes) {
+        if (b->d_scen) (void)hipFree(b->d_scen);
+        b->d_scen = nullptr;
+        b->scen_bytes = 0;
+        BHIP_TRY(b, hipMalloc(&b->d_scen, bytes));
+        b->scen_bytes = bytes;
+    }
+    // Members' pending work is on their own streams; the batch runs on its own.
+    for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    // The partial-sum slots depend on the work decomposition: fold them
+    // before switching to the batch tiling.
+    for (fl_ctx* c : b->members) {
+        Tiling own{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+        if (fold_budget(c, own)) return bfail(b, FL_EHIP, c->err);
+    }
+    for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_scen, scen.data(), bytes, hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipMemsetAsync(b->d_sync, 0, sizeof(unsigned long long) * (S + 1), b->stream));
+    BHIP_TRY(b, hipMemsetAsync(b->d_error, 0, sizeof(int), b->stream));
+    BatchArgs<T> ba{};
+    ba.scen = (const BatchScen<T>*)b->d_scen;
+    ba.nscen = S;
+    ba.per_step = first;
+    ba.nsteps = nsteps;
+    ba.next = b->d_sync;
+    ba.done = b->d_sync + 1;
+    ba.error = b->d_error;
+    ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: only a broken co-residency could reach it
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        BHIP_TRY(b, hipEventCreate(&e0));
+        BHIP_TRY(b, hipEventCreate(&e1));
+        BHIP_TRY(b, hipEventRecord(e0, b->stream));
+    }
+    BHIP_TRY(b, launch_batch<T>(ba, b->cpt, b->device, b->stream, &b->last_blocks));
+    if (ms) BHIP_TRY(b, hipEventRecord(e1, b->stream));
+    int error = 0;
+    BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (ms) {
+        BHIP_TRY(b, hipEventElapsedTime(ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    for (fl_ctx* c : b->members) c->nstep += nsteps;
+    for (int k = 0; k < S; ++k) {
+        fl_ctx* c = b->members[b->order[k]];
+        if (fold_budget(c, tiling_of(c, b->cpt, b->rows))) return bfail(b, FL_EHIP, c->err);
+        BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    }
+    if (error) return bfail(b, FL_EHIP, "fl_batch_run: a wait for a member's previous step timed out");
+    return FL_OK;
+}
+
+fl_status batch_run(fl_batch* b, long long nsteps, int freeze, float* ms) {
+    fl_status st = batch_check_members(b);
+    if (st) return st;
+    if (nsteps == 0) {
+        if (ms) *ms = 0.f;
+        return FL_OK;
+    }
+    BHIP_TRY(b, hipSetDevice(b->device));
+    return b->prec == FL_F64 ? batch_launch<double>(b, nsteps, freeze, ms)
+                             : batch_launch<float>(b, nsteps, freeze, ms);
+}
+
+}  // namespace
+
+extern "C" {
+
+fl_status fl_batch_create(fl_batch** out, int32_t nmembers, fl_ctx* const* members) {
+    if (!out) return FL_EINVAL;
+    *out = nullptr;
+    if (nmembers < 1 || !members) {
+        g_create_error = "fl_batch_create: need at least one member";
+        return FL_EINVAL;
+    }
+    for (int k = 0; k < nmembers; ++k) {
+        if (!members[k] || !members[k]->committed) {
+            g_create_error = "fl_batch_create: every member must be a committed context";
+            return FL_ESTATE;
+        }
+        if (members[k]->device != members[0]->device || members[k]->prec != members[0]->prec) {
+            g_create_error = "fl_batch_create: members must share device and precision";
+            return FL_EINVAL;
+        }
+        for (int l = 0; l < k; ++l)
+            if (members[l] == members[k]) {
+                g_create_error = "fl_batch_create: a context appears twice";
+                return FL_EINVAL;
+            }
+    }
+    fl_batch* b = new (std::nothrow) fl_batch();
+    if (!b) return FL_ENOMEM;
+    b->members.assign(members, members + nmembers);
+    b->device = members[0]->device;
+    b->prec = members[0]->prec;
+    b->cpt = b->prec == FL_F64 ? 2 : 4;
+    b->rows = 16;
+    hipError_t e = hipSetDevice(b->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_sync, sizeof(unsigned long long) * (nmembers + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_error, sizeof(int));
+    if (e != hipSuccess) {
+        g_create_error = std::string("fl_batch_create: ") + hipGetErrorString(e);
+        fl_batch_destroy(b);
+        return FL_EHIP;
+    }
+    b->order.resize(nmembers);
+    for (int k = 0; k < nmembers; ++k) b->order[k] = k;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        return (long long)members[x]->nx * members[x]->ny > (long long)members[y]->nx * members[y]->ny;
+    });
+    *out = b;
+    return FL_OK;
+}
+
+fl_status fl_batch_set_tiling(fl_batch* b, int32_t cells_per_lane, int32_t rows_per_item) {
+    if (!b) return FL_EINVAL;
+    if (cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
+        return bfail(b, FL_EINVAL, "fl_batch_set_tiling: cells_per_lane must be 1, 2 or 4");
+    if (b->prec == FL_F64 && cells_per_lane == 4)
+        return bfail(b, FL_EINVAL, "fl_batch_set_tiling: FP64 supports 1 or 2 cells per lane");
+    if (rows_per_item < 1) return bfail(b, FL_EINVAL, "fl_batch_set_tiling: rows_per_item must be >= 1");
+    b->cpt = cells_per_lane;
+    b->rows = rows_per_item;
+    return FL_OK;
+}
+
+fl_status fl_batch_run(fl_batch* b, int64_t nsteps) {
+    if (!b) return FL_EINVAL;
+    if (nsteps < 0) return bfail(b, FL_EINVAL, "fl_batch_run: nsteps < 0");
+    return batch_run(b, nsteps, 0, nullptr);
+}
+
+fl_status fl_batch_time(fl_batch* b, int64_t nsteps, double* elapsed_ms) {
+    if (!b || !elapsed_ms) return FL_EINVAL;
+    if (nsteps < 0) return bfail(b, FL_EINVAL, "fl_batch_time: nsteps < 0");
+    float ms = 0.f;
+    fl_status st = batch_run(b, nsteps, 0, &ms);
+    *elapsed_ms = ms;
+    return st;
+}
+
+fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncand, int32_t trial_steps,
+                            int32_t* best, double* best_ms) {
+    if (!b || !candidates || ncand < 1 || trial_steps < 1) return FL_EINVAL;
+    const int cpt0 = b->cpt, rows0 = b->rows;
+    double best_t = 1e300;
+    int bc = -1;
+    for (int k = 0; k < ncand; ++k) {
+        fl_status st = fl_batch_set_tiling(b, candidates[2 * k], candidates[2 * k + 1]);
+        if (st) {
+            b->cpt = cpt0;
+            b->rows = rows0;
+            return st;
+        }
+        float ms = 0.f;
+        // Frozen steps (dt = 0) stream the whole state like real steps but leave it unchanged.
+        st = batch_run(b, trial_steps, 1, &ms);
+        if (st) {
+            b->cpt = cpt0;
+            b->rows = rows0;
+            return st;
+        }
+        if (ms < best_t) {
+            best_t = ms;
+            bc = k;
+        }
+    }
+    b->cpt = candidates[2 * bc];
+    b->rows = candidates[2 * bc + 1];
+    if (best) {
+        best[0] = b->cpt;
+        best[1] = b->rows;
+    }
+    if (best_ms) *best_ms = best_t / trial_steps;
+    return FL_OK;
+}
+
+const char* fl_batch_last_error(const fl_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+void fl_batch_destroy(fl_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->d_scen) (void)hipFree(b->d_scen);
+    if (b->d_sync) (void)hipFree(b->d_sync);
+    if (b->d_error) (void)hipFree(b->d_error);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
 
 const char* fl_last_error(const fl_ctx* c) {
     if (!c) return g_create_error.c_str();
