@@ -26,7 +26,8 @@ def build(force: bool = True) -> str:
         srcs = [s for s in _SRC if os.path.exists(s)]
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                        "-fopenmp", "-fPIC", "-shared", "-o", tmp, *srcs, "-lm"], check=True)
+                        "-fopenmp", "-fPIC", "-shared", "-I", _HERE, "-o", tmp, *srcs, "-lm"],
+                       check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -71,11 +72,10 @@ def lib():
         L.orc_face_flux.restype = C.c_double
         L.orc_threads_used.argtypes = [C.c_int32]
         L.orc_threads_used.restype = C.c_int32
-        if hasattr(L, "orc_adj_run"):
-            L.orc_adj_run.argtypes = [C.POINTER(_Problem), dp, dp, dp, dp, dp, C.c_int64,
-                                      C.c_int32, C.POINTER(C.c_int64), C.c_int32, dp,
-                                      dp, dp, dp, C.c_int32]
-            L.orc_adj_run.restype = C.c_int
+        L.orc_adj_run.argtypes = [C.POINTER(_Problem), dp, dp, dp, dp, dp, C.c_int64, C.c_int32,
+                                  C.POINTER(C.c_int64), C.c_int32, dp, dp, dp, dp, dp, dp,
+                                  C.c_int32]
+        L.orc_adj_run.restype = C.c_int
         _lib = L
     return _lib
 
@@ -166,3 +166,32 @@ def face_flux(hL, hR, zL, zR, nL, nR, q, dx, dt, g=9.81, h_eps=1e-4) -> float:
 
 def threads_used(nthreads: int = 0) -> int:
     return lib().orc_threads_used(nthreads)
+
+
+def adjoint(scen, nsteps: int, gauges, obs_every: int, obs=None, dl_dseries=None,
+            n: Optional[np.ndarray] = None, qs: Optional[np.ndarray] = None,
+            positivity: bool = True):
+    """Reverse-mode gradient of the gauge misfit for a fixed-dt run (FP64).
+
+    gauges: flat cell indices j*nx + i.  Returns (series [nobs, ng], loss,
+    grad_n [ny, nx], grad_q [nsamples]).  Either obs (squared misfit) or
+    dl_dseries (adjoint seeds) must be given.
+    """
+    r = Run(scen, positivity=positivity, n=n, qs=qs)
+    g = np.ascontiguousarray(gauges, dtype=np.int64)
+    nobs = nsteps // obs_every
+    series = np.zeros((nobs, len(g)))
+    grad_n = np.zeros((scen.ny, scen.nx))
+    nsamp = r.p.nsamp if scen.inflow is not None else 0
+    grad_q = np.zeros(max(nsamp, 1))
+    loss = C.c_double(0.0)
+    ob = None if obs is None else np.ascontiguousarray(obs, dtype=np.float64)
+    dl = None if dl_dseries is None else np.ascontiguousarray(dl_dseries, dtype=np.float64)
+    rc = lib().orc_adj_run(C.byref(r.p), _dp(r.z), _dp(r.n), _dp(r.h), _dp(r.qx), _dp(r.qy),
+                           int(nsteps), len(g), g.ctypes.data_as(C.POINTER(C.c_int64)),
+                           int(obs_every), None if ob is None else _dp(ob),
+                           None if dl is None else _dp(dl), _dp(series), C.byref(loss),
+                           _dp(grad_n), _dp(grad_q), 1)
+    if rc != 0:
+        raise RuntimeError(f"orc_adj_run failed ({rc})")
+    return series, loss.value, grad_n, grad_q[:nsamp]

@@ -44,26 +44,7 @@
 #include <omp.h>
 #endif
 
-typedef struct {
-    int32_t nx, ny;
-    double dx, g, alpha, dt_max, h_eps, dt_fixed, t_end;
-    int32_t positivity;              /* 1 = donor-cell outflow scaling */
-    int32_t in_side, in_first, in_count;
-    double in_slope;
-    int32_t nsamp;
-    const double *ts, *qs;           /* hydrograph samples (s, m^3/s) */
-    int32_t out_side, out_first, out_count;
-    double out_slope;
-} orc_problem;
-
-typedef struct {
-    double t, last_dt;
-    int64_t steps;
-    double v_in, v_out;
-    int32_t done;                    /* 1 = reached t_end, 2 = non-finite depth */
-} orc_clock;
-
-enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
+#include "flood_oracle.h"
 
 /* x^(5/3) for x > 0, else 0. */
 static double pow53(double x)
@@ -169,7 +150,7 @@ static int orc_threads(int nthreads)
 }
 
 /* One step of the method.  Returns 0, or 2 if a non-finite depth was found. */
-static int orc_one_step(const orc_problem *p, const double *z, const double *n,
+int orc_one_step(const orc_problem *p, const double *z, const double *n,
                         double *h, double *qx, double *qy, double *r, orc_clock *clk,
                         int nth)
 {

@@ -42,19 +42,50 @@ MUTANTS = {
 }
 
 
+# Mistakes planted in the reverse-mode sweep; the finite-difference pins must catch them.
+ADJ_SRC = os.path.join(ROOT, "oracle", "flood_oracle_adjoint.c")
+ADJ_MUTANTS = {
+    "adj_limiter_depth_term_dropped": (
+        "lh[c] = lh1[c] + ((w->lim[c] && h[c] > 0.0) ? w->rho[c] / w->O[c] : 0.0);",
+        "lh[c] = lh1[c];"),
+    "adj_donor_scaling_ignored": ("w->mus[f] = w->mu[f] * rd + nud * sgn(w->qs[f]);",
+                                  "w->mus[f] = w->mu[f];"),
+    "adj_friction_partial_sign": ("*Pn = -qs * dden_dnf / den;", "*Pn = qs * dden_dnf / den;"),
+    "adj_depth_coupling_sign": ("w->mu[f] = l1 + cdt * (hR - hL);", "w->mu[f] = l1 + cdt * (hL - hR);"),
+    "adj_inflow_roughness_path_dropped": ("double dLdk = p53(W - zc[k]) * (a_in[k] - dx * A / D);",
+                                          "double dLdk = p53(W - zc[k]) * a_in[k];"),
+    "adj_hydrograph_weights_swapped": ("grad_q[k] += (1.0 - wgt) * dLdQ;",
+                                       "grad_q[k] += wgt * dLdQ;"),
+}
+
+
+def _build_and_run_pins(tmp_path, src_path, old, new, pins, name):
+    src = open(src_path).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    mut = tmp_path / os.path.basename(src_path)
+    mut.write_text(src.replace(old, new))
+    other = [os.path.join(ROOT, "oracle", f) for f in ("flood_oracle.c", "flood_oracle_adjoint.c")
+             if f != os.path.basename(src_path)]
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                    "-shared", "-I", os.path.join(ROOT, "oracle"), "-o", str(lib), str(mut), *other,
+                    "-lm"], check=True)
+    env = dict(os.environ, FLOOD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                          "--timeout", "60", os.path.join(ROOT, "tests", pins)],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, f"mutant {name} survived the pins:\n{res.stdout[-2000:]}"
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
     old, new = MUTANTS[name]
-    src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
-    mut = tmp_path / "mut.c"
-    mut.write_text(src.replace(old, new))
-    lib = tmp_path / "libmut.so"
-    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
-                    "-shared", "-o", str(lib), str(mut), "-lm"], check=True)
-    env = dict(os.environ, FLOOD_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
-    res = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "--timeout", "60",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
-                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert res.returncode != 0, f"mutant {name} survived the pins:\n{res.stdout[-2000:]}"
+    _build_and_run_pins(tmp_path, SRC, old, new, "test_oracle_pins.py", name)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(ADJ_MUTANTS))
+def test_adjoint_pins_catch_mutant(name, tmp_path):
+    old, new = ADJ_MUTANTS[name]
+    _build_and_run_pins(tmp_path, ADJ_SRC, old, new, "test_oracle_adjoint.py", name)
