@@ -209,6 +209,39 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
 size_t fl_device_bytes(const fl_ctx *ctx);
 
 /* ---------------------------------------------------------------------- */
+/* Reverse mode: gradients of a gauge misfit with respect to the per-cell
+ * Manning n and the inflow hydrograph samples, for runs with a fixed time
+ * step (the paper's constant-dt mode, Methods).  Motivated by calibration
+ * (Introduction) and data assimilation (Future Work).  The forward run keeps
+ * checkpoints of the state every ckpt_stride steps (default ceil(sqrt(N)));
+ * the backward sweep recomputes one segment at a time and reverses its steps
+ * with hand-written adjoint kernels.  Gradients are accumulated in FP64. */
+
+/* Gauges (flat cell indices j*nx + i, host memory) observed after every
+ * obs_every steps; obs [nobs][ngauges] (element type of the context, host or
+ * device) are the observations of the squared misfit, or NULL when the caller
+ * supplies dL/dseries to fl_adj_backward.  EINVAL: dt_fixed == 0, no gauges,
+ * a gauge outside the grid, obs_every < 1, ckpt_stride < 0.  ESTATE: not
+ * committed. */
+fl_status fl_adj_setup(fl_ctx *ctx, const int32_t *gauge_cells, int32_t ngauges, int32_t obs_every,
+                       const void *obs, int64_t nobs, int obs_on_device, int32_t ckpt_stride);
+
+/* Run nsteps steps from the current state, keeping checkpoints; series
+ * [nsteps/obs_every][ngauges] receives the gauge depths (host or device, may
+ * be NULL); *loss = sum (series - obs)^2 if observations were set, else 0.
+ * Synchronises.  EINVAL: t_end inside the run, too few observations. */
+fl_status fl_adj_forward(fl_ctx *ctx, int64_t nsteps, void *series, int on_device, double *loss);
+
+/* Gradients of the last fl_adj_forward run: dl_dseries [nobs][ngauges]
+ * (element type of the context, host or device) are the adjoint seeds, or
+ * NULL for the squared misfit against the observations.  grad_n receives
+ * dL/dn [ny][nx] in FP64 (host or device), grad_q (host, may be NULL) dL/dQ_k
+ * for each hydrograph sample.  The context is left at the end of the forward
+ * run.  ESTATE: no forward run, or the context was stepped since. */
+fl_status fl_adj_backward(fl_ctx *ctx, const void *dl_dseries, double *grad_n, int grad_on_device,
+                          double *grad_q);
+
+/* ---------------------------------------------------------------------- */
 /* Batched ensemble: many independent committed contexts (same device and
  * precision, any sizes) stepped together by ONE persistent launch.  Members
  * run the same kernels as fl_step, so each member's result is bitwise the

@@ -30,6 +30,7 @@ EXPORTS = [
     "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
     "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
+    "fl_adj_setup", "fl_adj_forward", "fl_adj_backward",
 ]
 
 
@@ -108,6 +109,9 @@ def lib() -> C.CDLL:
             "fl_batch_time": (C.c_int, [vp, i64, C.POINTER(dbl)]),
             "fl_batch_last_error": (C.c_char_p, [vp]),
             "fl_batch_destroy": (None, [vp]),
+            "fl_adj_setup": (C.c_int, [vp, C.POINTER(i32), i32, i32, vp, i64, C.c_int, i32]),
+            "fl_adj_forward": (C.c_int, [vp, i64, vp, C.c_int, C.POINTER(dbl)]),
+            "fl_adj_backward": (C.c_int, [vp, vp, C.POINTER(dbl), C.c_int, C.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -257,6 +261,52 @@ class Flood:
         if check:
             _check(self.ctx, st)
         return r
+
+    # -- reverse mode
+    def adj_setup(self, gauges, obs_every: int, obs=None, ckpt_stride: int = 0):
+        g = np.ascontiguousarray(gauges, dtype=np.int32)
+        self._nsamp = None
+        if obs is None:
+            st = lib().fl_adj_setup(self.ctx, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
+                                    obs_every, None, 0, 0, ckpt_stride)
+        else:
+            p, _, dev, keep = _as_input(obs, self.dtype)
+            nobs = obs.shape[0]
+            st = lib().fl_adj_setup(self.ctx, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
+                                    obs_every, p, nobs, dev, ckpt_stride)
+        _check(self.ctx, st)
+        self._ngauges, self._obs_every = len(g), obs_every
+
+    def adj_forward(self, nsteps: int, out=None):
+        """Run nsteps keeping checkpoints; returns (series, loss)."""
+        loss = C.c_double()
+        nobs = nsteps // self._obs_every
+        if out is not None:
+            p, _, dev, keep = _as_input(out, self.dtype)
+            _check(self.ctx, lib().fl_adj_forward(self.ctx, int(nsteps), p, dev, C.byref(loss)))
+            return out, loss.value
+        series = np.empty((nobs, self._ngauges), dtype=self.dtype)
+        _check(self.ctx, lib().fl_adj_forward(self.ctx, int(nsteps), C.c_void_p(series.ctypes.data),
+                                               0, C.byref(loss)))
+        return series, loss.value
+
+    def adj_backward(self, dl_dseries=None, nsamples: int = 0, grad_n_out=None):
+        """Gradients (grad_n [ny, nx] float64, grad_q [nsamples] float64) of the last adj_forward."""
+        dp = C.POINTER(C.c_double)
+        gq = np.zeros(max(1, nsamples), dtype=np.float64)
+        pdl = None
+        keep = None
+        if dl_dseries is not None:
+            pdl, _, _, keep = _as_input(dl_dseries, self.dtype)
+        if grad_n_out is not None:
+            _check(self.ctx, lib().fl_adj_backward(self.ctx, pdl,
+                                                   C.cast(C.c_void_p(grad_n_out.data_ptr()), dp), 1,
+                                                   gq.ctypes.data_as(dp)))
+            return grad_n_out, gq[:nsamples]
+        gn = np.zeros((self.ny, self.nx), dtype=np.float64)
+        _check(self.ctx, lib().fl_adj_backward(self.ctx, pdl, gn.ctypes.data_as(dp), 0,
+                                               gq.ctypes.data_as(dp)))
+        return gn, gq[:nsamples]
 
     def device_bytes(self) -> int:
         return int(lib().fl_device_bytes(self.ctx))

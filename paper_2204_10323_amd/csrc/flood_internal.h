@@ -89,7 +89,41 @@ struct BatchArgs {
     long long spin_limit;
 };
 
-// Host-side launchers (flood_kernels.hip).
+// Reverse of one fixed-dt step (flood_adjoint.hip).
+template <typename T>
+struct AdjArgs {
+    const T* h;            // state x^n (padded layout)
+    const T* qx;
+    const T* qy;
+    const T* z;
+    const T* n;
+    const T* lh1;          // adjoint of x^{n+1}
+    const T* lqx1;
+    const T* lqy1;
+    T* lh;                 // adjoint of x^n
+    T* lqx;
+    T* lqy;
+    T* rr;                 // per cell: donor factor r, and the limiter terms nu, kappa
+    T* nu;
+    T* kap;
+    double* gn;            // dL/dn per cell, dense [ny][nx], accumulated
+    double* ain;           // adjoint of the inflow magnitudes [in_count]
+    double* gq;            // dL/dQ_k [nsamp], accumulated
+    const T* kout;
+    const double* in_z;
+    const double* in_k;
+    const double* ts;
+    const double* qs;
+    long long pitch;
+    int nx, ny;
+    int in_side, in_first, in_count, nsamp;
+    int out_side, out_first, out_count;
+    int positivity;
+    double dx, g, dt, h_eps, in_slope, out_slope;
+    double t;              // time at the start of the forward step
+};
+
+// Host-side launchers (flood_kernels.hip, flood_adjoint.hip).
 template <typename T>
 hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s);
 template <typename T>
@@ -106,6 +140,15 @@ hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl*
 template <typename T>
 hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* partials,
                          int nparts, double* out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_gauge_gather(const T* h, long long pitch, int nx, const int* gauges, int ng,
+                               T* dst, hipStream_t s);
+template <typename T>
+hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* gauges, int ng,
+                             const T* series, const T* obs, const T* dl, hipStream_t s);
 
 int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
 constexpr int kVolumeParts = 1024;

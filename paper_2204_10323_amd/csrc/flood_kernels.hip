@@ -19,203 +19,9 @@
 
 #include <algorithm>
 
-#include "flood_internal.h"
+#include "flood_device.h"
 
 namespace flood {
-
-enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
-
-// ------------------------------------------------------------------ helpers
-// Ordered bits of a depth for the max-reduction: negative -> 0, NaN above +inf.
-template <typename T> struct Ord;
-template <> struct Ord<float> {
-    static __device__ __forceinline__ unsigned long long bits(float h) {
-        if (h >= 0.0f) return (unsigned long long)__float_as_uint(h);
-        if (h < 0.0f) return 0ull;
-        return 0x7fc00000ull;
-    }
-    static __device__ __forceinline__ double value(unsigned long long b) {
-        return (double)__uint_as_float((unsigned)b);
-    }
-    static __device__ __forceinline__ bool nonfinite(unsigned long long b) { return b >= 0x7f800000ull; }
-};
-template <> struct Ord<double> {
-    static __device__ __forceinline__ unsigned long long bits(double h) {
-        if (h >= 0.0) return (unsigned long long)__double_as_longlong(h);
-        if (h < 0.0) return 0ull;
-        return 0x7ff8000000000000ull;
-    }
-    static __device__ __forceinline__ double value(unsigned long long b) {
-        return __longlong_as_double((long long)b);
-    }
-    static __device__ __forceinline__ bool nonfinite(unsigned long long b) {
-        return b >= 0x7ff0000000000000ull;
-    }
-};
-
-__device__ __forceinline__ float cbrt_t(float x) { return cbrtf(x); }
-__device__ __forceinline__ double cbrt_t(double x) { return cbrt(x); }
-
-// x^(5/3) for x > 0, else 0.
-template <typename T>
-__device__ __forceinline__ T pow53(T x) {
-    if (!(x > T(0))) return T(0);
-    T c = cbrt_t(x);
-    return x * (c * c);
-}
-
-template <typename T>
-__device__ __forceinline__ T from_next(T v) { return __shfl_down(v, 1, 64); }
-template <typename T>
-__device__ __forceinline__ T from_prev(T v) { return __shfl_up(v, 1, 64); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-    for (int o = 32; o >= 1; o >>= 1) {
-        unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), o, 64);
-        unsigned hi = __shfl_xor((unsigned)(v >> 32), o, 64);
-        unsigned long long w = ((unsigned long long)hi << 32) | lo;
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N) VecT { T v[N]; };
-
-template <typename T, int N>
-__device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
-    VecT<T, N> t = *reinterpret_cast<const VecT<T, N>*>(p);
-#pragma unroll
-    for (int m = 0; m < N; ++m) o[m] = t.v[m];
-}
-// Non-temporal vector store: the new state is not read again in this step,
-// so it should not displace the halo rows and columns other waves still read.
-template <typename T, int N>
-struct NVec { typedef T type __attribute__((ext_vector_type(N))); };
-template <typename T, int N>
-__device__ __forceinline__ void stv(T* p, const T (&o)[N]) {
-    typename NVec<T, N>::type t;
-#pragma unroll
-    for (int m = 0; m < N; ++m) t[m] = o[m];
-    __builtin_nontemporal_store(t, reinterpret_cast<typename NVec<T, N>::type*>(p));
-}
-
-// ------------------------------------------------------------ the physics
-// Eq. (3) on one face between cells L and R (R on the +axis side).  q is the
-// face discharge at the start of the step; gdt = g*dt.  Flow depth h_f is the
-// higher water surface minus the higher bed; a face with h_f <= h_eps is dry.
-// Friction uses the face's own |q| (per-axis 1-D form) and n_f = (n_L+n_R)/2.
-template <typename T>
-__device__ __forceinline__ T face_q(T etaL, T etaR, T zL, T zR, T nL, T nR, T q, T gdt,
-                                    T inv_dx, T h_eps) {
-    T hf = fmax(etaL, etaR) - fmax(zL, zR);
-    if (hf <= h_eps) return T(0);
-    T nf = T(0.5) * (nL + nR);
-    T grad = (etaR - etaL) * inv_dx;
-    T num = q - (gdt * hf) * grad;
-    T den = T(1) + ((gdt * (nf * nf)) * fabs(q)) / ((hf * hf) * cbrt_t(hf));
-    return num / den;
-}
-
-// Border face value (eq. 5, 6), signed toward +axis.  Inflow magnitudes come
-// from the clock block's solve; outflow is the Manning discharge of the edge
-// cell's own depth; everything else is a closed wall.
-template <typename T>
-__device__ __forceinline__ T border_q(const StepArgs<T>& a, int side, int p, T h_edge) {
-    T v = T(0);
-    if (a.in_side == side) v = a.qin[p];
-    if (a.out_side == side) v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
-    return (side == SIDE_W || side == SIDE_S) ? v : -v;
-}
-
-// dt of this step from the clock slot and the deepest cell of the current
-// state: the fixed step, or min(dt_max, alpha dx / sqrt(g h_max)); shortened to
-// land on t_end; 0 once done or non-finite.  Rounded to T (the step uses it).
-template <typename T>
-__device__ __forceinline__ double step_dt(const StepArgs<T>& a, const ClockSlot& ck,
-                                          unsigned long long hb, double t_end, int& last,
-                                          int& done, int& nonfin) {
-    last = 0;
-    done = 0;
-    nonfin = ck.nonfinite || Ord<T>::nonfinite(hb);
-    if (nonfin || a.freeze) return 0.0;
-    double dt;
-    if (a.dt_fixed > 0.0) {
-        dt = a.dt_fixed;
-    } else {
-        double hm = Ord<T>::value(hb);
-        dt = hm > 0.0 ? fmin(a.dt_max, a.alpha * a.dx / sqrt(a.g * hm)) : a.dt_max;
-    }
-    double rem = t_end - ck.t;
-    if (!(rem > 0.0)) {
-        done = 1;
-        return 0.0;
-    }
-    if (dt >= rem) {
-        dt = rem;
-        last = 1;
-    }
-    return (double)(T)dt;
-}
-
-// Q_in(t): piecewise linear between samples, constant outside.
-template <typename T>
-__device__ double hydrograph(const StepArgs<T>& a, double t) {
-    const int ns = a.nsamp;
-    if (ns <= 0) return 0.0;
-    if (t <= a.ts[0]) return a.qs[0];
-    if (t >= a.ts[ns - 1]) return a.qs[ns - 1];
-    int lo = 0, hi = ns - 1;  // ts[lo] <= t < ts[hi]
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (a.ts[mid] <= t) lo = mid; else hi = mid;
-    }
-    return a.qs[lo] + (a.qs[hi] - a.qs[lo]) * ((t - a.ts[lo]) / (a.ts[hi] - a.ts[lo]));
-}
-
-// Eq. (6) on one wave: water level W with sum_c dx k_c (W - z_c)_+^{5/3} = Q,
-// bracketed and bisected 64 times in FP64; writes the per-cell face
-// discharges (per unit width) into dst[first .. first+count).
-template <typename T>
-__device__ void inflow_solve(const StepArgs<T>& a, double Q, T* dst) {
-    const int lane = threadIdx.x & 63;
-    const int nc = a.in_count;
-    if (nc <= 0) return;
-    if (!(Q > 0.0)) {
-        for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = T(0);
-        return;
-    }
-    double lo = 1e300, hi = -1e300, ks = 0.0;
-    for (int p = lane; p < nc; p += 64) {
-        lo = fmin(lo, a.in_z[p]);
-        hi = fmax(hi, a.in_z[p]);
-        ks += a.in_k[p];
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    ks = wave_sum(ks);
-    hi += pow(Q / (a.dx * ks), 0.6);
-    for (int it = 0; it < 64; ++it) {
-        double mid = 0.5 * (lo + hi), F = 0.0;
-        for (int p = lane; p < nc; p += 64) F += a.dx * a.in_k[p] * pow53(mid - a.in_z[p]);
-        F = wave_sum(F) - Q;
-        if (F < 0.0) lo = mid; else hi = mid;
-    }
-    const double W = 0.5 * (lo + hi);
-    for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = (T)(a.in_k[p] * pow53(W - a.in_z[p]));
-}
 
 // The clock (one full wave): closes the budget of the previous step, advances
 // the clock to the end of this step and prepares the inflow of the next step.

@@ -63,6 +63,22 @@ struct fl_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
+
+    // reverse mode (fl_adj_*): settings, checkpoints and the forward's record
+    bool adj_setup = false;
+    std::vector<int> gauges;
+    int obs_every = 0, ckpt_req = 0;
+    long long nobs_set = 0;
+    std::vector<void*> adj_allocs;       // freed by a new setup, commit or destroy
+    int* d_gauges = nullptr;
+    void* d_obs = nullptr;
+    void* d_series = nullptr;
+    void* d_ck = nullptr;                // checkpoints: [nck][h, qx, qy fields]
+    DevCtl* d_ck_ctl = nullptr;          // [nck]
+    void* d_ck_qin = nullptr;            // [nck][side length]
+    void* d_end = nullptr;               // the end-of-forward clock, inflow, partials, edges
+    long long adj_n0 = 0, adj_nsteps = 0, adj_C = 0, adj_nck = 0, adj_nobs = 0;
+    double adj_t0 = 0.0;
 };
 
 namespace {
@@ -115,7 +131,18 @@ fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int 
 
 void invalidate(fl_ctx* c) { c->committed = false; }
 
+void free_adjoint(fl_ctx* c) {
+    for (void* p : c->adj_allocs) (void)hipFree(p);
+    c->adj_allocs.clear();
+    c->d_gauges = nullptr;
+    c->d_obs = c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
+    c->d_ck_ctl = nullptr;
+    c->adj_setup = false;
+    c->adj_nsteps = 0;
+}
+
 void free_device(fl_ctx* c) {
+    free_adjoint(c);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->graph_exec = nullptr;
@@ -828,6 +855,347 @@ fl_status fl_get_report(fl_ctx* c, fl_report* r) {
 }
 
 size_t fl_device_bytes(const fl_ctx* c) { return c ? c->dev_bytes : 0; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ reverse mode
+namespace {
+
+fl_status adalloc(fl_ctx* c, void** p, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(c, e == hipErrorOutOfMemory ? FL_ENOMEM : FL_EHIP,
+                    std::string("hipMalloc (adjoint): ") + hipGetErrorString(e));
+    }
+    c->adj_allocs.push_back(*p);
+    HIP_TRY(c, hipMemsetAsync(*p, 0, bytes, c->stream));
+    return FL_OK;
+}
+
+size_t field_bytes(const fl_ctx* c) { return (size_t)c->pitch * (c->ny + 2 * kHalo) * esz(c); }
+size_t side_bytes(const fl_ctx* c) { return (size_t)std::max(c->nx, c->ny) * esz(c); }
+
+// Layout of the end-of-forward snapshot: clock block, both inflow buffers,
+// both partial-sum buffers, and the west/south edge faces.
+size_t end_bytes(const fl_ctx* c) {
+    return sizeof(DevCtl) + 2 * side_bytes(c) + 2 * sizeof(double) * std::max(c->nx, c->ny) +
+           ((size_t)c->ny + c->nx) * esz(c);
+}
+
+fl_status snapshot_end(fl_ctx* c, bool restore) {
+    unsigned char* e = static_cast<unsigned char*>(c->d_end);
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    auto mv = [&](void* live, size_t bytes) -> hipError_t {
+        hipError_t r = restore ? hipMemcpyAsync(live, e, bytes, k, c->stream)
+                               : hipMemcpyAsync(e, live, bytes, k, c->stream);
+        e += bytes;
+        return r;
+    };
+    const size_t pb = sizeof(double) * std::max(c->nx, c->ny);
+    HIP_TRY(c, mv(c->d_ctl, sizeof(DevCtl)));
+    HIP_TRY(c, mv(c->d_qin[0], side_bytes(c)));
+    HIP_TRY(c, mv(c->d_qin[1], side_bytes(c)));
+    HIP_TRY(c, mv(c->d_part[0], pb));
+    HIP_TRY(c, mv(c->d_part[1], pb));
+    HIP_TRY(c, mv(c->d_edge_w, (size_t)c->ny * esz(c)));
+    HIP_TRY(c, mv(c->d_edge_s, (size_t)c->nx * esz(c)));
+    return FL_OK;
+}
+
+template <typename T>
+fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_device,
+                         double* grad_q) {
+    const size_t fb = field_bytes(c), sb = side_bytes(c);
+    const long long N = c->adj_nsteps, C = c->adj_C, n0 = c->adj_n0;
+    const int nx = c->nx, ny = c->ny, ng = (int)c->gauges.size();
+    fl_status st;
+    // scratch of the sweep (freed at the end)
+    std::vector<void*> tmp;
+    auto talloc = [&](void** p, size_t bytes) -> fl_status {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return fail(c, FL_ENOMEM, std::string("adjoint scratch: ") + hipGetErrorString(e));
+        tmp.push_back(*p);
+        return hipMemsetAsync(*p, 0, std::max<size_t>(bytes, 256), c->stream) == hipSuccess
+                   ? FL_OK : fail(c, FL_EHIP, "hipMemsetAsync");
+    };
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        for (void* p : tmp) (void)hipFree(p);
+    };
+    void *store = nullptr, *lam = nullptr, *aux = nullptr;
+    double *gn = nullptr, *ain = nullptr, *gq = nullptr;
+    void* d_dl = nullptr;
+    const int nsamp = (int)c->ts.size();
+    if ((st = talloc(&store, fb * 3 * (C + 1))) || (st = talloc(&lam, fb * 6)) ||
+        (st = talloc(&aux, fb * 3)) || (st = talloc((void**)&gn, sizeof(double) * nx * ny)) ||
+        (st = talloc((void**)&ain, sizeof(double) * std::max(1, c->in_count))) ||
+        (st = talloc((void**)&gq, sizeof(double) * std::max(1, nsamp)))) {
+        cleanup();
+        return st;
+    }
+    if (dl) {
+        const size_t bytes = (size_t)c->adj_nobs * ng * sizeof(T);
+        if ((st = talloc(&d_dl, bytes))) { cleanup(); return st; }
+        hipError_t e = hipMemcpyAsync(d_dl, dl, bytes, hipMemcpyDefault, c->stream);
+        if (e != hipSuccess) { cleanup(); return hip_fail(c, e, "copy dL/dseries"); }
+    }
+    auto F = [&](void* base, long long k) { return static_cast<unsigned char*>(base) + fb * k; };
+    T* lamf[6];
+    for (int k = 0; k < 6; ++k) lamf[k] = (T*)F(lam, k);
+    int cur = 0;   // lamf[3*cur .. 3*cur+2] hold the adjoint of the later state
+    // the host replays the device clock: t_{k+1} = t_k + dt (dt rounded to T)
+    std::vector<double> tseq(N + 1);
+    const double dtT = (double)(T)c->params.dt_fixed;
+    tseq[0] = c->adj_t0;
+    for (long long k = 0; k < N; ++k) tseq[k + 1] = tseq[k] + dtT;
+    const T* series = (const T*)c->d_series;
+    const T* obs = (const T*)c->d_obs;
+    const T* dlT = (const T*)d_dl;
+    hipError_t e = hipSuccess;
+    for (long long sgi = c->adj_nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+        const long long ks = sgi * C, ke = std::min(ks + C, N);
+        // restore the checkpoint: clock, the inflow that step reads, the state
+        const long long nstart = n0 + ks;
+        e = hipMemcpyAsync(c->d_ctl, c->d_ck_ctl + sgi, sizeof(DevCtl), hipMemcpyDeviceToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->d_qin[nstart & 1], static_cast<unsigned char*>(c->d_ck_qin) + sb * sgi, sb,
+                               hipMemcpyDeviceToDevice, c->stream);
+        for (int f = 0; f < 3 && e == hipSuccess; ++f)
+            e = hipMemcpyAsync(F(store, f), static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + f), fb,
+                               hipMemcpyDeviceToDevice, c->stream);
+        // recompute the segment, keeping every state
+        for (long long k = ks; k < ke && e == hipSuccess; ++k) {
+            StepArgs<T> a = make_args<T>(c, n0 + k);
+            const long long si = k - ks;
+            a.h_in = (const T*)F(store, 3 * si + 0);
+            a.qx_in = (const T*)F(store, 3 * si + 1);
+            a.qy_in = (const T*)F(store, 3 * si + 2);
+            a.h_out = (T*)F(store, 3 * (si + 1) + 0);
+            a.qx_out = (T*)F(store, 3 * (si + 1) + 1);
+            a.qy_out = (T*)F(store, 3 * (si + 1) + 2);
+            e = launch_step<T>(a, c->cpt, c->stream);
+        }
+        // reverse the segment's steps
+        for (long long k = ke - 1; k >= ks && e == hipSuccess; --k) {
+            T* l1 = lamf[3 * cur];
+            if ((k + 1) % c->obs_every == 0) {
+                const long long o = (k + 1) / c->obs_every - 1;
+                e = launch_gauge_seed<T>(l1, c->pitch, nx, c->d_gauges, ng, series + o * ng,
+                                         obs ? obs + o * ng : nullptr, dlT ? dlT + o * ng : nullptr,
+                                         c->stream);
+                if (e != hipSuccess) break;
+            }
+            AdjArgs<T> a{};
+            const long long si = k - ks;
+            a.h = (const T*)F(store, 3 * si + 0);
+            a.qx = (const T*)F(store, 3 * si + 1);
+            a.qy = (const T*)F(store, 3 * si + 2);
+            a.z = (const T*)c->d_z;
+            a.n = (const T*)c->d_n;
+            a.lh1 = lamf[3 * cur];
+            a.lqx1 = lamf[3 * cur + 1];
+            a.lqy1 = lamf[3 * cur + 2];
+            a.lh = lamf[3 * (1 - cur)];
+            a.lqx = lamf[3 * (1 - cur) + 1];
+            a.lqy = lamf[3 * (1 - cur) + 2];
+            a.rr = (T*)F(aux, 0);
+            a.nu = (T*)F(aux, 1);
+            a.kap = (T*)F(aux, 2);
+            a.gn = gn;
+            a.ain = ain;
+            a.gq = gq;
+            a.kout = (const T*)c->d_kout;
+            a.in_z = c->d_in_z;
+            a.in_k = c->d_in_k;
+            a.ts = c->d_ts;
+            a.qs = c->d_qs;
+            a.pitch = c->pitch;
+            a.nx = nx;
+            a.ny = ny;
+            a.in_side = c->in_count > 0 ? c->in_side : -1;
+            a.in_first = c->in_first;
+            a.in_count = c->in_count;
+            a.nsamp = nsamp;
+            a.out_side = c->out_count > 0 ? c->out_side : -1;
+            a.out_first = c->out_first;
+            a.out_count = c->out_count;
+            a.positivity = c->params.positivity;
+            a.dx = c->dx;
+            a.g = c->params.g;
+            a.dt = c->params.dt_fixed;
+            a.h_eps = c->params.h_eps;
+            a.in_slope = c->in_slope;
+            a.out_slope = c->out_slope;
+            a.t = tseq[k];
+            e = launch_adjoint_step<T>(a, c->stream);
+            cur = 1 - cur;
+        }
+    }
+    if (e == hipSuccess) {
+        e = hipMemcpyAsync(grad_n, gn, sizeof(double) * nx * ny,
+                           grad_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+    }
+    std::vector<double> gqh(std::max(1, nsamp));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(gqh.data(), gq, sizeof(double) * gqh.size(), hipMemcpyDeviceToHost, c->stream);
+    // back to the end of the forward run
+    c->nstep = n0 + N;
+    if (e == hipSuccess && (st = snapshot_end(c, true))) { cleanup(); return st; }
+    cleanup();
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint sweep");
+    if (grad_q)
+        for (int k = 0; k < nsamp; ++k) grad_q[k] = gqh[k];
+    return FL_OK;
+}
+
+template <typename T>
+fl_status adj_forward_t(fl_ctx* c, long long N, void* series_out, int on_device, double* loss) {
+    fl_report r{};
+    fl_status st = read_report(c, &r, false);
+    if (st) return st;
+    const double dtT = (double)(T)c->params.dt_fixed;
+    if (!(c->params.t_end >= r.t + dtT * (double)N * (1.0 + 1e-12)))
+        return fail(c, FL_EINVAL, "fl_adj_forward: t_end falls inside the run");
+    const long long nobs = N / c->obs_every;
+    const int ng = (int)c->gauges.size();
+    if (c->d_obs && c->nobs_set < nobs)
+        return fail(c, FL_EINVAL, "fl_adj_forward: fewer observations set than the run takes");
+    // release the record of an earlier forward run (keep gauges and observations)
+    std::vector<void*> keep;
+    for (void* p : c->adj_allocs)
+        if (p == c->d_gauges || p == c->d_obs) keep.push_back(p); else (void)hipFree(p);
+    c->adj_allocs = keep;
+    c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
+    c->d_ck_ctl = nullptr;
+    c->adj_nsteps = 0;
+    const long long C = c->ckpt_req > 0 ? c->ckpt_req
+                                        : std::max<long long>(1, (long long)std::ceil(std::sqrt((double)N)));
+    const long long nck = (N + C - 1) / C;
+    const size_t fb = field_bytes(c), sb = side_bytes(c);
+    if ((st = adalloc(c, &c->d_series, sizeof(T) * std::max<long long>(1, nobs) * ng))) return st;
+    if ((st = adalloc(c, &c->d_ck, fb * 3 * nck))) return st;
+    if ((st = adalloc(c, (void**)&c->d_ck_ctl, sizeof(DevCtl) * nck))) return st;
+    if ((st = adalloc(c, &c->d_ck_qin, sb * nck))) return st;
+    if ((st = adalloc(c, &c->d_end, end_bytes(c)))) return st;
+    const long long n0 = c->nstep;
+    long long k = 0;
+    while (k < N) {
+        if (k % C == 0) {
+            const long long sgi = k / C;
+            const int p = (int)(c->nstep & 1);
+            HIP_TRY(c, hipMemcpyAsync(static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + 0), c->d_h[p], fb,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + 1), c->d_qx[p], fb,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + 2), c->d_qy[p], fb,
+                                      hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(c->d_ck_ctl + sgi, c->d_ctl, sizeof(DevCtl), hipMemcpyDeviceToDevice,
+                                      c->stream));
+            HIP_TRY(c, hipMemcpyAsync(static_cast<unsigned char*>(c->d_ck_qin) + sb * sgi, c->d_qin[p], sb,
+                                      hipMemcpyDeviceToDevice, c->stream));
+        }
+        const long long next_ck = (k / C + 1) * C;
+        const long long next_obs = (k / c->obs_every + 1) * c->obs_every;
+        const long long next = std::min(std::min(next_ck, next_obs), N);
+        if ((st = enqueue_steps(c, next - k))) return st;
+        k = next;
+        if (k % c->obs_every == 0 && k / c->obs_every <= nobs) {
+            const long long o = k / c->obs_every - 1;
+            HIP_TRY(c, launch_gauge_gather<T>((const T*)c->d_h[c->nstep & 1], c->pitch, c->nx, c->d_gauges, ng,
+                                              (T*)c->d_series + o * ng, c->stream));
+        }
+    }
+    if ((st = snapshot_end(c, false))) return st;
+    c->adj_n0 = n0;
+    c->adj_nsteps = N;
+    c->adj_C = C;
+    c->adj_nck = nck;
+    c->adj_nobs = nobs;
+    c->adj_t0 = r.t;
+    std::vector<T> sh((size_t)std::max<long long>(1, nobs) * ng), oh;
+    HIP_TRY(c, hipMemcpyAsync(sh.data(), c->d_series, sizeof(T) * nobs * ng, hipMemcpyDeviceToHost, c->stream));
+    if (c->d_obs) {
+        oh.resize(sh.size());
+        HIP_TRY(c, hipMemcpyAsync(oh.data(), c->d_obs, sizeof(T) * nobs * ng, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (series_out)
+        HIP_TRY(c, hipMemcpyAsync(series_out, c->d_series, sizeof(T) * nobs * ng,
+                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double L = 0.0;
+    if (c->d_obs)
+        for (size_t q = 0; q < (size_t)nobs * ng; ++q) {
+            const double d = (double)sh[q] - (double)oh[q];
+            L += d * d;
+        }
+    if (loss) *loss = L;
+    fl_report r2{};
+    if ((st = read_report(c, &r2, false))) return st;
+    return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, int32_t obs_every,
+                       const void* obs, int64_t nobs, int obs_on_device, int32_t ckpt_stride) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_adj_setup before fl_commit");
+    if (!(c->params.dt_fixed > 0.0))
+        return fail(c, FL_EINVAL, "fl_adj_setup: the reverse mode needs a fixed time step (dt_fixed > 0)");
+    if (!gauge_cells || ngauges < 1 || obs_every < 1 || ckpt_stride < 0 || (obs && nobs < 1))
+        return fail(c, FL_EINVAL, "fl_adj_setup: need gauges, obs_every >= 1, ckpt_stride >= 0");
+    for (int k = 0; k < ngauges; ++k)
+        if (gauge_cells[k] < 0 || (long long)gauge_cells[k] >= (long long)c->nx * c->ny)
+            return fail(c, FL_EINVAL, "fl_adj_setup: gauge cell outside the grid");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_adjoint(c);
+    c->gauges.assign(gauge_cells, gauge_cells + ngauges);
+    c->obs_every = obs_every;
+    c->ckpt_req = ckpt_stride;
+    fl_status st;
+    if ((st = adalloc(c, (void**)&c->d_gauges, sizeof(int) * ngauges))) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->d_gauges, gauge_cells, sizeof(int) * ngauges, hipMemcpyHostToDevice, c->stream));
+    c->nobs_set = 0;
+    if (obs) {
+        const size_t bytes = esz(c) * (size_t)nobs * ngauges;
+        if ((st = adalloc(c, &c->d_obs, bytes))) return st;
+        HIP_TRY(c, hipMemcpyAsync(c->d_obs, obs, bytes, obs_on_device ? hipMemcpyDeviceToDevice
+                                                                      : hipMemcpyHostToDevice, c->stream));
+        c->nobs_set = nobs;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->adj_setup = true;
+    return FL_OK;
+}
+
+fl_status fl_adj_forward(fl_ctx* c, int64_t nsteps, void* series, int on_device, double* loss) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed || !c->adj_setup) return fail(c, FL_ESTATE, "fl_adj_forward needs fl_commit and fl_adj_setup");
+    if (nsteps < 1) return fail(c, FL_EINVAL, "fl_adj_forward: nsteps < 1");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return c->prec == FL_F64 ? adj_forward_t<double>(c, nsteps, series, on_device, loss)
+                             : adj_forward_t<float>(c, nsteps, series, on_device, loss);
+}
+
+fl_status fl_adj_backward(fl_ctx* c, const void* dl_dseries, double* grad_n, int grad_on_device,
+                          double* grad_q) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed || !c->adj_setup || c->adj_nsteps < 1)
+        return fail(c, FL_ESTATE, "fl_adj_backward needs a completed fl_adj_forward");
+    if (c->nstep != c->adj_n0 + c->adj_nsteps)
+        return fail(c, FL_ESTATE, "fl_adj_backward: the context was stepped after fl_adj_forward");
+    if (!grad_n) return fail(c, FL_EINVAL, "fl_adj_backward: NULL grad_n");
+    if (!dl_dseries && !c->d_obs)
+        return fail(c, FL_EINVAL, "fl_adj_backward: no observations set and no dL/dseries given");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return c->prec == FL_F64 ? adj_backward_t<double>(c, dl_dseries, grad_n, grad_on_device, grad_q)
+                             : adj_backward_t<float>(c, dl_dseries, grad_n, grad_on_device, grad_q);
+}
 
 }  // extern "C"
 
