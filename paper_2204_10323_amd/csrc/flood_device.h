@@ -87,16 +87,20 @@ __device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
 #pragma unroll
     for (int m = 0; m < N; ++m) o[m] = t.v[m];
 }
-// Non-temporal vector store: the new state is not read again in this step,
-// so it should not displace the halo rows and columns other waves still read.
+// Vector store of the new state.  NT = true marks it non-temporal: the new
+// state is not read again within the launch, so it should not displace the
+// halo rows and columns other waves still read.  Kernels that hand data to
+// other waves inside one launch (the persistent batch) store normally, so the
+// data is resident in L2 when the wave's memory counter drains.
 template <typename T, int N>
 struct NVec { typedef T type __attribute__((ext_vector_type(N))); };
-template <typename T, int N>
+template <typename T, int N, bool NT>
 __device__ __forceinline__ void stv(T* p, const T (&o)[N]) {
     typename NVec<T, N>::type t;
 #pragma unroll
     for (int m = 0; m < N; ++m) t[m] = o[m];
-    __builtin_nontemporal_store(t, reinterpret_cast<typename NVec<T, N>::type*>(p));
+    if (NT) __builtin_nontemporal_store(t, reinterpret_cast<typename NVec<T, N>::type*>(p));
+    else *reinterpret_cast<typename NVec<T, N>::type*>(p) = t;
 }
 
 // ------------------------------------------------------------ the physics
@@ -172,30 +176,40 @@ __device__ double hydrograph(const StepArgs<T>& a, double t) {
     return a.qs[lo] + (a.qs[hi] - a.qs[lo]) * ((t - a.ts[lo]) / (a.ts[hi] - a.ts[lo]));
 }
 
-// Eq. (6) on one wave: the water level W with sum_c dx k_c (W - z_c)_+^{5/3} = Q
-// (k_c = sqrt(S_in)/n_c), bracketed and bisected 64 times in FP64.  The sum
-// is continuous and strictly increasing above min z, so W is unique.  Every
-// lane returns the same W.  Requires Q > 0 and nc > 0.
+// Eq. (6) on one wave: the water level W with F(W) = sum_c dx k_c (W - z_c)_+^{5/3}
+// - Q = 0 (k_c = sqrt(S_in)/n_c).  F is continuous, convex and strictly
+// increasing above min z, so the root is unique, and Newton's method started
+// where F >= 0 (the right end of the bracket [min z, max z + (Q/(dx sum k))^{3/5}])
+// decreases monotonically onto it; it stops when an update no longer
+// decreases W.  Every lane returns the same W.  Requires Q > 0 and nc > 0.
 __device__ inline double inflow_level(const double* in_z, const double* in_k, int nc, double dx,
                                       double Q) {
     const int lane = threadIdx.x & 63;
-    double lo = 1e300, hi = -1e300, ks = 0.0;
+    double hi = -1e300, ks = 0.0;
     for (int p = lane; p < nc; p += 64) {
-        lo = fmin(lo, in_z[p]);
         hi = fmax(hi, in_z[p]);
         ks += in_k[p];
     }
-    lo = wave_min(lo);
     hi = wave_max(hi);
     ks = wave_sum(ks);
-    hi += pow(Q / (dx * ks), 0.6);
-    for (int it = 0; it < 64; ++it) {
-        double mid = 0.5 * (lo + hi), F = 0.0;
-        for (int p = lane; p < nc; p += 64) F += dx * in_k[p] * pow53(mid - in_z[p]);
+    double W = hi + pow(Q / (dx * ks), 0.6);
+    for (int it = 0; it < 60; ++it) {
+        double F = 0.0, dF = 0.0;
+        for (int p = lane; p < nc; p += 64) {
+            const double d = W - in_z[p];
+            if (d > 0.0) {
+                const double c = cbrt(d);
+                F += dx * in_k[p] * (d * (c * c));
+                dF += dx * in_k[p] * (5.0 / 3.0) * (c * c);
+            }
+        }
         F = wave_sum(F) - Q;
-        if (F < 0.0) lo = mid; else hi = mid;
+        dF = wave_sum(dF);
+        const double Wn = W - F / dF;
+        if (!(Wn < W)) break;
+        W = Wn;
     }
-    return 0.5 * (lo + hi);
+    return W;
 }
 
 // The inflow split on one wave: per-cell face discharges (per unit width)

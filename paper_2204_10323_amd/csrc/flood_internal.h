@@ -77,13 +77,18 @@ struct BatchScen {
     int first;          // offset of this member's (1 + items) queue entries within a step
 };
 
+// Members are bin-packed onto the XCDs; each XCD has its own queue, served
+// only by the waves running on it, so a member's data never leaves one L2.
+constexpr int kMaxXcc = 16;
+
 template <typename T>
 struct BatchArgs {
-    const BatchScen<T>* scen;
-    int nscen;
-    int per_step;                 // sum over members of (1 + items)
+    const BatchScen<T>* scen;     // grouped by XCD: members [xbegin[x], xbegin[x+1]) run on XCD x
+    int nxcc;
+    int xbegin[kMaxXcc + 1];
+    int per_step[kMaxXcc];        // per XCD: sum over its members of (1 + items)
     long long nsteps;
-    unsigned long long* next;     // work-queue head
+    unsigned long long* next;     // per XCD work-queue head
     unsigned long long* done;     // per member: queue entries completed (monotone)
     int* error;                   // set when a wait exceeds its spin limit
     long long spin_limit;

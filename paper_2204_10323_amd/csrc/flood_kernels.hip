@@ -63,7 +63,7 @@ __device__ void clock_wave(const StepArgs<T>& a) {
 
 // One work item: strip s (columns), chunk c (rows).  Accumulates the ordered
 // bits of the deepest new depth and the outflow discharge leaving the grid.
-template <typename T, int CPT>
+template <typename T, int CPT, bool NTS>
 __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned long long& hbits,
                           double& outacc) {
     constexpr int WL = 64 * CPT;  // loaded columns
@@ -217,9 +217,9 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
             }
             const long long o = (long long)(ko + kHalo) * P + pcol;
             if (all_store) {
-                stv<T, CPT>(a.h_out + o, hn);
-                stv<T, CPT>(a.qx_out + o, qnx2);
-                stv<T, CPT>(a.qy_out + o, qny2);
+                stv<T, CPT, NTS>(a.h_out + o, hn);
+                stv<T, CPT, NTS>(a.qx_out + o, qnx2);
+                stv<T, CPT, NTS>(a.qy_out + o, qny2);
             } else if (any_store) {
 #pragma unroll
                 for (int m = 0; m < CPT; ++m)
@@ -286,7 +286,7 @@ __device__ __forceinline__ int part_slot(const StepArgs<T>& a, int s, int c) {
 
 // Work item `item` of one step (strip fastest): the marching tile, then the
 // wave's deepest cell into the next max slot and its outflow partial sum.
-template <typename T, int CPT>
+template <typename T, int CPT, bool NTS>
 __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     const ClockSlot ck = a.ctl->clk[a.phase & 1];
     int last, done, nonfin;
@@ -294,7 +294,7 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     const int s = item % a.nstrips, c = item / a.nstrips;
     unsigned long long hb = 0;
     double outacc = 0.0;
-    step_item<T, CPT>(a, s, c, (T)dt64, hb, outacc);
+    step_item<T, CPT, NTS>(a, s, c, (T)dt64, hb, outacc);
     hb = wave_max_u64(hb);
     const int slot = part_slot<T>(a, s, c);
     if (slot >= 0) outacc = wave_sum(outacc);
@@ -320,31 +320,41 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
     const int wave = lin * 4 + (threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
-    tile_item<T, CPT>(a, wave);
+    tile_item<T, CPT, true>(a, wave);
 }
 
-// Persistent batch of independent members, one launch for many steps.  The
-// queue holds, step after step, for each member one clock entry and its tile
-// items.  Entries of step k of a member wait only until that member's step
-// k-1 is complete (its depth maximum and clock then exist), so members do not
-// wait for each other and no grid-wide barrier is needed.  Every entry that
-// is waited on was dequeued earlier by a running wave (the launch is
-// cooperative: all waves are resident), so the lowest unfinished entry can
-// always run.  A wait longer than spin_limit sleeps sets *error and exits.
+// Persistent batch of independent members, one launch for many steps.
+// Members are assigned to XCDs; a wave reads the id of the XCD it runs on and
+// serves only that XCD's queue, so every member's data stays in one L2 and the
+// hand-over between steps needs no L2 write-back: stores are complete in the
+// shared L2 when the writer's vector memory counter drains, and a consumer
+// drops its CU's L1 (agent-scope acquire) before reading.  The queue holds, step after step,
+// for each member one clock entry and its tile items.  Entries of step k of a
+// member wait only until that member's step k-1 is complete (its depth
+// maximum and clock then exist), so members do not wait for each other and no
+// grid-wide barrier is needed.  Every entry that is waited on was dequeued
+// earlier by a running wave of the same XCD (the launch is cooperative: all
+// waves are resident), so the lowest unfinished entry can always run.  A
+// wait longer than spin_limit sleeps sets *error and exits.
 template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
     const int lane = threadIdx.x & 63;
-    const unsigned long long total = (unsigned long long)B.per_step * (unsigned long long)B.nsteps;
+    const int x = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15);  // XCC_ID
+    if (x >= B.nxcc) return;
+    const int m_lo = B.xbegin[x], m_hi = B.xbegin[x + 1];
+    if (m_lo >= m_hi) return;
+    const int per_step = B.per_step[x];
+    const unsigned long long total = (unsigned long long)per_step * (unsigned long long)B.nsteps;
     for (;;) {
         unsigned long long q = 0;
-        if (lane == 0) q = atomicAdd(B.next, 1ull);
+        if (lane == 0) q = atomicAdd(&B.next[x], 1ull);
         // wave-uniform from here on: scalar registers, scalar loads of the arguments
         q = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(q >> 32)) << 32) |
             (unsigned)__builtin_amdgcn_readfirstlane((unsigned)q);
         if (q >= total) break;
-        const long long k = (long long)(q / (unsigned long long)B.per_step);
-        const int r = (int)(q - (unsigned long long)k * B.per_step);
-        int lo = 0, hi = B.nscen - 1;      // member with first <= r, largest such
+        const long long k = (long long)(q / (unsigned long long)per_step);
+        const int r = (int)(q - (unsigned long long)k * per_step);
+        int lo = m_lo, hi = m_hi - 1;      // member with first <= r, largest such
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (B.scen[mid].first <= r) lo = mid; else hi = mid - 1;
@@ -367,12 +377,16 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
                 if (lane == 0) atomicExch(B.error, 1);
                 break;
             }
-            __threadfence();
+            // acquire: drop this CU's L1 copies (and clean L2 lines of
+            // non-coherent memory) so the member's new data is read from L2
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         const StepArgs<T>& a = S.a[(int)((S.n0 + k) % 6)];
         if (e == 0) clock_wave<T>(a);
-        else tile_item<T, CPT>(a, e - 1);
-        __threadfence();
+        else tile_item<T, CPT, false>(a, e - 1);
+        // release within the XCD: this wave's stores have reached L2
+        __builtin_amdgcn_s_waitcnt(0);
+        __asm__ volatile("" ::: "memory");
         if (lane == 0) atomicAdd(&B.done[m], 1ull);
     }
 }

@@ -1239,17 +1239,39 @@ fl_status batch_check_members(fl_batch* b) {
 template <typename T>
 fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     const int S = (int)b->members.size();
-    std::vector<BatchScen<T>> scen(S);
-    int first = 0;
-    for (int k = 0; k < S; ++k) {
-        fl_ctx* c = b->members[b->order[k]];
-        const Tiling tl = tiling_of(c, b->cpt, b->rows);
-        for (int r = 0; r < 6; ++r) scen[k].a[r] = make_args<T>(c, r, tl, freeze);
-        scen[k].n0 = c->nstep;
-        scen[k].items = tl.nstrips * tl.nchunks;
-        scen[k].first = first;
-        first += 1 + scen[k].items;
+    // Bin-pack the members onto the XCDs (largest first onto the least loaded).
+    int nxcc = 1;
+    if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, b->device) != hipSuccess || nxcc < 1)
+        nxcc = 1;
+    nxcc = std::min(nxcc, kMaxXcc);
+    std::vector<std::vector<int>> bins(nxcc);
+    std::vector<long long> load(nxcc, 0);
+    for (int k = 0; k < S; ++k) {    // b->order is by decreasing cell count
+        const int m = b->order[k];
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[x].push_back(m);
+        load[x] += (long long)b->members[m]->nx * b->members[m]->ny;
     }
+    std::vector<BatchScen<T>> scen(S);
+    BatchArgs<T> ba{};
+    ba.nxcc = nxcc;
+    int idx = 0;
+    for (int x = 0; x < nxcc; ++x) {
+        ba.xbegin[x] = idx;
+        int first = 0;
+        for (int m : bins[x]) {
+            fl_ctx* c = b->members[m];
+            const Tiling tl = tiling_of(c, b->cpt, b->rows);
+            for (int r = 0; r < 6; ++r) scen[idx].a[r] = make_args<T>(c, r, tl, freeze);
+            scen[idx].n0 = c->nstep;
+            scen[idx].items = tl.nstrips * tl.nchunks;
+            scen[idx].first = first;
+            first += 1 + scen[idx].items;
+            ++idx;
+        }
+        ba.per_step[x] = first;
+    }
+    ba.xbegin[nxcc] = idx;
     const size_t bytes = sizeof(BatchScen<T>) * S;
     if (bytes > b->scen_bytes) {
         if (b->d_scen) (void)hipFree(b->d_scen);
@@ -1268,15 +1290,12 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     }
     for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
     BHIP_TRY(b, hipMemcpyAsync(b->d_scen, scen.data(), bytes, hipMemcpyHostToDevice, b->stream));
-    BHIP_TRY(b, hipMemsetAsync(b->d_sync, 0, sizeof(unsigned long long) * (S + 1), b->stream));
+    BHIP_TRY(b, hipMemsetAsync(b->d_sync, 0, sizeof(unsigned long long) * (S + kMaxXcc), b->stream));
     BHIP_TRY(b, hipMemsetAsync(b->d_error, 0, sizeof(int), b->stream));
-    BatchArgs<T> ba{};
     ba.scen = (const BatchScen<T>*)b->d_scen;
-    ba.nscen = S;
-    ba.per_step = first;
     ba.nsteps = nsteps;
     ba.next = b->d_sync;
-    ba.done = b->d_sync + 1;
+    ba.done = b->d_sync + kMaxXcc;
     ba.error = b->d_error;
     ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: only a broken co-residency could reach it
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1352,7 +1371,7 @@ fl_status fl_batch_create(fl_batch** out, int32_t nmembers, fl_ctx* const* membe
     b->rows = 16;
     hipError_t e = hipSetDevice(b->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_sync, sizeof(unsigned long long) * (nmembers + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_sync, sizeof(unsigned long long) * (nmembers + kMaxXcc));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_error, sizeof(int));
     if (e != hipSuccess) {
         g_create_error = std::string("fl_batch_create: ") + hipGetErrorString(e);
