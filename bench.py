@@ -83,6 +83,90 @@ def cpu_baseline(sc, budget_s: float = 20.0):
                       f"from the same initial state, {el:.1f} s wall on {cores} host threads"}
 
 
+# (cells per lane, rows per work item) tried by the autotuner on small grids
+SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
+
+
+def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20):
+    """64 valleys of uneven size (sides log-uniform in [256, 2048]) for `steps`
+    steps: one persistent batch launch vs the same members one after another."""
+    import synth
+    sizes = synth.ensemble_sizes(members)
+    scs = [synth.config_d4_member(s, side, steps) for s, side in enumerate(sizes)]
+    cells = sum(sc.nx * sc.ny for sc in scs)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctxs = [fl.from_scenario(sc, "f32", stream=stream) for sc in scs]
+    # one after another: each member's own step kernel (autotuned) with graph replays
+    seq_ms = 0.0
+    for f in ctxs:
+        f.autotune(SMALL_GRID_TILINGS, 10)
+        f.step(3)
+        seq_ms += f.time_steps(steps)
+    b = fl.Batch(ctxs)
+    cands = [(4, 8), (4, 16), (4, 32), (2, 16), (2, 32)]
+    best, _ = b.autotune(cands, trial_steps)
+    batch_ms = b.time(steps)
+    rep = [f.get_report() for f in ctxs]
+    b.close()
+    for f in ctxs:
+        f.close()
+    return {"members": members, "sides": [min(sizes), max(sizes)], "cells": cells, "steps": steps,
+            "tiling_autotuned": list(best),
+            "batch_gcell_s": round(cells * steps / (batch_ms / 1e3) / 1e9, 3),
+            "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
+            "batch_vs_sequential": round(seq_ms / batch_ms, 3),
+            "batch_hbm_frac": round(32 * cells * steps / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "max_budget_error": max(r.budget_error() for r in rep)}
+
+
+def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500,
+                obs_every: int = 50):
+    """1024^2 valley, fixed dt 0.25 s: gradient of the gauge misfit against a run
+    with perturbed roughness, forward + checkpointed backward, vs the plain step."""
+    import numpy as np
+    import synth
+    sc = synth.config_d5(nx, steps)
+    stream = torch.cuda.current_stream().cuda_stream
+    cells = sc.nx * sc.ny
+    # the plain step on the same grid
+    f = fl.from_scenario(sc, "f32", stream=stream)
+    best, _ = f.autotune(SMALL_GRID_TILINGS, 10)
+    f.step(6)
+    plain_ms = f.time_steps(steps)
+    f.close()
+    # truth run with n_true, gauges among its wet cells at the last step
+    truth = synth.Scenario(sc.name, sc.nx, sc.ny, sc.dx, sc.z, sc.extra["n_true"], sc.h0,
+                           sc.inflow, sc.outflow, dt_max=sc.dt_max, dt_fixed=sc.dt_fixed)
+    t = fl.from_scenario(truth, "f32", stream=stream)
+    t.step(steps)
+    h_end = t.get_depth()
+    t.close()
+    rng = np.random.default_rng(55)
+    gauges = rng.choice(np.nonzero(h_end.ravel() > 0.05)[0], ngauges, replace=False)
+    t = fl.from_scenario(truth, "f32", stream=stream)
+    t.adj_setup(gauges, obs_every)
+    obs, _ = t.adj_forward(steps)
+    t.close()
+    m = fl.from_scenario(sc, "f32", stream=stream)
+    m.autotune(SMALL_GRID_TILINGS, 10)
+    m.adj_setup(gauges, obs_every, obs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, loss = m.adj_forward(steps)
+    t1 = time.perf_counter()
+    gn, gq = m.adj_backward(None, len(sc.inflow[5]))
+    t2 = time.perf_counter()
+    m.close()
+    return {"grid": f"{nx}x{nx}", "steps": steps, "dt_s": sc.dt_fixed, "gauges": ngauges,
+            "observations": steps // obs_every, "checkpoints": int(np.ceil(steps / np.ceil(np.sqrt(steps)))),
+            "loss": loss, "grad_n_nonzero": int((gn != 0).sum()), "grad_q_norm": float(np.linalg.norm(gq)),
+            "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+            "adjoint_gcell_s": round(cells * steps / (t2 - t0) / 1e9, 3),
+            "plain_tiling_autotuned": list(best),
+            "plain_gcell_s": round(cells * steps / (plain_ms / 1e3) / 1e9, 3),
+            "adjoint_vs_plain": round((plain_ms / 1e3) / (t2 - t0), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +181,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--extra-wet", action="store_true",
                     help="also time the pre-wetted start of the same grid")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the batched-ensemble comparison (64 uneven grids)")
+    ap.add_argument("--ensemble-steps", type=int, default=5000)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint comparison (1024^2, 5000 steps)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="also run the plain streaming copy of this many GiB (roofline "
                          "calibration: practical ceiling and PMC scale)")
@@ -172,6 +261,10 @@ def main():
         extras["prewetted_hbm_frac"] = round(bpc * cells / (ev2 / args.steps / 1e3) / 1e9 /
                                              HBM_PEAK_GBS, 4)
         sc = scw
+    if not args.no_ensemble:
+        extras["ensemble"] = run_ensemble(fl, torch, args.ensemble_steps)
+    if not args.no_adjoint:
+        extras["adjoint"] = run_adjoint(fl, torch)
     if args.copy_probe_gib > 0:
         nbytes = int(args.copy_probe_gib * (1 << 30))
         extras["copy_probe_bytes"] = nbytes

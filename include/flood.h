@@ -205,6 +205,15 @@ fl_status fl_time_steps(fl_ctx *ctx, int64_t nsteps, double *elapsed_ms);
  * the default.  EINVAL: unsupported value. */
 fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_item);
 
+/* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
+ * trial_steps frozen steps (dt = 0: the state is streamed like a real step but
+ * left unchanged) and keep the fastest for the following steps (the captured
+ * graph is rebuilt).  best[2] receives it, *best_ms its time per step.  The
+ * state, clock and budget are unchanged.  ESTATE before commit; EINVAL: a
+ * candidate fl_set_tiling would reject. */
+fl_status fl_autotune(fl_ctx *ctx, const int32_t *candidates, int32_t ncand, int32_t trial_steps,
+                      int32_t *best, double *best_ms);
+
 /* Bytes of device memory the context holds after commit. */
 size_t fl_device_bytes(const fl_ctx *ctx);
 

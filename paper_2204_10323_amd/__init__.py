@@ -30,7 +30,7 @@ EXPORTS = [
     "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
     "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
-    "fl_adj_setup", "fl_adj_forward", "fl_adj_backward",
+    "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune",
 ]
 
 
@@ -112,6 +112,7 @@ def lib() -> C.CDLL:
             "fl_adj_setup": (C.c_int, [vp, C.POINTER(i32), i32, i32, vp, i64, C.c_int, i32]),
             "fl_adj_forward": (C.c_int, [vp, i64, vp, C.c_int, C.POINTER(dbl)]),
             "fl_adj_backward": (C.c_int, [vp, vp, C.POINTER(dbl), C.c_int, C.POINTER(dbl)]),
+            "fl_autotune": (C.c_int, [vp, C.POINTER(i32), i32, i32, C.POINTER(i32), C.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -225,6 +226,16 @@ class Flood:
 
     def commit(self):
         _check(self.ctx, lib().fl_commit(self.ctx))
+
+    def autotune(self, candidates, trial_steps: int = 10):
+        """Pick the fastest (cells_per_lane, rows_per_item) by frozen trial steps (fl_autotune)."""
+        flat = [int(v) for pair in candidates for v in pair]
+        arr = (C.c_int32 * len(flat))(*flat)
+        best = (C.c_int32 * 2)()
+        ms = C.c_double()
+        _check(self.ctx, lib().fl_autotune(self.ctx, arr, len(candidates), trial_steps, best,
+                                           C.byref(ms)))
+        return (best[0], best[1]), ms.value
 
     # -- stepping
     def step(self, nsteps: int):

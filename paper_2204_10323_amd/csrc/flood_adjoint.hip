@@ -272,17 +272,22 @@ __global__ void k_gauge_gather(const T* h, long long pitch, int nx, const int* g
     dst[g] = h[(long long)(j + kHalo) * pitch + i + kHalo];
 }
 
-// Adjoint seeds of one observation: dl[g], or 2 (series[g] - obs[g]).
-// One thread, in gauge order (a cell may carry several gauges).
+// Adjoint seeds of one observation: dl[g], or 2 (series[g] - obs[g]), added
+// to the depth adjoint of the gauge cells.  Gauges are grouped by cell
+// (cells[u] holds gauges list[ptr[u] .. ptr[u+1]) in gauge order), one thread
+// per cell, so the sum is the same in every run.
 template <typename T>
-__global__ void k_gauge_seed(T* lh, long long pitch, int nx, const int* gauges, int ng,
-                             const T* series, const T* obs, const T* dl) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int g = 0; g < ng; ++g) {
-        const int c = gauges[g], j = c / nx, i = c - j * nx;
-        const T s = dl ? dl[g] : T(2) * (series[g] - obs[g]);
-        lh[(long long)(j + kHalo) * pitch + i + kHalo] += s;
+__global__ void k_gauge_seed(T* lh, long long pitch, int nx, const int* cells, const int* ptr,
+                             const int* list, int nu, const T* series, const T* obs, const T* dl) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nu) return;
+    T s = T(0);
+    for (int k = ptr[u]; k < ptr[u + 1]; ++k) {
+        const int g = list[k];
+        s += dl ? dl[g] : T(2) * (series[g] - obs[g]);
     }
+    const int c = cells[u], j = c / nx, i = c - j * nx;
+    lh[(long long)(j + kHalo) * pitch + i + kHalo] += s;
 }
 
 template <typename T>
@@ -303,10 +308,11 @@ hipError_t launch_gauge_gather(const T* h, long long pitch, int nx, const int* g
 }
 
 template <typename T>
-hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* gauges, int ng,
-                             const T* series, const T* obs, const T* dl, hipStream_t s) {
-    hipLaunchKernelGGL((k_gauge_seed<T>), dim3(1), dim3(64), 0, s, lh, pitch, nx, gauges, ng, series,
-                       obs, dl);
+hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, const int* ptr,
+                             const int* list, int nu, const T* series, const T* obs, const T* dl,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((k_gauge_seed<T>), dim3((nu + 255) / 256), dim3(256), 0, s, lh, pitch, nx,
+                       cells, ptr, list, nu, series, obs, dl);
     return hipGetLastError();
 }
 
@@ -316,10 +322,11 @@ template hipError_t launch_gauge_gather<float>(const float*, long long, int, con
                                                hipStream_t);
 template hipError_t launch_gauge_gather<double>(const double*, long long, int, const int*, int,
                                                 double*, hipStream_t);
-template hipError_t launch_gauge_seed<float>(float*, long long, int, const int*, int, const float*,
-                                             const float*, const float*, hipStream_t);
-template hipError_t launch_gauge_seed<double>(double*, long long, int, const int*, int,
-                                              const double*, const double*, const double*,
-                                              hipStream_t);
+template hipError_t launch_gauge_seed<float>(float*, long long, int, const int*, const int*,
+                                             const int*, int, const float*, const float*,
+                                             const float*, hipStream_t);
+template hipError_t launch_gauge_seed<double>(double*, long long, int, const int*, const int*,
+                                              const int*, int, const double*, const double*,
+                                              const double*, hipStream_t);
 
 }  // namespace flood

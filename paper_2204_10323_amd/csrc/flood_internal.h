@@ -152,8 +152,9 @@ template <typename T>
 hipError_t launch_gauge_gather(const T* h, long long pitch, int nx, const int* gauges, int ng,
                                T* dst, hipStream_t s);
 template <typename T>
-hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* gauges, int ng,
-                             const T* series, const T* obs, const T* dl, hipStream_t s);
+hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, const int* ptr,
+                             const int* list, int nu, const T* series, const T* obs, const T* dl,
+                             hipStream_t s);
 
 int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
 constexpr int kVolumeParts = 1024;

@@ -71,6 +71,8 @@ struct fl_ctx {
     long long nobs_set = 0;
     std::vector<void*> adj_allocs;       // freed by a new setup, commit or destroy
     int* d_gauges = nullptr;
+    int* d_gcell = nullptr;              // gauges grouped by cell: cells, offsets, gauge indices
+    int ngcell = 0;
     void* d_obs = nullptr;
     void* d_series = nullptr;
     void* d_ck = nullptr;                // checkpoints: [nck][h, qx, qy fields]
@@ -134,7 +136,8 @@ void invalidate(fl_ctx* c) { c->committed = false; }
 void free_adjoint(fl_ctx* c) {
     for (void* p : c->adj_allocs) (void)hipFree(p);
     c->adj_allocs.clear();
-    c->d_gauges = nullptr;
+    c->d_gauges = c->d_gcell = nullptr;
+    c->ngcell = 0;
     c->d_obs = c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
     c->d_ck_ctl = nullptr;
     c->adj_setup = false;
@@ -744,6 +747,69 @@ fl_status fl_set_tiling(fl_ctx* c, int32_t cells_per_lane, int32_t rows_per_item
     return FL_OK;
 }
 
+fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32_t trial_steps,
+                      int32_t* best, double* best_ms) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_autotune before fl_commit");
+    if (!candidates || ncand < 1 || trial_steps < 1) return fail(c, FL_EINVAL, "fl_autotune: no candidates");
+    for (int k = 0; k < ncand; ++k) {
+        const int cp = candidates[2 * k], rw = candidates[2 * k + 1];
+        if ((cp != 1 && cp != 2 && cp != 4) || (c->prec == FL_F64 && cp == 4) || rw < 1)
+            return fail(c, FL_EINVAL, "fl_autotune: bad candidate");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    fl_status st;
+    Tiling cur{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+    if ((st = fold_budget(c, cur))) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    double bt = 1e300;
+    int bk = 0;
+    for (int k = 0; k < ncand; ++k) {
+        const Tiling t = tiling_of(c, candidates[2 * k], candidates[2 * k + 1]);
+        float ms = 0.f;
+        // frozen steps (dt = 0): the state is streamed like a real step but unchanged
+        for (int r = 0; r < 2 + trial_steps; ++r) {
+            if (r == 2) HIP_TRY(c, hipEventRecord(e0, c->stream));
+            hipError_t e = c->prec == FL_F64
+                               ? launch_step<double>(make_args<double>(c, c->nstep, t, 1), t.cpt, c->stream)
+                               : launch_step<float>(make_args<float>(c, c->nstep, t, 1), t.cpt, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "fl_autotune trial");
+            c->nstep += 1;
+        }
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        if ((st = fold_budget(c, t))) return st;
+        if (ms < bt) {
+            bt = ms;
+            bk = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->cpt = candidates[2 * bk];
+    c->rows = c->rows_req = candidates[2 * bk + 1];
+    const Tiling t = tiling_of(c, c->cpt, c->rows);
+    c->nstrips = t.nstrips;
+    c->nchunks = t.nchunks;
+    c->npart = t.npart;
+    // the captured multi-step graph holds the old decomposition
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    if ((st = capture_graph(c))) return st;
+    if (best) {
+        best[0] = c->cpt;
+        best[1] = c->rows;
+    }
+    if (best_ms) *best_ms = bt / trial_steps;
+    return FL_OK;
+}
+
 fl_status fl_commit(fl_ctx* c) {
     if (!c) return FL_EINVAL;
     fl_status st = do_commit(c);
@@ -982,7 +1048,9 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
             T* l1 = lamf[3 * cur];
             if ((k + 1) % c->obs_every == 0) {
                 const long long o = (k + 1) / c->obs_every - 1;
-                e = launch_gauge_seed<T>(l1, c->pitch, nx, c->d_gauges, ng, series + o * ng,
+                const int nu = c->ngcell;
+                e = launch_gauge_seed<T>(l1, c->pitch, nx, c->d_gcell, c->d_gcell + nu,
+                                         c->d_gcell + 2 * nu + 1, nu, series + o * ng,
                                          obs ? obs + o * ng : nullptr, dlT ? dlT + o * ng : nullptr,
                                          c->stream);
                 if (e != hipSuccess) break;
@@ -1065,7 +1133,8 @@ fl_status adj_forward_t(fl_ctx* c, long long N, void* series_out, int on_device,
     // release the record of an earlier forward run (keep gauges and observations)
     std::vector<void*> keep;
     for (void* p : c->adj_allocs)
-        if (p == c->d_gauges || p == c->d_obs) keep.push_back(p); else (void)hipFree(p);
+        if (p == c->d_gauges || p == c->d_gcell || p == c->d_obs) keep.push_back(p);
+        else (void)hipFree(p);
     c->adj_allocs = keep;
     c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
     c->d_ck_ctl = nullptr;
@@ -1160,6 +1229,27 @@ fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, i
     fl_status st;
     if ((st = adalloc(c, (void**)&c->d_gauges, sizeof(int) * ngauges))) return st;
     HIP_TRY(c, hipMemcpyAsync(c->d_gauges, gauge_cells, sizeof(int) * ngauges, hipMemcpyHostToDevice, c->stream));
+    {   // gauges grouped by cell, each group in gauge order
+        std::vector<int> idx(ngauges);
+        for (int k = 0; k < ngauges; ++k) idx[k] = k;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return gauge_cells[a] < gauge_cells[b]; });
+        std::vector<int> cells, ptr, list;
+        for (int k = 0; k < ngauges; ++k) {
+            if (k == 0 || gauge_cells[idx[k]] != gauge_cells[idx[k - 1]]) {
+                cells.push_back(gauge_cells[idx[k]]);
+                ptr.push_back(k);
+            }
+            list.push_back(idx[k]);
+        }
+        ptr.push_back(ngauges);
+        c->ngcell = (int)cells.size();
+        std::vector<int> packed(cells);
+        packed.insert(packed.end(), ptr.begin(), ptr.end());
+        packed.insert(packed.end(), list.begin(), list.end());
+        if ((st = adalloc(c, (void**)&c->d_gcell, sizeof(int) * packed.size()))) return st;
+        HIP_TRY(c, hipMemcpyAsync(c->d_gcell, packed.data(), sizeof(int) * packed.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    }
     c->nobs_set = 0;
     if (obs) {
         const size_t bytes = esz(c) * (size_t)nobs * ngauges;

@@ -217,3 +217,22 @@ def test_graph_replay_matches_single_launches(spg):
     r2 = f.get_report()
     f.close()
     assert np.array_equal(h1, h2) and r1.t == r2.t and r1.v_out == r2.v_out
+
+
+def test_autotune_keeps_results_bitwise():
+    """fl_autotune's frozen trial steps leave the state untouched, and the chosen
+    decomposition gives the same bits as the default one."""
+    sc = config_d1()
+    h1, qx1, qy1, r1 = run_gpu(sc, 500, "f32")
+    f = fl.from_scenario(sc, "f32")
+    f.step(123)
+    best, ms = f.autotune([(1, 4), (2, 8), (4, 16), (4, 32)], trial_steps=5)
+    assert best in ((1, 4), (2, 8), (4, 16), (4, 32)) and ms > 0
+    f.step(377)
+    h2 = f.get_depth()
+    qx2, qy2 = f.get_discharge()
+    r2 = f.get_report()
+    f.close()
+    assert np.array_equal(h1, h2) and np.array_equal(qx1, qx2) and np.array_equal(qy1, qy2)
+    assert r1.t == r2.t and r1.steps == r2.steps == 500
+    assert abs(r1.v_out - r2.v_out) <= 1e-12 * max(1.0, r1.v_out)
