@@ -161,6 +161,23 @@ fl_status fl_set_params(fl_ctx *ctx, const fl_params *p);
 fl_status fl_set_state(fl_ctx *ctx, const void *h, const void *qx, const void *qy, double t,
                        int on_device);
 
+/* Device memory for the buffers fl_commit allocates, for a caller that owns
+ * its memory (for example a PyTorch tensor):
+ * fl_workspace_bytes gives the bytes a grid needs (0 for invalid arguments);
+ * flags: FL_WS_TWO_STEP adds the buffers of fl_set_fusion(ctx, 2, ...).
+ * fl_bind_workspace makes the following commits carve their buffers from
+ * dev_ptr (256-byte aligned, on the context's device) instead of allocating;
+ * the caller keeps ownership and must keep the memory alive until fl_destroy,
+ * another bind or fl_init_grid (which unbinds).  NULL unbinds.  Binding
+ * frees the current device buffers, so a commit must follow.  Reverse mode
+ * (fl_adj_setup) still allocates its checkpoints itself.  ESTATE before
+ * fl_init_grid; EINVAL: misaligned or smaller than fl_workspace_bytes (flags
+ * 0); fl_commit returns EINVAL if the workspace is smaller than its flags
+ * need. */
+#define FL_WS_TWO_STEP 1u
+size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t flags);
+fl_status fl_bind_workspace(fl_ctx *ctx, void *dev_ptr, size_t bytes);
+
 /* Validate, allocate device memory, upload, reset clock and budget, capture
  * the multi-step graph.  Must follow fl_init_grid, fl_set_dem and
  * fl_set_manning (ESTATE otherwise).  Any fl_set_* after commit needs a new
@@ -183,6 +200,14 @@ fl_status fl_get_depth(fl_ctx *ctx, void *dst, int64_t row_stride, int on_device
 /* Copy the current discharges, border faces included (layout above). */
 fl_status fl_get_discharge(fl_ctx *ctx, void *qx, void *qy, int on_device);
 
+/* The whole state in the layout fl_set_state takes: depth h (ny x nx), qx
+ * (ny x (nx+1)) and qy ((ny+1) x nx) with the border faces, and the time t;
+ * any of them may be NULL (qx and qy together).  Host or device memory.
+ * Synchronises.  ENONFINITE if a depth became non-finite (the outputs are
+ * still filled).  Feeding the result to fl_set_state on a context with the
+ * same inputs continues the run bit for bit. */
+fl_status fl_get_state(fl_ctx *ctx, void *h, void *qx, void *qy, double *t, int on_device);
+
 /* Clock and volume budget.  Synchronises.  ENONFINITE if a depth became
  * non-finite (the report is still filled). */
 fl_status fl_get_report(fl_ctx *ctx, fl_report *r);
@@ -204,6 +229,21 @@ fl_status fl_time_steps(fl_ctx *ctx, int64_t nsteps, double *elapsed_ms);
  * and rows per work item (>= 1).  Takes effect at the next fl_commit. 0 keeps
  * the default.  EINVAL: unsupported value. */
 fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_item);
+
+/* Steps per launch of fl_step and fl_time_steps: 1 (default) or 2, and the
+ * tiling of the two-step kernel (0 = default: 2 cells per lane in FP32, 1 in
+ * FP64; rows as fl_set_tiling).  With 2, one launch reads the state once and
+ * makes two steps (Methods, eqs. 3-6, applied twice), halving the HBM traffic
+ * per step.  Under the CFL clock the second step's dt is taken as if the
+ * deepest cell of the intermediate state were shallow; the next launch checks
+ * it against that state's actual maximum and, if it differs, redoes both steps
+ * from the kept input.  Results are bitwise those of one step per launch.
+ * fl_step then synchronises the context's stream before it returns; a count
+ * of 1 still makes a single-step launch.  fl_advance, fl_autotune, reverse
+ * mode and batches use single-step launches.  Takes effect at the next
+ * fl_commit.  EINVAL: steps_per_launch not 1 or 2, an unsupported tiling. */
+fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per_lane,
+                        int32_t rows_per_item);
 
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
  * trial_steps frozen steps (dt = 0: the state is streamed like a real step but

@@ -30,7 +30,8 @@ EXPORTS = [
     "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
     "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
-    "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune",
+    "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
+    "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state",
 ]
 
 
@@ -113,6 +114,10 @@ def lib() -> C.CDLL:
             "fl_adj_forward": (C.c_int, [vp, i64, vp, C.c_int, C.POINTER(dbl)]),
             "fl_adj_backward": (C.c_int, [vp, vp, C.POINTER(dbl), C.c_int, C.POINTER(dbl)]),
             "fl_autotune": (C.c_int, [vp, C.POINTER(i32), i32, i32, C.POINTER(i32), C.POINTER(dbl)]),
+            "fl_set_fusion": (C.c_int, [vp, i32, i32, i32]),
+            "fl_workspace_bytes": (C.c_size_t, [i32, i32, C.c_int, C.c_uint32]),
+            "fl_bind_workspace": (C.c_int, [vp, vp, C.c_size_t]),
+            "fl_get_state": (C.c_int, [vp, vp, vp, vp, C.POINTER(dbl), C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -224,6 +229,11 @@ class Flood:
     def set_tiling(self, cells_per_lane: int = 0, rows_per_item: int = 0):
         _check(self.ctx, lib().fl_set_tiling(self.ctx, cells_per_lane, rows_per_item))
 
+    def set_fusion(self, steps_per_launch: int, cells_per_lane: int = 0, rows_per_item: int = 0):
+        """Steps per launch (1 or 2) and the two-step kernel's tiling (fl_set_fusion)."""
+        _check(self.ctx, lib().fl_set_fusion(self.ctx, steps_per_launch, cells_per_lane,
+                                             rows_per_item))
+
     def commit(self):
         _check(self.ctx, lib().fl_commit(self.ctx))
 
@@ -265,6 +275,31 @@ class Flood:
         _check(self.ctx, lib().fl_get_discharge(self.ctx, C.c_void_p(qx.ctypes.data),
                                                 C.c_void_p(qy.ctypes.data), 0))
         return qx, qy
+
+    def get_state(self):
+        """(h, qx, qy, t) in the layout set_state takes (fl_get_state)."""
+        h = np.empty((self.ny, self.nx), dtype=self.dtype)
+        qx = np.empty((self.ny, self.nx + 1), dtype=self.dtype)
+        qy = np.empty((self.ny + 1, self.nx), dtype=self.dtype)
+        t = C.c_double()
+        _check(self.ctx, lib().fl_get_state(self.ctx, C.c_void_p(h.ctypes.data),
+                                            C.c_void_p(qx.ctypes.data),
+                                            C.c_void_p(qy.ctypes.data), C.byref(t), 0))
+        return h, qx, qy, t.value
+
+    def workspace_bytes(self, two_step: bool = False) -> int:
+        return int(lib().fl_workspace_bytes(self.nx, self.ny, self.prec, 1 if two_step else 0))
+
+    def bind_workspace(self, buf):
+        """Carve the commit buffers from a caller-owned device tensor (kept
+        referenced here); None unbinds (fl_bind_workspace)."""
+        if buf is None:
+            _check(self.ctx, lib().fl_bind_workspace(self.ctx, None, 0))
+            self._ws = None
+            return
+        nbytes = buf.numel() * buf.element_size()
+        _check(self.ctx, lib().fl_bind_workspace(self.ctx, C.c_void_p(buf.data_ptr()), nbytes))
+        self._ws = buf
 
     def get_report(self, check: bool = True) -> fl_report:
         r = fl_report()
@@ -392,7 +427,8 @@ def copy_probe(nbytes: int, reps: int = 20, variant: int = 1, device: int = 0) -
 
 
 def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,
-                  cells_per_lane: int = 0, rows_per_item: int = 0, **param_over) -> Flood:
+                  cells_per_lane: int = 0, rows_per_item: int = 0, fusion=None,
+                  **param_over) -> Flood:
     """A committed context for a synthetic scenario (see the `synth` module)."""
     f = Flood(sc.nx, sc.ny, sc.dx, precision, device, stream)
     f.set_dem(sc.z)
@@ -411,6 +447,8 @@ def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, comm
         f.set_state(sc.h0, qx0, qy0, 0.0)
     if cells_per_lane or rows_per_item:
         f.set_tiling(cells_per_lane, rows_per_item)
+    if fusion is not None:
+        f.set_fusion(*((fusion,) if isinstance(fusion, int) else tuple(fusion)))
     if commit:
         f.commit()
     return f

@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/flood_kernels.hip", "csrc/flood_adjoint.hip", "csrc/flood_runtime.hip",
+SOURCES = ["csrc/flood_kernels.hip", "csrc/flood_fused.hip", "csrc/flood_adjoint.hip", "csrc/flood_runtime.hip",
            "csrc/hbm_probe.hip"]
 LIB = os.path.join(HERE, "libflood.so")
 

@@ -120,17 +120,6 @@ __device__ __forceinline__ T face_q(T etaL, T etaR, T zL, T zR, T nL, T nR, T q,
     return num / den;
 }
 
-// Border face value (eq. 5, 6), signed toward +axis.  Inflow magnitudes come
-// from the clock block's solve; outflow is the Manning discharge of the edge
-// cell's own depth; everything else is a closed wall.
-template <typename T>
-__device__ __forceinline__ T border_q(const StepArgs<T>& a, int side, int p, T h_edge) {
-    T v = T(0);
-    if (a.in_side == side) v = a.qin[p];
-    if (a.out_side == side) v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
-    return (side == SIDE_W || side == SIDE_S) ? v : -v;
-}
-
 // dt of this step from the clock slot and the deepest cell of the current
 // state: the fixed step, or min(dt_max, alpha dx / sqrt(g h_max)); shortened to
 // land on t_end; 0 once done or non-finite.  Rounded to T (the step uses it).
@@ -159,6 +148,23 @@ __device__ __forceinline__ double step_dt(const StepArgs<T>& a, const ClockSlot&
         last = 1;
     }
     return (double)(T)dt;
+}
+
+// The clock after a step of length dt (flags from step_dt) whose inflow faces
+// carried si in total (per unit width).  The outflow volume is added
+// separately, once the step's partial sums exist.
+__device__ __forceinline__ ClockSlot advance_clock(const ClockSlot& ck, double dt, int last,
+                                                   int done, int nonfin, double si, double dx,
+                                                   double t_end) {
+    ClockSlot nk = ck;
+    nk.t = last ? t_end : ck.t + dt;
+    nk.dt_prev = dt;
+    nk.last_dt = dt > 0.0 ? dt : ck.last_dt;
+    nk.v_in = ck.v_in + dt * dx * si;
+    nk.steps = ck.steps + (dt > 0.0 ? 1 : 0);
+    nk.done = (done || last) ? 1 : 0;
+    nk.nonfinite = nonfin ? 1 : 0;
+    return nk;
 }
 
 // Q_in(t): piecewise linear between samples, constant outside.

@@ -1,0 +1,489 @@
+// Two flood steps per launch (Methods, "Shallow Water Equations", eqs. 3-6).
+//
+// The single-step kernel reads the state once and writes it once per step,
+// so a step costs at least 32 bytes per cell of HBM traffic.  Here one wave
+// runs two row marchers on its strip: the second consumes the rows the first
+// one emits, still in registers, so two steps cost one read and one write of
+// the state.  A strip loads 64*CPT columns and outputs 64*CPT - 8 of them
+// (each step needs two halo columns on each side).
+//
+// The second step's dt depends on the deepest cell of the intermediate state,
+// a grid-wide maximum that exists only once the launch has ended.  The launch
+// therefore runs the second step with the dt it would have if that maximum
+// were small (the fixed dt, or dt_max, in both cases cut at t_end); the next
+// launch computes the true dt from the maximum the tiles recorded and, if
+// they differ, redoes both steps with the right dt from the launch's input,
+// which the ping-pong buffers still hold.  Either way every step uses exactly
+// the dt, inflow and arithmetic of the single-step kernel, so the two paths
+// give the same bits.  When the CFL bound is close to active the launch makes
+// one step only.
+//
+// Every wave derives the launch's plan from the device clock, so the number
+// of steps a launch makes is decided on the device; launches past the
+// requested count do nothing.
+#include <math.h>
+
+#include <algorithm>
+
+#include "flood_march.h"
+
+namespace flood {
+
+// What a launch does; every wave computes the same plan.
+struct Plan2 {
+    int mode;            // 0 nothing, 1 one step, 2 two steps, 3 redo the last launch's two steps
+    int in;              // buffer read; the launch writes buffer in ^ 1
+    int verified;        // the state claimed by the last launch holds
+    ClockSlot ck0;       // clock at the start of the first step
+    ClockSlot ck1;       // clock at the start of the second step (t and nonfinite; complete in mode 3)
+    double dt_a, dt_b;
+    int last_a, done_a, nonfin_a, last_b, done_b, nonfin_b;
+};
+
+// Whether to run a second step with a speculated dt: always with a fixed dt,
+// and with the CFL clock when the bound is well clear of dt_max (the deepest
+// cell may deepen by half within the step without making it active).
+template <typename T>
+__device__ __forceinline__ bool spec_room(const StepArgs<T>& a, unsigned long long hb) {
+    if (a.dt_fixed > 0.0) return true;
+    const double hm = Ord<T>::value(hb);
+    return !(hm > 0.0) || a.alpha * a.dx / sqrt(a.g * hm) >= 1.25 * a.dt_max;
+}
+
+template <typename T>
+__device__ Plan2 make_plan(const Step2Args<T>& A) {
+    const StepArgs<T>& a = A.a;
+    const DevCtl* ctl = a.ctl;
+    const Clock2& S = ctl->c2[A.phase & 1];
+    const int gp = (A.phase + 2) % 3;
+    const unsigned long long hmid = ctl->hm2[2 * gp], hend = ctl->hm2[2 * gp + 1];
+    const double t_end = ctl->t_end;
+    Plan2 P;
+    P.mode = 0;
+    P.verified = 1;
+    P.dt_a = P.dt_b = 0.0;
+    P.last_a = P.done_a = P.nonfin_a = P.last_b = P.done_b = P.nonfin_b = 0;
+    double dt_true = 0.0;
+    int lt = 0, dn = 0, nf = 0;
+    if (S.pending) {
+        dt_true = step_dt<T>(a, S.mid, hmid, t_end, lt, dn, nf);
+        P.verified = (dt_true == S.dt_b) ? 1 : 0;
+    }
+    if (!P.verified) {
+        P.mode = 3;
+        P.in = S.cur ^ 1;
+        P.ck0 = S.back;
+        P.ck1 = S.mid;
+        P.dt_a = S.dt_a;
+        P.dt_b = dt_true;
+        P.last_b = lt;
+        P.done_b = dn;
+        P.nonfin_b = nf;
+        return P;
+    }
+    P.in = S.cur;
+    P.ck0 = S.ck;
+    P.ck1 = S.ck;
+    const long long remaining = ctl->target2 - S.vsteps;
+    if (A.resolve || remaining <= 0) return P;
+    P.dt_a = step_dt<T>(a, S.ck, hend, t_end, P.last_a, P.done_a, P.nonfin_a);
+    P.ck1.t = P.last_a ? t_end : S.ck.t + P.dt_a;
+    P.ck1.nonfinite = P.nonfin_a ? 1 : 0;
+    if (remaining < 2 || !spec_room<T>(a, hend)) {
+        P.mode = 1;
+        return P;
+    }
+    P.mode = 2;
+    P.dt_b = step_dt<T>(a, P.ck1, 0ull, t_end, P.last_b, P.done_b, P.nonfin_b);
+    return P;
+}
+
+// Total inflow (per unit width) of a step starting at time t: eq. (6) solved
+// and summed exactly as the single-step clock sums the stored magnitudes.
+template <typename T>
+__device__ double inflow_sum(const StepArgs<T>& a, double t) {
+    const int lane = threadIdx.x & 63;
+    if (a.in_count <= 0) return 0.0;
+    const double Q = hydrograph<T>(a, t);
+    if (!(Q > 0.0)) return 0.0;
+    const double W = inflow_level(a.in_z, a.in_k, a.in_count, a.dx, Q);
+    double si = 0.0;
+    for (int p = lane; p < a.in_count; p += 64) si += (double)(T)(a.in_k[p] * pow53(W - a.in_z[p]));
+    return wave_sum(si);
+}
+
+template <typename T>
+__device__ double partial_sum(const double* part, int npart) {
+    const int lane = threadIdx.x & 63;
+    double so = 0.0;
+    for (int p = lane; p < npart; p += 64) so += part[p];
+    return wave_sum(so);
+}
+
+// The clock wave of a two-step launch: closes the outflow of the last launch
+// once its state is known to hold, advances the clock over this launch's
+// steps and publishes the next slot.
+template <typename T>
+__device__ void clock2_wave(const Step2Args<T>& A, const Plan2& P) {
+    const StepArgs<T>& a = A.a;
+    const int lane = threadIdx.x & 63;
+    DevCtl* ctl = a.ctl;
+    const Clock2 S = ctl->c2[A.phase & 1];
+    const int gp = (A.phase + 2) % 3, g = A.phase % 3, gn = (A.phase + 1) % 3;
+    const int pp = (A.phase + 1) & 1;  // parity of the last launch
+    const double t_end = ctl->t_end;
+    ClockSlot base = P.ck0;
+    if (P.verified && S.nclose >= 1) {
+        double so = partial_sum<T>(A.part_a[pp], a.npart);
+        base.v_out = base.v_out + S.dt_a * a.dx * so;
+        if (S.nclose == 2) {
+            so = partial_sum<T>(A.part_b[pp], a.npart);
+            base.v_out = base.v_out + S.dt_b * a.dx * so;
+        }
+    }
+    Clock2 N = S;
+    if (P.mode == 0) {
+        N.ck = base;
+        N.nclose = 0;
+        N.pending = 0;
+        if (lane == 0) {
+            ctl->hm2[2 * g] = ctl->hm2[2 * gp];
+            ctl->hm2[2 * g + 1] = ctl->hm2[2 * gp + 1];
+        }
+    } else {
+        ClockSlot c1;
+        if (P.mode == 3) {
+            c1 = S.mid;
+        } else {
+            const double si = inflow_sum<T>(a, base.t);
+            c1 = advance_clock(base, P.dt_a, P.last_a, P.done_a, P.nonfin_a, si, a.dx, t_end);
+        }
+        N.back = base;
+        N.mid = c1;
+        N.dt_a = P.dt_a;
+        N.cur = P.in ^ 1;
+        if (P.mode == 1) {
+            N.ck = c1;
+            N.dt_b = 0.0;
+            N.nclose = 1;
+            N.pending = 0;
+            N.vsteps = S.vsteps + 1;
+        } else {
+            const double si = inflow_sum<T>(a, c1.t);
+            N.ck = advance_clock(c1, P.dt_b, P.last_b, P.done_b, P.nonfin_b, si, a.dx, t_end);
+            N.dt_b = P.dt_b;
+            N.nclose = 2;
+            N.pending = (P.mode == 2) ? 1 : 0;
+            N.vsteps = S.vsteps + (P.mode == 2 ? 2 : 0);
+        }
+    }
+    if (lane == 0) {
+        ctl->hm2[2 * gn] = 0ull;
+        ctl->hm2[2 * gn + 1] = 0ull;
+        ctl->c2[(A.phase + 1) & 1] = N;
+    }
+}
+
+// Whether the waves of strip s, rows [j0, j1) meet an inflow face: those
+// solve eq. (6) themselves (the second step's time is not known before the
+// launch).
+template <typename T>
+__device__ __forceinline__ bool needs_inflow(const StepArgs<T>& a, int s, int j0, int j1, int wo,
+                                             int wl) {
+    if (a.in_side < 0 || a.in_count <= 0) return false;
+    const int f = a.in_first, e = a.in_first + a.in_count;
+    const int c0 = s * wo - kHalo;  // real column of the strip's first loaded cell
+    switch (a.in_side) {
+    case SIDE_W: return s == 0 && j0 - 4 < e && j1 + 4 > f;
+    case SIDE_E: return a.nx - 1 >= c0 && a.nx - 1 < c0 + wl && j0 - 4 < e && j1 + 4 > f;
+    case SIDE_S: return j0 <= 4 && c0 < e && c0 + wl > f;
+    default: return j1 + 3 >= a.ny && c0 < e && c0 + wl > f;
+    }
+}
+
+// One work item of a two-step (two = true) or one-step launch: strip s,
+// rows [j0, j1).  Row k enters marcher A; the row A emits (k - 2) enters
+// marcher B with the bed and roughness of that row; B emits row k - 4.
+// Values of A's emitted rows outside the grid are replaced by zeros, which is
+// what the single-step kernel reads from the halo there.
+template <typename T, int CPT>
+__device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
+                           const T* __restrict__ qx_in, const T* __restrict__ qy_in,
+                           T* __restrict__ h_out, T* __restrict__ qx_out, T* __restrict__ qy_out,
+                           const StepK<T>& KA, const StepK<T>& KB, bool two, int s, int j0, int j1,
+                           unsigned long long& hbA, unsigned long long& hbB, double& outA,
+                           double& outB) {
+    constexpr int WL = 64 * CPT;  // loaded columns
+    constexpr int WO = WL - 8;    // output columns (strip 0: two more on the left)
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx, ny = a.ny;
+    const long long P = a.pitch;
+    const int pcol = s * WO + lane * CPT;
+    const bool loads = pcol < nx + 2 * kHalo;
+    const StripGeo<CPT> G = strip_geo<CPT>(nx, s, WO, WL, lane);
+    const bool south_chunk = (j0 == 0);
+    const int lo = (s == 0) ? kHalo : 2 * kHalo;
+
+    bool store_col[CPT];
+    bool all_store = true, any_store = false;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int l = lane * CPT + m;
+        store_col[m] = (l >= lo && l < WL - 2 * kHalo && G.i0 + m < nx);
+        all_store = all_store && store_col[m];
+        any_store = any_store || store_col[m];
+    }
+
+    T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
+    auto load_row = [&](int k) {
+        if (loads && k >= -kHalo && k < ny + kHalo) {
+            const long long o = (long long)(k + kHalo) * P + pcol;
+            ldv<T, CPT>(h_in + o, hN);
+            ldv<T, CPT>(a.z + o, zN);
+            ldv<T, CPT>(a.n + o, nN);
+            ldv<T, CPT>(qx_in + o, qxN);
+            ldv<T, CPT>(qy_in + o, qyN);
+        } else {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
+        }
+    };
+    auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
+        const long long o = (long long)(r + kHalo) * P + pcol;
+        if (all_store) {
+            stv<T, CPT, true>(h_out + o, hv);
+            stv<T, CPT, true>(qx_out + o, qxv);
+            stv<T, CPT, true>(qy_out + o, qyv);
+        } else if (any_store) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (store_col[m]) {
+                    h_out[o + m] = hv[m];
+                    qx_out[o + m] = qxv[m];
+                    qy_out[o + m] = qyv[m];
+                }
+        }
+    };
+
+    Marcher<T, CPT> MA, MB;
+    MA.reset();
+    MB.reset();
+    T zd1[CPT], zd2[CPT], nd1[CPT], nd2[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) zd1[m] = zd2[m] = nd1[m] = nd2[m] = T(0);
+
+    const int kb = two ? j0 - 4 : j0 - 2;
+    const int ke = two ? j1 + 3 : j1 + 1;
+    load_row(kb);
+    for (int k = kb; k <= ke; ++k) {
+        T h0[CPT], z0[CPT], n0[CPT], qx0[CPT], qy0[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
+        }
+        if (k < ke) load_row(k + 1);
+        T hA[CPT], qxA[CPT], qyA[CPT];
+        MA.row(a, KA, G, k, h0, z0, n0, qx0, qy0, hA, qxA, qyA);
+        T zr[CPT], nr[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            zr[m] = zd2[m]; nr[m] = nd2[m];
+            zd2[m] = zd1[m]; nd2[m] = nd1[m];
+            zd1[m] = z0[m]; nd1[m] = n0[m];
+        }
+        const int ra = k - 2;
+        const bool a_item = (ra >= j0 && ra < j1);
+        if (!two) {
+            if (a_item) store_row(ra, hA, qxA, qyA);
+            row_books<T, CPT>(a, G, store_col, ra, a_item, south_chunk, hA, qxA, qyA, true, hbA,
+                              outA);
+            continue;
+        }
+        row_books<T, CPT>(a, G, store_col, ra, a_item, south_chunk, hA, qxA, qyA, false, hbA, outA);
+        if (ra < j0 - 2) continue;
+        const bool ra_real = (ra >= 0 && ra < ny);
+#pragma unroll
+        for (int m = 0; m < CPT; ++m)
+            if (!ra_real || G.outside[m]) hA[m] = qxA[m] = qyA[m] = T(0);
+        T hB[CPT], qxB[CPT], qyB[CPT];
+        MB.row(a, KB, G, ra, hA, zr, nr, qxA, qyA, hB, qxB, qyB);
+        const int rb = ra - 2;
+        const bool b_item = (rb >= j0 && rb < j1);
+        if (b_item) store_row(rb, hB, qxB, qyB);
+        row_books<T, CPT>(a, G, store_col, rb, b_item, south_chunk, hB, qxB, qyB, true, hbB, outB);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void step_consts(const StepArgs<T>& a, double dt, StepK<T>& K) {
+    K.dt = (T)dt;
+    K.gdt = T(a.g) * K.dt;
+    K.inv_dx = T(1) / T(a.dx);
+    K.h_eps = T(a.h_eps);
+    K.qin = nullptr;
+    K.W = 0.0;
+    K.inflow_on = 0;
+}
+
+template <typename T>
+__device__ __forceinline__ void inflow_consts(const StepArgs<T>& a, double t, StepK<T>& K) {
+    const double Q = hydrograph<T>(a, t);
+    if (Q > 0.0) {
+        K.W = inflow_level(a.in_z, a.in_k, a.in_count, a.dx, Q);
+        K.inflow_on = 1;
+    }
+}
+
+template <typename T, int CPT>
+__device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P, int item) {
+    const StepArgs<T>& a = A.a;
+    constexpr int WL = 64 * CPT, WO = WL - 8;
+    const int s = item % a.nstrips, c = item / a.nstrips;
+    const int j0 = c * a.rows, j1 = min(j0 + a.rows, a.ny);
+    const bool two = P.mode != 1;
+    StepK<T> KA, KB;
+    step_consts<T>(a, P.dt_a, KA);
+    step_consts<T>(a, P.dt_b, KB);
+    if (needs_inflow<T>(a, s, j0, j1, WO, WL)) {
+        inflow_consts<T>(a, P.ck0.t, KA);
+        if (two) inflow_consts<T>(a, P.ck1.t, KB);
+    }
+    const bool in1 = P.in != 0;
+    unsigned long long hbA = 0, hbB = 0;
+    double oA = 0.0, oB = 0.0;
+    step2_item<T, CPT>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0], in1 ? A.qy[1] : A.qy[0],
+                       in1 ? A.h[0] : A.h[1], in1 ? A.qx[0] : A.qx[1], in1 ? A.qy[0] : A.qy[1], KA,
+                       KB, two, s, j0, j1, hbA, hbB, oA, oB);
+    hbA = wave_max_u64(hbA);
+    if (two) hbB = wave_max_u64(hbB);
+    const int slot = part_slot<T>(a, s, c);
+    if (slot >= 0) {
+        oA = wave_sum(oA);
+        if (two) oB = wave_sum(oB);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* hm = a.ctl->hm2 + 2 * (A.phase % 3);
+        if (two) {
+            if (hbA) atomicMax(&hm[0], hbA);
+            if (hbB) atomicMax(&hm[1], hbB);
+        } else if (hbA) {
+            atomicMax(&hm[1], hbA);
+        }
+        if (slot >= 0) {
+            A.part_a[A.phase & 1][slot] = oA;
+            if (two) A.part_b[A.phase & 1][slot] = oB;
+        }
+    }
+}
+
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_step2(Step2Args<T> A) {
+    const Plan2 P = make_plan<T>(A);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) clock2_wave<T>(A, P);
+        return;
+    }
+    if (P.mode == 0) return;
+    // XCD-aware order, as in the single-step kernel: XCD x runs blocks
+    // b % 8 == x and gets one contiguous horizontal band of work items.
+    const int nblk = gridDim.x - 1, b = blockIdx.x - 1;
+    const int xcd = b & 7, q8 = nblk >> 3, r8 = nblk & 7;
+    const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int wave = lin * 4 + (threadIdx.x >> 6);
+    if (wave >= A.a.nstrips * A.a.nchunks) return;
+    tile2_item<T, CPT>(A, P, wave);
+}
+
+template <typename T>
+__global__ void k_enter2(StepArgs<T> a, int cur, long long target) {
+    if (threadIdx.x != 0) return;
+    DevCtl* ctl = a.ctl;
+    Clock2 S;
+    S.ck = ctl->clk[a.phase & 1];
+    S.back = S.ck;
+    S.mid = S.ck;
+    S.dt_a = S.dt_b = 0.0;
+    S.vsteps = 0;
+    S.cur = cur;
+    S.pending = 0;
+    S.nclose = 0;
+    S.pad = 0;
+    ctl->c2[0] = S;
+    for (int q = 0; q < 4; ++q) ctl->hm2[q] = 0ull;
+    ctl->hm2[4] = 0ull;
+    ctl->hm2[5] = ctl->hmax[a.phase % 3];
+    ctl->target2 = target;
+}
+
+template <typename T>
+__global__ void k_leave2(StepArgs<T> a, Step2Args<T> A, long long launches) {
+    const int lane = threadIdx.x & 63;
+    DevCtl* ctl = a.ctl;
+    const Clock2 S = ctl->c2[launches & 1];
+    const int pl = (int)((launches - 1) % 6);
+    ClockSlot ck = S.ck;
+    if (S.nclose >= 1) {
+        double so = partial_sum<T>(A.part_a[pl & 1], A.a.npart);
+        ck.v_out = ck.v_out + S.dt_a * a.dx * so;
+        if (S.nclose == 2) {
+            so = partial_sum<T>(A.part_b[pl & 1], A.a.npart);
+            ck.v_out = ck.v_out + S.dt_b * a.dx * so;
+        }
+    }
+    ck.dt_prev = 0.0;
+    inflow_solve<T>(a, hydrograph<T>(a, ck.t), const_cast<T*>(a.qin));
+    for (int q = lane; q < a.npart; q += 64) const_cast<double*>(a.part_prev)[q] = 0.0;
+    if (lane == 0) {
+        ctl->clk[a.phase & 1] = ck;
+        ctl->hmax[a.phase % 3] = ctl->hm2[2 * (pl % 3) + 1];
+        ctl->hmax[(a.phase + 1) % 3] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+int strip_width2(int cpt) { return 64 * cpt - 8; }
+
+template <typename T, int CPT>
+static hipError_t launch_step2_cpt(const Step2Args<T>& a, hipStream_t s) {
+    const long long items = (long long)a.a.nstrips * a.a.nchunks;
+    const unsigned blocks = (unsigned)(1 + (items + 3) / 4);
+    hipLaunchKernelGGL((k_step2<T, CPT>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step2(const Step2Args<T>& a, int cpt, hipStream_t s) {
+    switch (cpt) {
+    case 1: return launch_step2_cpt<T, 1>(a, s);
+    case 2: return launch_step2_cpt<T, 2>(a, s);
+    case 4: return sizeof(T) == 4 ? launch_step2_cpt<T, 4>(a, s) : hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_enter2(const StepArgs<T>& single, long long target, hipStream_t s) {
+    // the single-step state at counter n lives in buffer n % 2, i.e. the
+    // buffer of single.h_in; phase = n % 6
+    hipLaunchKernelGGL((k_enter2<T>), dim3(1), dim3(64), 0, s, single, single.phase & 1, target);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long long launches,
+                         hipStream_t s) {
+    if (launches < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_leave2<T>), dim3(1), dim3(64), 0, s, single, a2, launches);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step2<float>(const Step2Args<float>&, int, hipStream_t);
+template hipError_t launch_step2<double>(const Step2Args<double>&, int, hipStream_t);
+template hipError_t launch_enter2<float>(const StepArgs<float>&, long long, hipStream_t);
+template hipError_t launch_enter2<double>(const StepArgs<double>&, long long, hipStream_t);
+template hipError_t launch_leave2<float>(const StepArgs<float>&, const Step2Args<float>&, long long,
+                                         hipStream_t);
+template hipError_t launch_leave2<double>(const StepArgs<double>&, const Step2Args<double>&,
+                                          long long, hipStream_t);
+
+}  // namespace flood

@@ -25,12 +25,35 @@ struct ClockSlot {
     int nonfinite;     // a depth became NaN or infinite
 };
 
+// Clock of the two-step launches, one slot per launch parity.  A launch
+// claims the state it wrote.  When its second step ran with a speculated dt
+// (pending), the next launch compares that dt with the one the depth maximum
+// of the intermediate state gives; if they differ it redoes both steps from
+// the launch's input, which the ping-pong buffers still hold.
+struct Clock2 {
+    ClockSlot ck;       // clock of the claimed state; v_out without the last launch's outflow
+    ClockSlot back;     // clock at the start of the last launch (v_out complete)
+    ClockSlot mid;      // clock after the last launch's first step
+    double dt_a, dt_b;  // dt of its first and second step
+    long long vsteps;   // steps claimed since entering two-step mode (dt = 0 steps included)
+    int cur;            // buffer holding the claimed state
+    int pending;        // the second dt was speculated and is not checked yet
+    int nclose;         // steps of the last launch whose outflow is not in ck.v_out
+    int pad;
+};
+
 // Device control block of one context.
 struct DevCtl {
     ClockSlot clk[2];            // read clk[n % 2], written clk[(n + 1) % 2] by step n
     unsigned long long hmax[3];  // deepest cell as ordered bits: read [n%3], max into [(n+1)%3]
     double t_end;                // effective end time (host may lower it between launches)
     double report[8];            // filled by the flush kernel
+    // two-step launches: launch p reads c2[p % 2] and writes c2[(p + 1) % 2]; its
+    // tiles put the deepest cell of the intermediate and the final state into
+    // hm2[2 (p % 3)] and hm2[2 (p % 3) + 1]
+    Clock2 c2[2];
+    unsigned long long hm2[6];
+    long long target2;           // steps to claim before launches become no-ops
 };
 
 template <typename T>
@@ -64,6 +87,21 @@ struct StepArgs {
     int nstrips, nchunks, rows;   // tiling: strips along x, chunks of `rows` rows along y
     int phase;                    // step index modulo 6
     double dx, g, alpha, dt_max, h_eps, dt_fixed;
+};
+
+// A two-step launch: the grid, boundary data and constants (with the
+// two-step tiling) in `a`; both ping-pong buffers, since the launch decides
+// on the device which one holds its input.
+template <typename T>
+struct Step2Args {
+    StepArgs<T> a;
+    T* h[2];
+    T* qx[2];
+    T* qy[2];
+    double* part_a[2];  // outflow partial sums of the first and second step, by launch parity
+    double* part_b[2];
+    int phase;          // launch counter modulo 6
+    int resolve;        // 1: only check (and if needed redo) the last launch
 };
 
 // One member of a batch: its step arguments for each step counter modulo 6
@@ -156,7 +194,21 @@ hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
                              const int* list, int nu, const T* series, const T* obs, const T* dl,
                              hipStream_t s);
 
+// Two-step launches (flood_fused.hip).  enter: the single-step state at
+// step counter n (its budget folded) becomes slot 0 of the two-step clock,
+// with `target` steps to claim.  leave: the state claimed after `launches`
+// launches becomes the single-step state at counter n2 (buffer n2 % 2 must
+// hold it).
+template <typename T>
+hipError_t launch_step2(const Step2Args<T>& a, int cpt, hipStream_t s);
+template <typename T>
+hipError_t launch_enter2(const StepArgs<T>& single, long long target, hipStream_t s);
+template <typename T>
+hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long long launches,
+                         hipStream_t s);
+
 int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
+int strip_width2(int cpt);  // the same for the two-step kernel
 constexpr int kVolumeParts = 1024;
 
 }  // namespace flood

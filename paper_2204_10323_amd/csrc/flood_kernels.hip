@@ -19,7 +19,7 @@
 
 #include <algorithm>
 
-#include "flood_device.h"
+#include "flood_march.h"
 
 namespace flood {
 
@@ -44,15 +44,8 @@ __device__ void clock_wave(const StepArgs<T>& a) {
     for (int p = lane; p < a.in_count; p += 64) si += (double)a.qin[a.in_first + p];
     si = wave_sum(si);
 
-    ClockSlot nk = ck;
-    nk.t = last ? t_end : ck.t + dt;
-    nk.dt_prev = dt;
-    nk.last_dt = dt > 0.0 ? dt : ck.last_dt;
-    nk.v_in = ck.v_in + dt * a.dx * si;
+    ClockSlot nk = advance_clock(ck, dt, last, done, nonfin, si, a.dx, t_end);
     nk.v_out = ck.v_out + ck.dt_prev * a.dx * so;
-    nk.steps = ck.steps + (dt > 0.0 ? 1 : 0);
-    nk.done = (done || last) ? 1 : 0;
-    nk.nonfinite = nonfin ? 1 : 0;
 
     inflow_solve<T>(a, hydrograph<T>(a, nk.t), a.qin_next);
     if (lane == 0) {
@@ -72,33 +65,29 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
     const int nx = a.nx, ny = a.ny;
     const long long P = a.pitch;
     const int pcol = s * WO + lane * CPT;  // padded column of my first cell
-    const int i0 = pcol - kHalo;           // its real column
     const bool loads = pcol < nx + 2 * kHalo;
     const int j0 = c * a.rows;
     const int j1 = min(j0 + a.rows, ny);
-    const T inv_dx = T(1) / T(a.dx);
-    const T gdt = T(a.g) * dt;
-    const T h_eps = T(a.h_eps);
-    // Strips whose loaded columns include a border face apply its boundary
-    // condition (the east border can sit in the halo of the second-last strip).
-    const bool west_strip = (s == 0);
-    const bool east_strip = (nx - 1 >= s * WO - kHalo) && (nx - 1 < s * WO - kHalo + WL);
+    const StripGeo<CPT> G = strip_geo<CPT>(nx, s, WO, WL, lane);
     const bool south_chunk = (j0 == 0);
+    StepK<T> K;
+    K.dt = dt;
+    K.gdt = T(a.g) * dt;
+    K.inv_dx = T(1) / T(a.dx);
+    K.h_eps = T(a.h_eps);
+    K.qin = a.qin;
+    K.W = 0.0;
+    K.inflow_on = 0;
 
-    bool outside[CPT], west_face[CPT], east_face[CPT], store_col[CPT];
-    bool all_store = true;
+    bool store_col[CPT];
+    bool all_store = true, any_store = false;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-        const int i = i0 + m, l = lane * CPT + m;
-        outside[m] = (i < 0 || i >= nx);
-        west_face[m] = (i == -1);
-        east_face[m] = (i == nx - 1);
-        store_col[m] = (l >= kHalo && l < WL - kHalo && i < nx);
+        const int l = lane * CPT + m;
+        store_col[m] = (l >= kHalo && l < WL - kHalo && G.i0 + m < nx);
         all_store = all_store && store_col[m];
+        any_store = any_store || store_col[m];
     }
-    bool any_store = false;
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) any_store = any_store || store_col[m];
 
     T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
     auto load_row = [&](int k) {
@@ -115,16 +104,8 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
         }
     };
 
-    // Rolling window (row index relative to the row k just loaded).
-    T eta1[CPT], z1[CPT], n1[CPT], qy1[CPT], h1[CPT], h2[CPT];
-    T qsx1[CPT], qsy2[CPT], r2[CPT], qnx2[CPT], qny3[CPT];
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-        eta1[m] = z1[m] = n1[m] = qy1[m] = h1[m] = h2[m] = T(0);
-        qsx1[m] = qsy2[m] = qnx2[m] = qny3[m] = T(0);
-        r2[m] = T(1);
-    }
-
+    Marcher<T, CPT> M;
+    M.reset();
     load_row(j0 - 2);
     for (int k = j0 - 2; k <= j1 + 1; ++k) {
         T h0[CPT], z0[CPT], n0[CPT], qx0[CPT], qy0[CPT];
@@ -133,154 +114,29 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
             h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
         }
         if (k < j1 + 1) load_row(k + 1);
-        const bool row_real = (k >= 0 && k < ny);
+        T hn[CPT], qxo[CPT], qyo[CPT];
+        M.row(a, K, G, k, h0, z0, n0, qx0, qy0, hn, qxo, qyo);
 
-        // A: x-faces of row k (eq. 3), border faces from the boundary conditions.
-        T eta0[CPT], qsx0[CPT];
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) eta0[m] = h0[m] + z0[m];
-        const T etaRn = from_next(eta0[0]), zRn = from_next(z0[0]), nRn = from_next(n0[0]);
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const T eR = (m + 1 < CPT) ? eta0[(m + 1) % CPT] : etaRn;
-            const T zR = (m + 1 < CPT) ? z0[(m + 1) % CPT] : zRn;
-            const T nR = (m + 1 < CPT) ? n0[(m + 1) % CPT] : nRn;
-            qsx0[m] = face_q<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], gdt, inv_dx, h_eps);
-        }
-        if (west_strip) {
-            const T hRn = from_next(h0[0]);
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                if (west_face[m]) {
-                    const T hR = (m + 1 < CPT) ? h0[(m + 1) % CPT] : hRn;
-                    qsx0[m] = row_real ? border_q<T>(a, SIDE_W, k, hR) : T(0);
-                }
-        }
-        if (east_strip) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                if (east_face[m]) qsx0[m] = row_real ? border_q<T>(a, SIDE_E, k, h0[m]) : T(0);
-        }
-
-        // B: y-faces between rows k-1 and k.
-        T qsy1[CPT];
-#pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            qsy1[m] = face_q<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], gdt, inv_dx,
-                                h_eps);
-        if (k - 1 == -1) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                qsy1[m] = outside[m] ? T(0) : border_q<T>(a, SIDE_S, i0 + m, h0[m]);
-        } else if (k - 1 == ny - 1) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                qsy1[m] = outside[m] ? T(0) : border_q<T>(a, SIDE_N, i0 + m, h1[m]);
-        }
-
-        // C: donor scaling factor of row k-1.
-        const bool row1_real = (k - 1 >= 0 && k - 1 < ny);
-        const T qWn = from_prev(qsx1[CPT - 1]);
-        T r1[CPT];
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const T qW = (m > 0) ? qsx1[(m + CPT - 1) % CPT] : qWn;
-            T out = fmax(T(0), -qW);
-            out += fmax(T(0), qsx1[m]);
-            out += fmax(T(0), -qsy2[m]);
-            out += fmax(T(0), qsy1[m]);
-            const T O = (dt * out) * inv_dx;
-            const T hp = fmax(h1[m], T(0));
-            const T rr = (O > hp) ? hp / O : T(1);
-            r1[m] = (a.positivity && row1_real && !outside[m]) ? rr : T(1);
-        }
-
-        // D: applied discharges: x-faces of row k-1 and y-faces between rows k-2 and k-1.
-        const T rRn = from_next(r1[0]);
-        T qnx1[CPT], qny2[CPT];
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const T rR = (m + 1 < CPT) ? r1[(m + 1) % CPT] : rRn;
-            qnx1[m] = qsx1[m] * (qsx1[m] > T(0) ? r1[m] : rR);
-            qny2[m] = qsy2[m] * (qsy2[m] > T(0) ? r2[m] : r1[m]);
-        }
-
-        // E: depth of row k-2 (eq. 4) and the stores of the new state.
-        const T qnWn = from_prev(qnx2[CPT - 1]);
         const int ko = k - 2;
-        if (ko >= j0 && ko < j1) {
-            T hn[CPT];
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) {
-                const T qW = (m > 0) ? qnx2[(m + CPT - 1) % CPT] : qnWn;
-                hn[m] = h2[m] + (dt * ((qW - qnx2[m]) + (qny3[m] - qny2[m]))) * inv_dx;
-            }
+        const bool in_item = (ko >= j0 && ko < j1);
+        if (in_item) {
             const long long o = (long long)(ko + kHalo) * P + pcol;
             if (all_store) {
                 stv<T, CPT, NTS>(a.h_out + o, hn);
-                stv<T, CPT, NTS>(a.qx_out + o, qnx2);
-                stv<T, CPT, NTS>(a.qy_out + o, qny2);
+                stv<T, CPT, NTS>(a.qx_out + o, qxo);
+                stv<T, CPT, NTS>(a.qy_out + o, qyo);
             } else if (any_store) {
 #pragma unroll
                 for (int m = 0; m < CPT; ++m)
                     if (store_col[m]) {
                         a.h_out[o + m] = hn[m];
-                        a.qx_out[o + m] = qnx2[m];
-                        a.qy_out[o + m] = qny2[m];
+                        a.qx_out[o + m] = qxo[m];
+                        a.qy_out[o + m] = qyo[m];
                     }
             }
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                if (store_col[m]) {
-                    const unsigned long long b = Ord<T>::bits(hn[m]);
-                    hbits = b > hbits ? b : hbits;
-                }
-            if (west_strip) {
-#pragma unroll
-                for (int m = 0; m < CPT; ++m)
-                    if (west_face[m]) {
-                        a.edge_w[ko] = qnx2[m];
-                        if (a.out_side == SIDE_W && a.kout[ko] > T(0)) outacc -= (double)qnx2[m];
-                    }
-            }
-            if (east_strip && a.out_side == SIDE_E) {
-#pragma unroll
-                for (int m = 0; m < CPT; ++m)
-                    if (east_face[m] && store_col[m] && a.kout[ko] > T(0)) outacc += (double)qnx2[m];
-            }
-            if (ko == ny - 1 && a.out_side == SIDE_N) {
-#pragma unroll
-                for (int m = 0; m < CPT; ++m)
-                    if (store_col[m] && a.kout[i0 + m] > T(0)) outacc += (double)qny2[m];
-            }
-        } else if (ko == -1 && south_chunk) {
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                if (store_col[m]) {
-                    a.edge_s[i0 + m] = qny2[m];
-                    if (a.out_side == SIDE_S && a.kout[i0 + m] > T(0)) outacc -= (double)qny2[m];
-                }
         }
-
-#pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            h2[m] = h1[m]; h1[m] = h0[m];
-            eta1[m] = eta0[m]; z1[m] = z0[m]; n1[m] = n0[m]; qy1[m] = qy0[m];
-            qsx1[m] = qsx0[m]; qsy2[m] = qsy1[m]; r2[m] = r1[m];
-            qnx2[m] = qnx1[m]; qny3[m] = qny2[m];
-        }
-    }
-}
-
-// Outflow partial-sum slot of a work item, or -1 if it has no outflow face.
-template <typename T>
-__device__ __forceinline__ int part_slot(const StepArgs<T>& a, int s, int c) {
-    switch (a.out_side) {
-    case SIDE_W: return s == 0 ? c : -1;
-    case SIDE_E: return s == a.nstrips - 1 ? c : -1;
-    case SIDE_S: return c == 0 ? s : -1;
-    case SIDE_N: return c == a.nchunks - 1 ? s : -1;
-    default: return -1;
+        row_books<T, CPT>(a, G, store_col, ko, in_item, south_chunk, hn, qxo, qyo, true, hbits,
+                          outacc);
     }
 }
 

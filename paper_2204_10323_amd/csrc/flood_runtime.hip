@@ -58,11 +58,23 @@ struct fl_ctx {
     DevCtl* d_ctl = nullptr;
     std::vector<void*> allocs;
     size_t dev_bytes = 0;
+    // caller-owned device memory for the commit buffers (fl_bind_workspace)
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
     long long nstep = 0;  // steps enqueued since commit
     double v0 = 0.0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
+
+    // two-step launches (fl_set_fusion): requested and effective tiling,
+    // outflow partial sums of the first and second step by launch parity
+    int fuse = 1, cpt2_req = 0, rows2_req = 0;
+    int cpt2 = 0, rows2 = 0, nstrips2 = 0, nchunks2 = 0, npart2 = 0;
+    double* d_part2[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph2 = nullptr;
+    hipGraphExec_t graph2_exec = nullptr;
+    int graph2_k = 0;
 
     // reverse mode (fl_adj_*): settings, checkpoints and the forward's record
     bool adj_setup = false;
@@ -151,9 +163,16 @@ void free_device(fl_ctx* c) {
     c->graph_exec = nullptr;
     c->graph = nullptr;
     c->graph_k = 0;
+    if (c->graph2_exec) (void)hipGraphExecDestroy(c->graph2_exec);
+    if (c->graph2) (void)hipGraphDestroy(c->graph2);
+    c->graph2_exec = nullptr;
+    c->graph2 = nullptr;
+    c->graph2_k = 0;
+    for (auto& q : c->d_part2) q = nullptr;
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     c->dev_bytes = 0;
+    c->ws_used = 0;
     c->d_h[0] = c->d_h[1] = c->d_qx[0] = c->d_qx[1] = c->d_qy[0] = c->d_qy[1] = nullptr;
     c->d_z = c->d_n = c->d_edge_w = c->d_edge_s = c->d_kout = nullptr;
     c->d_qin[0] = c->d_qin[1] = nullptr;
@@ -163,16 +182,27 @@ void free_device(fl_ctx* c) {
     c->committed = false;
 }
 
+size_t ws_round(size_t bytes) { return (std::max<size_t>(bytes, 256) + 255) & ~size_t(255); }
+
 fl_status dalloc(fl_ctx* c, void** p, size_t bytes) {
-    bytes = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        return fail(c, e == hipErrorOutOfMemory ? FL_ENOMEM : FL_EHIP,
-                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    bytes = ws_round(bytes);
+    if (c->ws) {
+        if (c->ws_used + bytes > c->ws_bytes) {
+            *p = nullptr;
+            return fail(c, FL_ENOMEM, "bound workspace too small");
+        }
+        *p = c->ws + c->ws_used;
+        c->ws_used += bytes;
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return fail(c, e == hipErrorOutOfMemory ? FL_ENOMEM : FL_EHIP,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        c->allocs.push_back(*p);
+        c->dev_bytes += bytes;
     }
-    c->allocs.push_back(*p);
-    c->dev_bytes += bytes;
     return hipMemsetAsync(*p, 0, bytes, c->stream) == hipSuccess
                ? FL_OK
                : fail(c, FL_EHIP, "hipMemsetAsync failed");
@@ -266,6 +296,66 @@ hipError_t enqueue_one(fl_ctx* c, long long n, hipStream_t s) {
     return launch_step<float>(make_args<float>(c, n), c->cpt, s);
 }
 
+// Work decomposition of the two-step kernel: strip 0 outputs columns
+// [0, W + 2), strip s > 0 columns [s W + 2, (s + 1) W + 2), W = strip_width2.
+Tiling tiling2_of(const fl_ctx* c, int cpt, int rows) {
+    Tiling t{cpt, rows, 0, 0, 0};
+    const int w = strip_width2(cpt);
+    t.nstrips = std::max(1, (c->nx - 2 + w - 1) / w);
+    t.nchunks = (c->ny + rows - 1) / rows;
+    if (c->out_count > 0)
+        t.npart = (c->out_side == FL_WEST || c->out_side == FL_EAST) ? t.nchunks : t.nstrips;
+    return t;
+}
+
+template <typename T>
+Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve) {
+    Step2Args<T> A{};
+    const Tiling tl{c->cpt2, c->rows2, c->nstrips2, c->nchunks2, c->npart2};
+    A.a = make_args<T>(c, 0, tl, 0);
+    for (int p = 0; p < 2; ++p) {
+        A.h[p] = (T*)c->d_h[p];
+        A.qx[p] = (T*)c->d_qx[p];
+        A.qy[p] = (T*)c->d_qy[p];
+        A.part_a[p] = c->d_part2[p];
+        A.part_b[p] = c->d_part2[2 + p];
+    }
+    A.phase = (int)(launch % 6);
+    A.resolve = resolve;
+    return A;
+}
+
+hipError_t enqueue_two(fl_ctx* c, long long launch, int resolve, hipStream_t s) {
+    if (c->prec == FL_F64) return launch_step2<double>(make_args2<double>(c, launch, resolve), c->cpt2, s);
+    return launch_step2<float>(make_args2<float>(c, launch, resolve), c->cpt2, s);
+}
+
+// K two-step launches with launch counters 0 .. K-1 (K a multiple of 6, so
+// the graph can be replayed whenever the counter is a multiple of 6).
+fl_status capture_graph2(fl_ctx* c) {
+    int K = c->params.steps_per_graph > 0 ? c->params.steps_per_graph / 2 : 30;
+    K = std::max(6, ((K + 5) / 6) * 6);
+    hipStream_t cs;
+    HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_two(c, k, 0, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) {
+            e = hipGraphInstantiate(&c->graph2_exec, g, nullptr, nullptr, 0);
+            c->graph2 = g;
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture (two-step)");
+    c->graph2_k = K;
+    return FL_OK;
+}
+
 fl_status capture_graph(fl_ctx* c) {
     int K = c->params.steps_per_graph > 0 ? c->params.steps_per_graph : 60;
     K = ((K + 5) / 6) * 6;
@@ -315,6 +405,14 @@ int default_rows(int nx, int ny, int cpt) {
     return (int)std::max<long long>(8, std::min<long long>(32, r));
 }
 
+// Rows per work item of the two-step kernel: like the single-step kernel,
+// at least ~6000 waves on small grids.
+int default_rows2(int nx, int ny, int cpt) {
+    const long long strips = std::max(1, (nx - 2 + strip_width2(cpt) - 1) / strip_width2(cpt));
+    const long long r = (long long)ny * strips / 6144;
+    return (int)std::max<long long>(8, std::min<long long>(32, r));
+}
+
 // Fold the last step's outflow partial sums into the clock (see k_fold).
 fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
     if (c->prec == FL_F64)
@@ -322,6 +420,27 @@ fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
     else
         HIP_TRY(c, launch_fold<float>(make_args<float>(c, c->nstep, tl, 0), c->stream));
     return FL_OK;
+}
+
+// Bytes fl_commit takes for a grid: the same buffers, in the same order and
+// rounding, as do_commit allocates, with every size that depends on the
+// boundary data at its largest (sections up to the longest side, hydrographs
+// up to 4096 samples).
+size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step) {
+    const size_t es = elem_size(prec);
+    const long long align = 256 / (long long)es;
+    const long long pitch = ((nx + 8 + align - 1) / align) * align;
+    const size_t field = (size_t)pitch * (ny + 2 * kHalo) * es;
+    const size_t side = (size_t)std::max(nx, ny);
+    size_t b = 0;
+    b += 2 * (3 * ws_round(field) + ws_round(side * es) + ws_round(sizeof(double) * side));
+    b += 2 * ws_round(field);
+    b += ws_round((size_t)ny * es) + ws_round((size_t)nx * es) + ws_round(side * es);
+    b += 2 * ws_round(sizeof(double) * side);
+    b += 2 * ws_round(sizeof(double) * 4096);
+    b += ws_round(sizeof(double) * kVolumeParts) + ws_round(sizeof(double)) + ws_round(sizeof(DevCtl));
+    if (two_step) b += 4 * ws_round(sizeof(double) * side);
+    return b;
 }
 
 fl_status do_commit(fl_ctx* c) {
@@ -332,6 +451,8 @@ fl_status do_commit(fl_ctx* c) {
     free_device(c);
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
+    if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse == 2))
+        return fail(c, FL_EINVAL, "fl_commit: the bound workspace is smaller than fl_workspace_bytes");
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
     c->rows = c->rows_req ? c->rows_req : default_rows(nx, ny, c->cpt);
     const long long align = 256 / (long long)es;
@@ -439,6 +560,17 @@ fl_status do_commit(fl_ctx* c) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->v0 *= c->dx * c->dx;
     if ((st = capture_graph(c))) return st;
+    if (c->fuse == 2) {
+        c->cpt2 = c->cpt2_req ? c->cpt2_req : (c->prec == FL_F64 ? 1 : 2);
+        c->rows2 = c->rows2_req ? c->rows2_req : default_rows2(nx, ny, c->cpt2);
+        const Tiling t2 = tiling2_of(c, c->cpt2, c->rows2);
+        c->nstrips2 = t2.nstrips;
+        c->nchunks2 = t2.nchunks;
+        c->npart2 = t2.npart;
+        for (auto& q : c->d_part2)
+            if ((st = dalloc(c, (void**)&q, sizeof(double) * std::max(nx, ny)))) return st;
+        if ((st = capture_graph2(c))) return st;
+    }
     c->committed = true;
     return FL_OK;
 }
@@ -456,6 +588,58 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
         }
     }
     return FL_OK;
+}
+
+// nsteps steps by two-step launches.  The single-step state (budget folded)
+// becomes the two-step clock; about nsteps/2 launches follow, then one that
+// only settles the last launch's speculated dt (redoing it if needed); the
+// claimed count is read back, and further rounds run if redone or one-step
+// launches left steps over.  Finally the state becomes the single-step state
+// again, at a step counter whose parity names the buffer that holds it.
+template <typename T>
+fl_status fused_steps_t(fl_ctx* c, long long nsteps) {
+    fl_status st;
+    {
+        const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+        if ((st = fold_budget(c, tl))) return st;
+    }
+    HIP_TRY(c, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, c->stream));
+    long long lc = 0;
+    long long want = (nsteps + 1) / 2;
+    Clock2 slot{};
+    for (int round = 0;; ++round) {
+        while (want > 0) {
+            if (c->graph2_exec && lc % 6 == 0 && want >= c->graph2_k) {
+                HIP_TRY(c, hipGraphLaunch(c->graph2_exec, c->stream));
+                lc += c->graph2_k;
+                want -= c->graph2_k;
+            } else {
+                HIP_TRY(c, enqueue_two(c, lc, 0, c->stream));
+                lc += 1;
+                want -= 1;
+            }
+        }
+        HIP_TRY(c, enqueue_two(c, lc, 1, c->stream));
+        lc += 1;
+        HIP_TRY(c, hipMemcpyAsync(&slot, &c->d_ctl->c2[lc & 1], sizeof(slot), hipMemcpyDeviceToHost,
+                                  c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (slot.pending) return fail(c, FL_EHIP, "two-step launches: unsettled state");
+        if (slot.vsteps >= nsteps) break;
+        if (round >= 64) return fail(c, FL_EHIP, "two-step launches: no progress");
+        want = nsteps - slot.vsteps;  // enough even if every launch makes one step
+    }
+    long long n2 = c->nstep + nsteps;
+    n2 += (n2 ^ (long long)slot.cur) & 1;
+    HIP_TRY(c, launch_leave2<T>(make_args<T>(c, n2), make_args2<T>(c, 0, 0), lc, c->stream));
+    c->nstep = n2;
+    return FL_OK;
+}
+
+fl_status run_steps(fl_ctx* c, long long nsteps) {
+    if (c->fuse == 2 && nsteps >= 2)
+        return c->prec == FL_F64 ? fused_steps_t<double>(c, nsteps) : fused_steps_t<float>(c, nsteps);
+    return enqueue_steps(c, nsteps);
 }
 
 struct HostReport {
@@ -577,6 +761,31 @@ fl_status fl_init_grid(fl_ctx* c, int32_t nx, int32_t ny, double dx) {
     c->ts.clear();
     c->qs.clear();
     c->t0 = 0.0;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    return FL_OK;
+}
+
+size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t flags) {
+    if (nx < 1 || ny < 1 || (prec != FL_F32 && prec != FL_F64) || (flags & ~1u)) return 0;
+    if ((long long)nx + 8 > (1LL << 30) || (long long)ny + 8 > (1LL << 30)) return 0;
+    return workspace_bytes(nx, ny, prec, (flags & 1u) != 0);
+}
+
+fl_status fl_bind_workspace(fl_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return FL_EINVAL;
+    if (!c->have_grid) return fail(c, FL_ESTATE, "fl_bind_workspace before fl_init_grid");
+    if (dev_ptr) {
+        if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
+            return fail(c, FL_EINVAL, "fl_bind_workspace: pointer not 256-byte aligned");
+        if (bytes < workspace_bytes(c->nx, c->ny, c->prec, false))
+            return fail(c, FL_EINVAL, "fl_bind_workspace: smaller than fl_workspace_bytes");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_device(c);
+    c->ws = static_cast<unsigned char*>(dev_ptr);
+    c->ws_bytes = dev_ptr ? bytes : 0;
     return FL_OK;
 }
 
@@ -747,6 +956,23 @@ fl_status fl_set_tiling(fl_ctx* c, int32_t cells_per_lane, int32_t rows_per_item
     return FL_OK;
 }
 
+fl_status fl_set_fusion(fl_ctx* c, int32_t steps_per_launch, int32_t cells_per_lane,
+                        int32_t rows_per_item) {
+    if (!c) return FL_EINVAL;
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return fail(c, FL_EINVAL, "fl_set_fusion: steps_per_launch must be 1 or 2");
+    if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
+        return fail(c, FL_EINVAL, "fl_set_fusion: cells_per_lane must be 1, 2 or 4");
+    if (c->prec == FL_F64 && cells_per_lane == 4)
+        return fail(c, FL_EINVAL, "fl_set_fusion: FP64 supports 1 or 2 cells per lane");
+    if (rows_per_item < 0) return fail(c, FL_EINVAL, "fl_set_fusion: rows_per_item < 0");
+    c->fuse = steps_per_launch;
+    c->cpt2_req = cells_per_lane;
+    c->rows2_req = rows_per_item;
+    invalidate(c);
+    return FL_OK;
+}
+
 fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32_t trial_steps,
                       int32_t* best, double* best_ms) {
     if (!c) return FL_EINVAL;
@@ -822,7 +1048,7 @@ fl_status fl_step(fl_ctx* c, int64_t nsteps) {
     if (!c->committed) return fail(c, FL_ESTATE, "fl_step before fl_commit");
     if (nsteps < 0) return fail(c, FL_EINVAL, "fl_step: nsteps < 0");
     HIP_TRY(c, hipSetDevice(c->device));
-    return enqueue_steps(c, nsteps);
+    return run_steps(c, nsteps);
 }
 
 fl_status fl_time_steps(fl_ctx* c, int64_t nsteps, double* elapsed_ms) {
@@ -833,7 +1059,7 @@ fl_status fl_time_steps(fl_ctx* c, int64_t nsteps, double* elapsed_ms) {
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     HIP_TRY(c, hipEventRecord(e0, c->stream));
-    fl_status st = enqueue_steps(c, nsteps);
+    fl_status st = run_steps(c, nsteps);
     HIP_TRY(c, hipEventRecord(e1, c->stream));
     HIP_TRY(c, hipEventSynchronize(e1));
     float ms = 0.f;
@@ -918,6 +1144,20 @@ fl_status fl_get_report(fl_ctx* c, fl_report* r) {
     if (!c || !r) return FL_EINVAL;
     if (!c->committed) return fail(c, FL_ESTATE, "fl_get_report before fl_commit");
     return read_report(c, r, true);
+}
+
+fl_status fl_get_state(fl_ctx* c, void* h, void* qx, void* qy, double* t, int on_device) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_get_state before fl_commit");
+    if ((qx == nullptr) != (qy == nullptr))
+        return fail(c, FL_EINVAL, "fl_get_state: give both qx and qy, or neither");
+    fl_status st;
+    if (h && (st = fl_get_depth(c, h, c->nx, on_device))) return st;
+    if (qx && (st = fl_get_discharge(c, qx, qy, on_device))) return st;
+    fl_report r{};
+    st = read_report(c, &r, false);
+    if (t) *t = r.t;
+    return st;
 }
 
 size_t fl_device_bytes(const fl_ctx* c) { return c ? c->dev_bytes : 0; }

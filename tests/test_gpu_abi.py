@@ -236,3 +236,54 @@ def test_autotune_keeps_results_bitwise():
     assert np.array_equal(h1, h2) and np.array_equal(qx1, qx2) and np.array_equal(qy1, qy2)
     assert r1.t == r2.t and r1.steps == r2.steps == 500
     assert abs(r1.v_out - r2.v_out) <= 1e-12 * max(1.0, r1.v_out)
+
+
+def test_get_state_round_trip():
+    """fl_get_state gives what fl_set_state takes: a new context continues bit for bit."""
+    sc = config_d1()
+    h_ref, qx_ref, qy_ref, r_ref = run_gpu(sc, 250, "f32")
+    f = fl.from_scenario(sc, "f32")
+    f.step(97)
+    h, qx, qy, t = f.get_state()
+    f.close()
+    g = fl.from_scenario(sc, "f32", commit=False)
+    g.set_state(h, qx, qy, t)
+    g.commit()
+    g.step(153)
+    h2, qx2, qy2, t2 = g.get_state()
+    g.close()
+    assert np.array_equal(h2, h_ref) and np.array_equal(qx2, qx_ref) and np.array_equal(qy2, qy_ref)
+    assert t2 == r_ref.t
+
+
+@pytest.mark.parametrize("fusion", [1, 2])
+def test_bound_workspace(fusion):
+    """Commit buffers carved from a caller-owned tensor: nothing allocated by
+    the library, the same bits as library-owned memory."""
+    import torch
+    sc = config_d1()
+    ref = run_gpu(sc, 300, "f32")
+    f = fl.from_scenario(sc, "f32", commit=False, fusion=fusion)
+    L = fl.lib()
+    need = f.workspace_bytes(two_step=(fusion == 2))
+    assert need >= 8 * 32 * sc.nx * sc.ny // 8
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    if fusion == 2:
+        assert need > f.workspace_bytes(False)
+        f.bind_workspace(torch.empty(f.workspace_bytes(False), dtype=torch.uint8, device="cuda"))
+        assert L.fl_commit(f.ctx) == fl.FL_EINVAL           # too small for two-step buffers
+    else:
+        assert L.fl_bind_workspace(f.ctx, C.c_void_p(small.data_ptr()), need - 256) == fl.FL_EINVAL
+    assert L.fl_bind_workspace(f.ctx, C.c_void_p(small.data_ptr() + 4), need) == fl.FL_EINVAL
+    ws = torch.zeros(need, dtype=torch.uint8, device="cuda")
+    f.bind_workspace(ws)
+    f.commit()
+    assert f.device_bytes() == 0
+    f.step(300)
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    r = f.get_report()
+    f.close()
+    assert np.array_equal(h, ref[0]) and np.array_equal(qx, ref[1]) and np.array_equal(qy, ref[2])
+    assert r.t == ref[3].t
+    assert L.fl_workspace_bytes(0, 5, 0, 0) == 0 and L.fl_workspace_bytes(5, 5, 0, 2) == 0
