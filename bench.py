@@ -24,20 +24,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 BYTES_PER_CELL = {"f32": 32, "f64": 64}   # read h z n qx qy, write h qx qy
-KERNEL_SRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc", "flood_kernels.hip")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md")
+CSRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc")
+# the sources that make the step kernels' code
+KERNEL_SRCS = ["flood_device.h", "flood_march.h", "flood_kernels.hip", "flood_fused.hip"]
+# committed PMC summaries of the dominant kernel, by steps per launch
+PMC_SUMMARY = {1: os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md"),
+               2: os.path.join(ROOT, "profiles", "k_step2_valley16384_pmc.md")}
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SRCS:
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(cells: int):
-    """HBM bytes per step-kernel launch from the committed PMC summary, if it was
-    taken on the current kernel source; else None."""
+def measured_traffic(cells: int, fusion: int):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, if it was taken on the current kernel sources; else None."""
     try:
-        txt = open(PMC_SUMMARY).read()
-    except OSError:
+        txt = open(PMC_SUMMARY[fusion]).read()
+    except (OSError, KeyError):
         return None
     m = re.search(r"```json\s*(\{.*?\})\s*```", txt, re.S)
     if not m:
@@ -87,6 +94,11 @@ def cpu_baseline(sc, budget_s: float = 20.0):
 SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
 
 
+def progress(msg: str):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20):
     """64 valleys of uneven size (sides log-uniform in [256, 2048]) for `steps`
     steps: one persistent batch launch vs the same members one after another."""
@@ -102,6 +114,15 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
         f.autotune(SMALL_GRID_TILINGS, 10)
         f.step(3)
         seq_ms += f.time_steps(steps)
+    progress("ensemble: members one after another, one step per launch, done")
+    # one after another with two steps per launch
+    seq2_ms = 0.0
+    for sc in scs:
+        g = fl.from_scenario(sc, "f32", stream=stream, fusion=2)
+        g.step(3)
+        seq2_ms += g.time_steps(steps)
+        g.close()
+    progress("ensemble: members one after another, two steps per launch, done")
     b = fl.Batch(ctxs)
     cands = [(4, 8), (4, 16), (4, 32), (2, 16), (2, 32)]
     best, _ = b.autotune(cands, trial_steps)
@@ -115,6 +136,8 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
             "batch_gcell_s": round(cells * steps / (batch_ms / 1e3) / 1e9, 3),
             "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
             "batch_vs_sequential": round(seq_ms / batch_ms, 3),
+            "sequential_two_step_gcell_s": round(cells * steps / (seq2_ms / 1e3) / 1e9, 3),
+            "batch_vs_best_sequential": round(min(seq_ms, seq2_ms) / batch_ms, 3),
             "batch_hbm_frac": round(32 * cells * steps / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "max_budget_error": max(r.budget_error() for r in rep)}
 
@@ -133,6 +156,10 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
     best, _ = f.autotune(SMALL_GRID_TILINGS, 10)
     f.step(6)
     plain_ms = f.time_steps(steps)
+    f.close()
+    f = fl.from_scenario(sc, "f32", stream=stream, fusion=2)
+    f.step(6)
+    plain2_ms = f.time_steps(steps)
     f.close()
     # truth run with n_true, gauges among its wet cells at the last step
     truth = synth.Scenario(sc.name, sc.nx, sc.ny, sc.dx, sc.z, sc.extra["n_true"], sc.h0,
@@ -164,7 +191,9 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
             "adjoint_gcell_s": round(cells * steps / (t2 - t0) / 1e9, 3),
             "plain_tiling_autotuned": list(best),
             "plain_gcell_s": round(cells * steps / (plain_ms / 1e3) / 1e9, 3),
-            "adjoint_vs_plain": round((plain_ms / 1e3) / (t2 - t0), 4)}
+            "adjoint_vs_plain": round((plain_ms / 1e3) / (t2 - t0), 4),
+            "plain_two_step_gcell_s": round(cells * steps / (plain2_ms / 1e3) / 1e9, 3),
+            "adjoint_vs_best_plain": round((min(plain_ms, plain2_ms) / 1e3) / (t2 - t0), 4)}
 
 
 def main():
@@ -174,8 +203,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="valley16384")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--cells-per-lane", type=int, default=0)
+    ap.add_argument("--fusion", type=int, default=2, choices=[1, 2],
+                    help="time steps per launch (2: two-step kernel, the default)")
+    ap.add_argument("--cells-per-lane", type=int, default=0,
+                    help="tiling of the kernel in use (0: its default)")
     ap.add_argument("--rows-per-item", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the other steps-per-launch setting for comparison")
     ap.add_argument("--steps-per-graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -206,11 +240,13 @@ def main():
     t_gen = time.perf_counter() - t_gen
     cells = sc.nx * sc.ny
 
-    def run_timed(scn):
+    def run_timed(scn, fusion=args.fusion):
+        tiling = dict(cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item)
+        if fusion == 2:
+            tiling = dict(fusion=(2, args.cells_per_lane, args.rows_per_item))
         f = fl.from_scenario(scn, args.precision, device=0,
                              stream=torch.cuda.current_stream().cuda_stream,
-                             cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item,
-                             steps_per_graph=args.steps_per_graph)
+                             steps_per_graph=args.steps_per_graph, **tiling)
         f.step(args.warmup)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
@@ -222,12 +258,14 @@ def main():
         f.close()
         return ev_ms, wall, rep, dev_bytes
 
+    progress(f"inputs ready ({t_gen:.1f} s); timing {args.steps} steps")
     ev_ms, wall, rep, dev_bytes = run_timed(sc)
+    progress(f"timed: {ev_ms / args.steps:.4f} ms/step")
     ms_step = ev_ms / args.steps
     value = cells * args.steps / (ev_ms / 1e3) / 1e9
     bpc = BYTES_PER_CELL[args.precision]
     achieved = bpc * cells / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(cells) if args.precision == "f32" else None
+    traffic = measured_traffic(cells, args.fusion) if args.precision == "f32" else None
     out = {
         "metric": "Gcell-updates/s + % of HBM BW; batched & adjoint vs plain step, same GPU",
         "value": round(value, 3),
@@ -245,31 +283,47 @@ def main():
                    "cells": cells, "dt": "CFL alpha 0.7, device-side", "dt_max_s": sc.dt_max,
                    "inflow_cells": sc.inflow[2], "outflow": "east edge",
                    "steps_in_run": args.warmup + args.steps, "parallelism": "single GPU"},
+        # algorithmic bytes = 32 B (FP32) per cell-update x the cell-updates one
+        # launch makes (cells x steps per launch), over the launch's duration;
+        # traffic = HBM bytes per launch measured by PMC counters
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "steps_per_launch": args.fusion,
+                     "algorithmic_bytes_per_launch": bpc * cells * args.fusion,
+                     "launch_ms": round(ms_step * args.fusion, 5),
+                     # the bytes the launch actually moves, as a fraction of the peak
+                     "traffic_frac": (round(traffic / (ms_step * args.fusion / 1e3) / 1e9 /
+                                            HBM_PEAK_GBS, 4) if traffic else None)},
     }
     extras = {"wall_s_timed_region": round(wall, 4), "input_generation_s": round(t_gen, 1),
               "device_bytes": dev_bytes, "budget_error": rep.budget_error(),
               "sim_time_s": rep.t, "kernel_sha256_16": kernel_hash()}
+    other = 3 - args.fusion
+    if not args.no_compare:
+        ev1, _, rep1, _ = run_timed(sc, other)
+        extras[f"steps_per_launch_{other}_gcell_s"] = round(cells * args.steps / (ev1 / 1e3) / 1e9, 3)
+        extras[f"steps_per_launch_{other}_same_clock"] = (rep1.t == rep.t and rep1.steps == rep.steps)
     if args.extra_wet and args.workload == "valley16384":
         import synth
         del sc
         scw = synth.config_d3(16384, wet=True)
-        ev2, _, rep2, _ = run_timed(scw)
-        extras["prewetted_gcell_s"] = round(cells * args.steps / (ev2 / 1e3) / 1e9, 3)
-        extras["prewetted_hbm_frac"] = round(bpc * cells / (ev2 / args.steps / 1e3) / 1e9 /
-                                             HBM_PEAK_GBS, 4)
+        for fu in ((args.fusion,) if args.no_compare else (args.fusion, other)):
+            ev2, _, rep2, _ = run_timed(scw, fu)
+            extras[f"prewetted_steps_per_launch_{fu}_gcell_s"] = round(
+                cells * args.steps / (ev2 / 1e3) / 1e9, 3)
         sc = scw
     if not args.no_ensemble:
+        progress("ensemble")
         extras["ensemble"] = run_ensemble(fl, torch, args.ensemble_steps)
     if not args.no_adjoint:
+        progress("adjoint")
         extras["adjoint"] = run_adjoint(fl, torch)
     if args.copy_probe_gib > 0:
         nbytes = int(args.copy_probe_gib * (1 << 30))
         extras["copy_probe_bytes"] = nbytes
         extras["copy_probe_gbs"] = {v: round(fl.copy_probe(nbytes, 10, v), 1) for v in (1, 3)}
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         if args.extra_wet and args.workload == "valley16384":
             sc, _ = build_workload(args.workload)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)

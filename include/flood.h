@@ -118,7 +118,7 @@ void fl_default_params(fl_params *p);
 fl_status fl_create(fl_ctx **ctx, int device, void *hip_stream, fl_precision prec);
 
 /* Grid of nx x ny cells of side dx metres.  EINVAL: nx or ny < 1, dx <= 0 or
- * not finite, or more than 2^31 cells per row pitch.  Resets everything set
+ * not finite, nx + 264 > 2^28 or ny + 8 > 2^30.  Resets everything set
  * before (DEM, roughness, boundaries, state). */
 fl_status fl_init_grid(fl_ctx *ctx, int32_t nx, int32_t ny, double dx);
 

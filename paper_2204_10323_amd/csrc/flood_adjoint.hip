@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_adj_a(AdjArgs<T> a) {
     if (qs[1] > T(0)) rho += mu[1] * qs[1];
     if (qs[2] < T(0)) rho += mu[2] * qs[2];
     if (qs[3] > T(0)) rho += mu[3] * qs[3];
-    a.rr[o] = lim ? hp / O : T(1);
+    a.rr[o] = lim ? donor_ratio<T>(hp, O) : T(1);
     a.nu[o] = lim ? rho * (-hp / (O * O)) * dtdx : T(0);
     a.kap[o] = (lim && h > T(0)) ? rho / O : T(0);
 }

@@ -16,6 +16,12 @@ enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 // Ordered bits of a depth for the max-reduction: negative -> 0, NaN above +inf.
 template <typename T> struct Ord;
 template <> struct Ord<float> {
+    typedef unsigned U;  // the key in the working precision's width
+    static __device__ __forceinline__ U key(float h) {
+        if (h >= 0.0f) return __float_as_uint(h);
+        if (h < 0.0f) return 0u;
+        return 0x7fc00000u;
+    }
     static __device__ __forceinline__ unsigned long long bits(float h) {
         if (h >= 0.0f) return (unsigned long long)__float_as_uint(h);
         if (h < 0.0f) return 0ull;
@@ -27,6 +33,8 @@ template <> struct Ord<float> {
     static __device__ __forceinline__ bool nonfinite(unsigned long long b) { return b >= 0x7f800000ull; }
 };
 template <> struct Ord<double> {
+    typedef unsigned long long U;
+    static __device__ __forceinline__ U key(double h) { return bits(h); }
     static __device__ __forceinline__ unsigned long long bits(double h) {
         if (h >= 0.0) return (unsigned long long)__double_as_longlong(h);
         if (h < 0.0) return 0ull;
@@ -51,10 +59,24 @@ __device__ __forceinline__ T pow53(T x) {
     return x * (c * c);
 }
 
-template <typename T>
-__device__ __forceinline__ T from_next(T v) { return __shfl_down(v, 1, 64); }
-template <typename T>
-__device__ __forceinline__ T from_prev(T v) { return __shfl_up(v, 1, 64); }
+// Value held by the next (lane + 1) or previous (lane - 1) lane of the wave,
+// by the wave-wide DPP shifts of GFX9 (wave_shl:1, wave_shr:1): a register
+// move the ALU does in place, no LDS round trip.  The last (first) lane keeps
+// its own value.
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+__device__ __forceinline__ double from_next(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_next((int)(b & 0xffffffffll)), hi = dpp_next((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_prev(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_prev((int)(b & 0xffffffffll)), hi = dpp_prev((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -68,6 +90,17 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
+__device__ __forceinline__ unsigned wave_max_key(unsigned v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v);
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long v) {
+    return wave_max_u64(v);
+}
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
     for (int o = 32; o >= 1; o >>= 1) {
         unsigned lo = __shfl_xor((unsigned)(v & 0xffffffffull), o, 64);
@@ -76,6 +109,18 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
         v = w > v ? w : v;
     }
     return v;
+}
+
+// Element at byte offset boff (32-bit, per lane) from a row start that is the
+// same in every lane: the form the scalar-base + 32-bit-offset memory
+// instructions take, with no per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T* at_byte(T* row, unsigned boff) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(row) + boff);
+}
+template <typename T>
+__device__ __forceinline__ const T* at_byte(const T* row, unsigned boff) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
 }
 
 template <typename T, int N>
@@ -118,6 +163,33 @@ __device__ __forceinline__ T face_q(T etaL, T etaR, T zL, T zR, T nL, T nR, T q,
     T num = q - (gdt * hf) * grad;
     T den = T(1) + ((gdt * (nf * nf)) * fabs(q)) / ((hf * hf) * cbrt_t(hf));
     return num / den;
+}
+
+// FP32 face update: the same formula with h_f^(-7/3) = 2^(-(7/3) log2 h_f)
+// and the quotient by the hardware reciprocal (v_log_f32, v_exp_f32,
+// v_rcp_f32, about one ulp each) instead of cbrt and two correctly rounded
+// divisions, which roughly halves the face's ALU work.  FP64 keeps the
+// correctly rounded operations.
+template <>
+__device__ __forceinline__ float face_q<float>(float etaL, float etaR, float zL, float zR,
+                                               float nL, float nR, float q, float gdt,
+                                               float inv_dx, float h_eps) {
+    float hf = fmaxf(etaL, etaR) - fmaxf(zL, zR);
+    if (hf <= h_eps) return 0.0f;
+    float nf = 0.5f * (nL + nR);
+    float grad = (etaR - etaL) * inv_dx;
+    float num = q - (gdt * hf) * grad;
+    float m73 = __builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(hf));
+    float den = 1.0f + ((gdt * (nf * nf)) * fabsf(q)) * m73;
+    return num * __builtin_amdgcn_rcpf(den);
+}
+
+// Donor-cell factor r = h+/O of a cell whose outflow O exceeds its depth h+.
+template <typename T>
+__device__ __forceinline__ T donor_ratio(T hp, T O) { return hp / O; }
+template <>
+__device__ __forceinline__ float donor_ratio<float>(float hp, float O) {
+    return fminf(hp * __builtin_amdgcn_rcpf(O), 1.0f);
 }
 
 // dt of this step from the clock slot and the deepest cell of the current

@@ -211,7 +211,7 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
                            const T* __restrict__ qx_in, const T* __restrict__ qy_in,
                            T* __restrict__ h_out, T* __restrict__ qx_out, T* __restrict__ qy_out,
                            const StepK<T>& KA, const StepK<T>& KB, bool two, int s, int j0, int j1,
-                           unsigned long long& hbA, unsigned long long& hbB, double& outA,
+                           typename Ord<T>::U& hbA, typename Ord<T>::U& hbB, double& outA,
                            double& outB) {
     constexpr int WL = 64 * CPT;  // loaded columns
     constexpr int WO = WL - 8;    // output columns (strip 0: two more on the left)
@@ -219,6 +219,8 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     const int nx = a.nx, ny = a.ny;
     const long long P = a.pitch;
     const int pcol = s * WO + lane * CPT;
+    const unsigned ucol = (unsigned)pcol;  // lane offset from a row's start (row pointers are uniform)
+    const unsigned boff = ucol * (unsigned)sizeof(T);
     const bool loads = pcol < nx + 2 * kHalo;
     const StripGeo<CPT> G = strip_geo<CPT>(nx, s, WO, WL, lane);
     const bool south_chunk = (j0 == 0);
@@ -237,30 +239,33 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
     auto load_row = [&](int k) {
         if (loads && k >= -kHalo && k < ny + kHalo) {
-            const long long o = (long long)(k + kHalo) * P + pcol;
-            ldv<T, CPT>(h_in + o, hN);
-            ldv<T, CPT>(a.z + o, zN);
-            ldv<T, CPT>(a.n + o, nN);
-            ldv<T, CPT>(qx_in + o, qxN);
-            ldv<T, CPT>(qy_in + o, qyN);
+            const long long o = (long long)(k + kHalo) * P;
+            ldv<T, CPT>(at_byte(h_in + o, boff), hN);
+            ldv<T, CPT>(at_byte(a.z + o, boff), zN);
+            ldv<T, CPT>(at_byte(a.n + o, boff), nN);
+            ldv<T, CPT>(at_byte(qx_in + o, boff), qxN);
+            ldv<T, CPT>(at_byte(qy_in + o, boff), qyN);
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
         }
     };
     auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
-        const long long o = (long long)(r + kHalo) * P + pcol;
+        const long long o = (long long)(r + kHalo) * P;
+        T* const ho = h_out + o;
+        T* const qxr = qx_out + o;
+        T* const qyr = qy_out + o;
         if (all_store) {
-            stv<T, CPT, true>(h_out + o, hv);
-            stv<T, CPT, true>(qx_out + o, qxv);
-            stv<T, CPT, true>(qy_out + o, qyv);
+            stv<T, CPT, true>(at_byte(ho, boff), hv);
+            stv<T, CPT, true>(at_byte(qxr, boff), qxv);
+            stv<T, CPT, true>(at_byte(qyr, boff), qyv);
         } else if (any_store) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
                 if (store_col[m]) {
-                    h_out[o + m] = hv[m];
-                    qx_out[o + m] = qxv[m];
-                    qy_out[o + m] = qyv[m];
+                    ho[ucol + m] = hv[m];
+                    qxr[ucol + m] = qxv[m];
+                    qyr[ucol + m] = qyv[m];
                 }
         }
     };
@@ -340,7 +345,8 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
     constexpr int WL = 64 * CPT, WO = WL - 8;
     const int s = item % a.nstrips, c = item / a.nstrips;
     const int j0 = c * a.rows, j1 = min(j0 + a.rows, a.ny);
-    const bool two = P.mode != 1;
+    // the plan is the same in every lane; keep what steers control flow scalar
+    const bool two = __builtin_amdgcn_readfirstlane(P.mode) != 1;
     StepK<T> KA, KB;
     step_consts<T>(a, P.dt_a, KA);
     step_consts<T>(a, P.dt_b, KB);
@@ -348,14 +354,14 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
         inflow_consts<T>(a, P.ck0.t, KA);
         if (two) inflow_consts<T>(a, P.ck1.t, KB);
     }
-    const bool in1 = P.in != 0;
-    unsigned long long hbA = 0, hbB = 0;
+    const bool in1 = __builtin_amdgcn_readfirstlane(P.in) != 0;
+    typename Ord<T>::U hbA = 0, hbB = 0;
     double oA = 0.0, oB = 0.0;
     step2_item<T, CPT>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0], in1 ? A.qy[1] : A.qy[0],
                        in1 ? A.h[0] : A.h[1], in1 ? A.qx[0] : A.qx[1], in1 ? A.qy[0] : A.qy[1], KA,
                        KB, two, s, j0, j1, hbA, hbB, oA, oB);
-    hbA = wave_max_u64(hbA);
-    if (two) hbB = wave_max_u64(hbB);
+    hbA = wave_max_key(hbA);
+    if (two) hbB = wave_max_key(hbB);
     const int slot = part_slot<T>(a, s, c);
     if (slot >= 0) {
         oA = wave_sum(oA);
@@ -364,10 +370,10 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
     if ((threadIdx.x & 63) == 0) {
         unsigned long long* hm = a.ctl->hm2 + 2 * (A.phase % 3);
         if (two) {
-            if (hbA) atomicMax(&hm[0], hbA);
-            if (hbB) atomicMax(&hm[1], hbB);
+            if (hbA) atomicMax(&hm[0], (unsigned long long)hbA);
+            if (hbB) atomicMax(&hm[1], (unsigned long long)hbB);
         } else if (hbA) {
-            atomicMax(&hm[1], hbA);
+            atomicMax(&hm[1], (unsigned long long)hbA);
         }
         if (slot >= 0) {
             A.part_a[A.phase & 1][slot] = oA;
@@ -389,7 +395,9 @@ __global__ __launch_bounds__(256) void k_step2(Step2Args<T> A) {
     const int nblk = gridDim.x - 1, b = blockIdx.x - 1;
     const int xcd = b & 7, q8 = nblk >> 3, r8 = nblk & 7;
     const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
-    const int wave = lin * 4 + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: keep it (and everything
+    // derived from it: strip, rows, loop counter, border tests) scalar
+    const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= A.a.nstrips * A.a.nchunks) return;
     tile2_item<T, CPT>(A, P, wave);
 }

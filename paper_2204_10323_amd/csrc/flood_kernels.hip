@@ -57,7 +57,7 @@ __device__ void clock_wave(const StepArgs<T>& a) {
 // One work item: strip s (columns), chunk c (rows).  Accumulates the ordered
 // bits of the deepest new depth and the outflow discharge leaving the grid.
 template <typename T, int CPT, bool NTS>
-__device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned long long& hbits,
+__device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord<T>::U& hbits,
                           double& outacc) {
     constexpr int WL = 64 * CPT;  // loaded columns
     constexpr int WO = WL - 4;    // output columns
@@ -65,6 +65,8 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
     const int nx = a.nx, ny = a.ny;
     const long long P = a.pitch;
     const int pcol = s * WO + lane * CPT;  // padded column of my first cell
+    const unsigned ucol = (unsigned)pcol;  // lane offset from a row's start (row pointers are uniform)
+    const unsigned boff = ucol * (unsigned)sizeof(T);
     const bool loads = pcol < nx + 2 * kHalo;
     const int j0 = c * a.rows;
     const int j1 = min(j0 + a.rows, ny);
@@ -92,12 +94,12 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
     T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
     auto load_row = [&](int k) {
         if (loads) {
-            const long long o = (long long)(k + kHalo) * P + pcol;
-            ldv<T, CPT>(a.h_in + o, hN);
-            ldv<T, CPT>(a.z + o, zN);
-            ldv<T, CPT>(a.n + o, nN);
-            ldv<T, CPT>(a.qx_in + o, qxN);
-            ldv<T, CPT>(a.qy_in + o, qyN);
+            const long long o = (long long)(k + kHalo) * P;
+            ldv<T, CPT>(at_byte(a.h_in + o, boff), hN);
+            ldv<T, CPT>(at_byte(a.z + o, boff), zN);
+            ldv<T, CPT>(at_byte(a.n + o, boff), nN);
+            ldv<T, CPT>(at_byte(a.qx_in + o, boff), qxN);
+            ldv<T, CPT>(at_byte(a.qy_in + o, boff), qyN);
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
@@ -120,18 +122,20 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, unsigned lon
         const int ko = k - 2;
         const bool in_item = (ko >= j0 && ko < j1);
         if (in_item) {
-            const long long o = (long long)(ko + kHalo) * P + pcol;
+            T* const ho = a.h_out + (long long)(ko + kHalo) * P;
+            T* const qxr = a.qx_out + (long long)(ko + kHalo) * P;
+            T* const qyr = a.qy_out + (long long)(ko + kHalo) * P;
             if (all_store) {
-                stv<T, CPT, NTS>(a.h_out + o, hn);
-                stv<T, CPT, NTS>(a.qx_out + o, qxo);
-                stv<T, CPT, NTS>(a.qy_out + o, qyo);
+                stv<T, CPT, NTS>(at_byte(ho, boff), hn);
+                stv<T, CPT, NTS>(at_byte(qxr, boff), qxo);
+                stv<T, CPT, NTS>(at_byte(qyr, boff), qyo);
             } else if (any_store) {
 #pragma unroll
                 for (int m = 0; m < CPT; ++m)
                     if (store_col[m]) {
-                        a.h_out[o + m] = hn[m];
-                        a.qx_out[o + m] = qxo[m];
-                        a.qy_out[o + m] = qyo[m];
+                        ho[ucol + m] = hn[m];
+                        qxr[ucol + m] = qxo[m];
+                        qyr[ucol + m] = qyo[m];
                     }
             }
         }
@@ -148,14 +152,14 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     int last, done, nonfin;
     const double dt64 = step_dt<T>(a, ck, a.ctl->hmax[a.phase % 3], a.ctl->t_end, last, done, nonfin);
     const int s = item % a.nstrips, c = item / a.nstrips;
-    unsigned long long hb = 0;
+    typename Ord<T>::U hb = 0;
     double outacc = 0.0;
     step_item<T, CPT, NTS>(a, s, c, (T)dt64, hb, outacc);
-    hb = wave_max_u64(hb);
+    hb = wave_max_key(hb);
     const int slot = part_slot<T>(a, s, c);
     if (slot >= 0) outacc = wave_sum(outacc);
     if ((threadIdx.x & 63) == 0) {
-        if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], hb);
+        if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], (unsigned long long)hb);
         if (slot >= 0) a.part_cur[slot] = outacc;
     }
 }
@@ -174,7 +178,9 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     const int nblk = gridDim.x - 1, b = blockIdx.x - 1;
     const int xcd = b & 7, q8 = nblk >> 3, r8 = nblk & 7;
     const int lin = xcd * q8 + min(xcd, r8) + (b >> 3);
-    const int wave = lin * 4 + (threadIdx.x >> 6);
+    // the wave index is uniform across the wave: keep it (and everything
+    // derived from it: strip, rows, loop counter, border tests) scalar
+    const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
     tile_item<T, CPT, true>(a, wave);
 }

@@ -134,7 +134,7 @@ struct Marcher {
             out += fmax(T(0), qsy1[m]);
             const T O = (K.dt * out) * K.inv_dx;
             const T hp = fmax(h1[m], T(0));
-            const T rr = (O > hp) ? hp / O : T(1);
+            const T rr = (O > hp) ? donor_ratio<T>(hp, O) : T(1);
             r1[m] = (a.positivity && row1_real && !G.outside[m]) ? rr : T(1);
         }
 
@@ -194,14 +194,14 @@ __device__ __forceinline__ void row_books(const StepArgs<T>& a, const StripGeo<C
                                           const bool (&store_col)[CPT], int ko, bool in_item,
                                           bool south_chunk, const T (&hn)[CPT],
                                           const T (&qxo)[CPT], const T (&qyo)[CPT],
-                                          bool keep_edges, unsigned long long& hbits,
+                                          bool keep_edges, typename Ord<T>::U& hbits,
                                           double& outacc) {
     const int ny = a.ny;
     if (in_item) {
 #pragma unroll
         for (int m = 0; m < CPT; ++m)
             if (store_col[m]) {
-                const unsigned long long b = Ord<T>::bits(hn[m]);
+                const typename Ord<T>::U b = Ord<T>::key(hn[m]);
                 hbits = b > hbits ? b : hbits;
             }
         if (G.west_strip) {

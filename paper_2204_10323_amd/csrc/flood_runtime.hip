@@ -748,7 +748,9 @@ fl_status fl_init_grid(fl_ctx* c, int32_t nx, int32_t ny, double dx) {
     if (!c) return FL_EINVAL;
     if (nx < 1 || ny < 1) return fail(c, FL_EINVAL, "fl_init_grid: nx and ny must be >= 1");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(c, FL_EINVAL, "fl_init_grid: dx must be finite and > 0");
-    if ((long long)nx + 8 > (1LL << 30) || (long long)ny + 8 > (1LL << 30))
+    // a row's byte offsets must fit 31 bits (the kernels address a row's
+    // cells by 32-bit offsets from the row start)
+    if ((long long)nx + 8 + 256 > (1LL << 28) || (long long)ny + 8 > (1LL << 30))
         return fail(c, FL_EINVAL, "fl_init_grid: grid too large");
     invalidate(c);
     c->nx = nx;
@@ -768,7 +770,7 @@ fl_status fl_init_grid(fl_ctx* c, int32_t nx, int32_t ny, double dx) {
 
 size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t flags) {
     if (nx < 1 || ny < 1 || (prec != FL_F32 && prec != FL_F64) || (flags & ~1u)) return 0;
-    if ((long long)nx + 8 > (1LL << 30) || (long long)ny + 8 > (1LL << 30)) return 0;
+    if ((long long)nx + 8 + 256 > (1LL << 28) || (long long)ny + 8 > (1LL << 30)) return 0;
     return workspace_bytes(nx, ny, prec, (flags & 1u) != 0);
 }
 
