@@ -110,8 +110,18 @@ __device__ __forceinline__ FaceGeo face_geo(int f, long long o, long long P, int
 
 // Pass A: per cell, the donor factor r of the forward step, and the
 // limiter's adjoint terms nu = rho dr/dO dt/dx and kappa = rho dr/dh.
+// An extra block column runs the inflow pass of the step reversed just
+// before (its pass B is complete; pass A reads nothing that pass touches), so
+// it overlaps this pass instead of following the previous one.
+template <typename T>
+__device__ void adj_inflow(const AdjArgs<T>& a, double t);
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_a(AdjArgs<T> a) {
+    if (blockIdx.x == gridDim.x - 1) {
+        if (a.bc_prev && blockIdx.y == 0 && threadIdx.x < 64) adj_inflow<T>(a, a.t_prev);
+        return;
+    }
     const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
     if (i >= a.nx) return;
     const long long P = a.pitch, o = (long long)(j + kHalo) * P + i + kHalo;
@@ -225,16 +235,17 @@ __device__ __forceinline__ double hydro_weights(const double* ts, const double* 
     return qs[lo] + (qs[hi] - qs[lo]) * w;
 }
 
-// Inflow section (one wave): with G(W) = sum_c dx k_c (W - z_c)_+^{5/3} - Q = 0,
+// Inflow section of the step that started at time t (one wave; needs that
+// step's pass B complete): with G(W) = sum_c dx k_c (W - z_c)_+^{5/3} - Q = 0,
 // dW/dQ = 1/D and dW/dk_j = -dx (W - z_j)^{5/3} / D, D = sum_c dx k_c (5/3)(W - z_c)^{2/3}.
 template <typename T>
-__global__ void k_adj_bc(AdjArgs<T> a) {
+__device__ void adj_inflow(const AdjArgs<T>& a, double t) {
     const int lane = threadIdx.x & 63;
     const int nc = a.in_count;
     if (nc <= 0 || a.nsamp <= 0) return;
     int k0;
     double w;
-    const double Q = hydro_weights(a.ts, a.qs, a.nsamp, a.t, k0, w);
+    const double Q = hydro_weights(a.ts, a.qs, a.nsamp, t, k0, w);
     if (!(Q > 0.0)) return;
     const double W = inflow_level(a.in_z, a.in_k, nc, a.dx, Q);
     double D = 0.0, A = 0.0;
@@ -260,6 +271,12 @@ __global__ void k_adj_bc(AdjArgs<T> a) {
         const double dLdk = pow53(W - a.in_z[p]) * (a.ain[p] - a.dx * A / D);
         a.gn[(long long)cj * a.nx + ci] += dLdk * (-sqrt(a.in_slope) / (nc_ * nc_));
     }
+}
+
+// The inflow pass on its own (the last step of a sweep).
+template <typename T>
+__global__ void k_adj_bc(AdjArgs<T> a) {
+    adj_inflow<T>(a, a.t);
 }
 
 // Depth at the gauge cells (flat j*nx + i) into dst[0 .. ng).
@@ -293,8 +310,13 @@ __global__ void k_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s) {
     const dim3 grid((a.nx + 255) / 256, a.ny);
-    hipLaunchKernelGGL((k_adj_a<T>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_adj_a<T>), dim3(grid.x + 1, grid.y), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_adj_b<T>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_inflow(const AdjArgs<T>& a, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_bc<T>), dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
@@ -318,6 +340,8 @@ hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
 
 template hipError_t launch_adjoint_step<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_step<double>(const AdjArgs<double>&, hipStream_t);
+template hipError_t launch_adjoint_inflow<float>(const AdjArgs<float>&, hipStream_t);
+template hipError_t launch_adjoint_inflow<double>(const AdjArgs<double>&, hipStream_t);
 template hipError_t launch_gauge_gather<float>(const float*, long long, int, const int*, int, float*,
                                                hipStream_t);
 template hipError_t launch_gauge_gather<double>(const double*, long long, int, const int*, int,

@@ -164,6 +164,8 @@ struct AdjArgs {
     int positivity;
     double dx, g, dt, h_eps, in_slope, out_slope;
     double t;              // time at the start of the forward step
+    int bc_prev;           // 1: the inflow pass of the step reversed just before is still due
+    double t_prev;         // ... and that step's start time
 };
 
 // Host-side launchers (flood_kernels.hip, flood_adjoint.hip).
@@ -186,6 +188,8 @@ hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* pa
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_inflow(const AdjArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_gauge_gather(const T* h, long long pitch, int nx, const int* gauges, int ng,
                                T* dst, hipStream_t s);

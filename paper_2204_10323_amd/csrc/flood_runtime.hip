@@ -1339,8 +1339,12 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
             a.in_slope = c->in_slope;
             a.out_slope = c->out_slope;
             a.t = tseq[k];
+            // the inflow pass of step k+1 (reversed just before) runs inside pass A
+            a.bc_prev = (k + 1 < N) ? 1 : 0;
+            a.t_prev = (k + 1 < N) ? tseq[k + 1] : 0.0;
             e = launch_adjoint_step<T>(a, c->stream);
             cur = 1 - cur;
+            if (k == 0 && e == hipSuccess) e = launch_adjoint_inflow<T>(a, c->stream);
         }
     }
     if (e == hipSuccess) {
