@@ -1,0 +1,46 @@
+"""Host-side checks of the benchmark script and the discharge-sweep helper
+(no GPU needed): the one-GPU refusal, the profile summaries bench.py reads,
+and argument validation."""
+import json
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+@pytest.mark.parametrize("name", ["k_step2_valley16384_pmc.md", "k_step_valley16384_pmc.md"])
+def test_pmc_summaries_parse(name):
+    """The machine-readable block bench.py takes roofline.traffic from."""
+    txt = open(os.path.join(ROOT, "profiles", name)).read()
+    d = json.loads(re.search(r"```json\s*(\{.*?\})\s*```", txt, re.S).group(1))
+    for k in ("kernel", "steps_per_launch", "cells", "kernel_sha256_16", "hbm_bytes_per_launch",
+              "algorithmic_bytes_per_launch", "fetch_scale", "write_scale"):
+        assert k in d, k
+    assert abs(d["hbm_bytes_per_launch"] - d["hbm_read_bytes_per_launch"]
+               - d["hbm_write_bytes_per_launch"]) <= 2    # each rounded to whole bytes
+    assert d["algorithmic_bytes_per_launch"] == 32 * d["cells"] * d["steps_per_launch"]
+    # at least one pass over the state (20 B read, 12 B written per cell)
+    assert d["hbm_read_bytes_per_launch"] >= 20 * d["cells"]
+    assert d["hbm_write_bytes_per_launch"] >= 12 * d["cells"]
+
+
+def test_sweep_rejects_bad_arguments():
+    from paper_2204_10323_amd.sweep import discharge_sweep
+    z = np.zeros((4, 4), np.float32)
+    n = np.full((4, 4), 0.03, np.float32)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 0, 0.1)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 10, 0.0)
