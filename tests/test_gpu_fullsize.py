@@ -30,10 +30,13 @@ def d3_dry():
     return synth.config_d3(N, wet=False)
 
 
-def test_valley16384_dry_1000_steps_full_grid(d3_dry):
+@pytest.mark.parametrize("spl", [2, 1])
+def test_valley16384_dry_1000_steps_full_grid(d3_dry, spl):
+    """spl = 2 is the benchmark's launch configuration (two steps per launch,
+    default tiling); spl = 1 the single-step kernel."""
     sc = d3_dry
-    print("CASE fullsize dry 1000 steps", flush=True)
-    f = fl.from_scenario(sc, "f32")          # default launch configuration, as the benchmark
+    print(f"CASE fullsize dry 1000 steps, {spl} step(s) per launch", flush=True)
+    f = fl.from_scenario(sc, "f32", fusion=spl)
     f.step(1000)
     h = f.get_depth()
     qx, qy = f.get_discharge()
@@ -77,7 +80,7 @@ def test_valley16384_prewetted_two_steps_full_grid(d3_dry):
     wet = Scenario("d3wet", sc.nx, sc.ny, sc.dx, z, sc.n, h0, sc.inflow, sc.outflow,
                    dt_max=sc.dt_max)
     print("CASE fullsize prewetted 2 steps", flush=True)
-    f = fl.from_scenario(wet, "f32")
+    f = fl.from_scenario(wet, "f32", fusion=2)    # one two-step launch
     f.step(2)
     h = f.get_depth()
     qx, qy = f.get_discharge()
