@@ -14,25 +14,36 @@ import numpy as np
 
 from . import Batch, Flood
 
-# (cells per lane, rows per work item) the batch autotuner tries
-BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (2, 8), (2, 16), (2, 32), (1, 16)]
+# (cells per lane, rows per work item) the autotuners try: for the batch
+# launch, and for one member stepped alone
+BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32), (1, 16)]
+SINGLE_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
 
 
 def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tuple,
                     outflow_section: Optional[tuple], discharges: Sequence[float], steps: int,
                     dt: float, threshold: float = 0.1, precision: str = "f32", device: int = 0,
                     stream=None, h0: Optional[np.ndarray] = None, keep_depths: bool = False,
-                    tiling: Optional[tuple] = None, trial_steps: int = 10, **params) -> dict:
+                    tiling: Optional[tuple] = None, trial_steps: int = 10, mode: str = "auto",
+                    **params) -> dict:
     """Run one member per discharge (m^3/s) for `steps` steps of `dt` seconds.
 
     inflow_section: (side, first, count, slope); outflow_section: (side, first,
-    count, slope) or None (closed borders).  tiling: (cells_per_lane,
-    rows_per_item) of the batch launch, or None to let the batch autotuner
-    pick one over `trial_steps` frozen steps (which leave the state as it is).
+    count, slope) or None (closed borders).
+    mode: "batch" (all members in one persistent launch), "sequential" (one
+    member after another, each with its own graph-captured steps) or "auto":
+    time both over `trial_steps` frozen steps (which leave the state as it is),
+    each with its autotuned tiling, and run the faster.  With only a few
+    members per XCD the batch launch has too little independent work to hide
+    the wait between a member's steps.
+    tiling: (cells_per_lane, rows_per_item) of the batch launch (mode
+    "batch"), or None for the autotuner's choice.
     Returns per-member arrays: flooded cell count and area, deepest cell,
     inflow and outflow volume, relative volume-budget error, and the depths if
-    keep_depths; plus the launch time in milliseconds.
+    keep_depths; the mode used and its time in milliseconds.
     """
+    if mode not in ("auto", "batch", "sequential"):
+        raise ValueError("discharge_sweep: mode must be auto, batch or sequential")
     if steps < 1 or not (dt > 0.0):
         raise ValueError("discharge_sweep: steps >= 1 and dt > 0 are required")
     z = np.ascontiguousarray(z)
@@ -52,19 +63,35 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
             if h0 is not None:
                 f.set_state(h0, None, None, 0.0)
             f.commit()
-        b = Batch(members)
-        try:
-            if tiling is not None:
-                b.set_tiling(*tiling)
-            else:
-                fp64 = precision in ("f64", "fp64", "double")
-                cands = [t for t in BATCH_TILINGS if not fp64 or t[0] < 4]
-                b.autotune(cands, trial_steps)
-            ms = b.time(steps)
-        finally:
-            b.close()
+        fp64 = precision in ("f64", "fp64", "double")
+        single_cands = [t for t in SINGLE_TILINGS if not fp64 or t[0] < 4]
+        ms = 0.0
+        if mode == "sequential":
+            best, _ = members[0].autotune(single_cands, trial_steps)
+        else:
+            b = Batch(members)
+            try:
+                if tiling is not None:
+                    b.set_tiling(*tiling)
+                    mode = "batch"
+                else:
+                    cands = [t for t in BATCH_TILINGS if not fp64 or t[0] < 4]
+                    _, batch_trial = b.autotune(cands, trial_steps)
+                    if mode == "auto":
+                        # members share the grid: one member's tuned step, times their number
+                        best, one = members[0].autotune(single_cands, trial_steps)
+                        mode = "sequential" if one * len(members) < batch_trial else "batch"
+                if mode == "batch":
+                    ms = b.time(steps)
+            finally:
+                b.close()
+        if mode == "sequential":
+            for f in members[1:]:
+                f.set_tiling(*best)
+                f.commit()
+            ms = sum(f.time_steps(steps) for f in members)
         out = {"discharge": np.asarray(discharges, dtype=np.float64), "steps": steps, "dt": dt,
-               "seconds": steps * dt, "threshold": threshold, "batch_ms": ms,
+               "seconds": steps * dt, "threshold": threshold, "mode": mode, "ms": ms,
                "flooded_cells": [], "flooded_area_m2": [], "max_depth": [], "v_in": [],
                "v_out": [], "budget_error": []}
         if keep_depths:

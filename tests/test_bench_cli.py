@@ -44,3 +44,5 @@ def test_sweep_rejects_bad_arguments():
         discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 0, 0.1)
     with pytest.raises(ValueError):
         discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 10, 0.0)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 10, 0.1, mode="fastest")

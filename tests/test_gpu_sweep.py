@@ -41,7 +41,7 @@ def test_sweep_against_oracle(prec):
     print(f"CASE discharge sweep {prec}", flush=True)
     out = discharge_sweep(z, n, v.dx, inflow, outflow, Q, STEPS, DT, threshold=THR,
                           precision=prec, keep_depths=True)
-    assert out["seconds"] == STEPS * DT and out["batch_ms"] > 0
+    assert out["seconds"] == STEPS * DT and out["ms"] > 0 and out["mode"] in ("batch", "sequential")
     ext_o = []
     for k, q in enumerate(Q):
         o = _oracle_member(v, z, n, inflow, outflow, q)
@@ -80,3 +80,16 @@ def test_sweep_members_equal_single_runs():
         h = f.get_depth()
         f.close()
         assert np.array_equal(h, out["depth"][k])
+
+
+def test_sweep_modes_agree():
+    """Batched and one-after-another members give the same bits."""
+    v, z, n, inflow, outflow = _valley()
+    qs = [15.0, 150.0, 600.0]
+    b = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True, mode="batch")
+    s = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True,
+                        mode="sequential")
+    assert b["mode"] == "batch" and s["mode"] == "sequential"
+    for hb, hs in zip(b["depth"], s["depth"]):
+        assert np.array_equal(hb, hs)
+    assert np.array_equal(b["v_in"], s["v_in"])
