@@ -254,6 +254,18 @@ fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per
 fl_status fl_autotune(fl_ctx *ctx, const int32_t *candidates, int32_t ncand, int32_t trial_steps,
                       int32_t *best, double *best_ms);
 
+/* Time one step per launch (the current tiling) against two steps per launch
+ * (the current two-step tiling) over trial_steps frozen steps each (dt = 0:
+ * the state is streamed but left as it is), and keep the faster for the
+ * following fl_step calls; both give the same bits.  Two steps per launch pay
+ * off on large grids that HBM bandwidth bounds; wet or cache-resident grids
+ * can be faster with one.  *steps_per_launch receives the choice (1 or 2),
+ * *ms_per_step its time per step.  ESTATE: not committed, or committed
+ * without fl_set_fusion(ctx, 2, ...) (the two-step buffers).  EINVAL:
+ * trial_steps < 2. */
+fl_status fl_autotune_fusion(fl_ctx *ctx, int32_t trial_steps, int32_t *steps_per_launch,
+                             double *ms_per_step);
+
 /* Bytes of device memory the context holds after commit. */
 size_t fl_device_bytes(const fl_ctx *ctx);
 

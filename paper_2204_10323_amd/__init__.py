@@ -31,7 +31,7 @@ EXPORTS = [
     "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
-    "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state",
+    "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state", "fl_autotune_fusion",
 ]
 
 
@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
             "fl_workspace_bytes": (C.c_size_t, [i32, i32, C.c_int, C.c_uint32]),
             "fl_bind_workspace": (C.c_int, [vp, vp, C.c_size_t]),
             "fl_get_state": (C.c_int, [vp, vp, vp, vp, C.POINTER(dbl), C.c_int]),
+            "fl_autotune_fusion": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(dbl)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -246,6 +247,15 @@ class Flood:
         _check(self.ctx, lib().fl_autotune(self.ctx, arr, len(candidates), trial_steps, best,
                                            C.byref(ms)))
         return (best[0], best[1]), ms.value
+
+    def autotune_fusion(self, trial_steps: int = 20):
+        """Keep one or two steps per launch, whichever frozen trials find faster
+        (fl_autotune_fusion); needs a commit after set_fusion(2)."""
+        spl = C.c_int32()
+        ms = C.c_double()
+        _check(self.ctx, lib().fl_autotune_fusion(self.ctx, int(trial_steps), C.byref(spl),
+                                                  C.byref(ms)))
+        return spl.value, ms.value
 
     # -- stepping
     def step(self, nsteps: int):

@@ -309,10 +309,10 @@ Tiling tiling2_of(const fl_ctx* c, int cpt, int rows) {
 }
 
 template <typename T>
-Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve) {
+Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve, int freeze = 0) {
     Step2Args<T> A{};
     const Tiling tl{c->cpt2, c->rows2, c->nstrips2, c->nchunks2, c->npart2};
-    A.a = make_args<T>(c, 0, tl, 0);
+    A.a = make_args<T>(c, 0, tl, freeze);
     for (int p = 0; p < 2; ++p) {
         A.h[p] = (T*)c->d_h[p];
         A.qx[p] = (T*)c->d_qx[p];
@@ -325,9 +325,10 @@ Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve) {
     return A;
 }
 
-hipError_t enqueue_two(fl_ctx* c, long long launch, int resolve, hipStream_t s) {
-    if (c->prec == FL_F64) return launch_step2<double>(make_args2<double>(c, launch, resolve), c->cpt2, s);
-    return launch_step2<float>(make_args2<float>(c, launch, resolve), c->cpt2, s);
+hipError_t enqueue_two(fl_ctx* c, long long launch, int resolve, hipStream_t s, int freeze = 0) {
+    if (c->prec == FL_F64)
+        return launch_step2<double>(make_args2<double>(c, launch, resolve, freeze), c->cpt2, s);
+    return launch_step2<float>(make_args2<float>(c, launch, resolve, freeze), c->cpt2, s);
 }
 
 // K two-step launches with launch counters 0 .. K-1 (K a multiple of 6, so
@@ -597,7 +598,7 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
 // launches left steps over.  Finally the state becomes the single-step state
 // again, at a step counter whose parity names the buffer that holds it.
 template <typename T>
-fl_status fused_steps_t(fl_ctx* c, long long nsteps) {
+fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
     fl_status st;
     {
         const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
@@ -609,17 +610,17 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps) {
     Clock2 slot{};
     for (int round = 0;; ++round) {
         while (want > 0) {
-            if (c->graph2_exec && lc % 6 == 0 && want >= c->graph2_k) {
+            if (!freeze && c->graph2_exec && lc % 6 == 0 && want >= c->graph2_k) {
                 HIP_TRY(c, hipGraphLaunch(c->graph2_exec, c->stream));
                 lc += c->graph2_k;
                 want -= c->graph2_k;
             } else {
-                HIP_TRY(c, enqueue_two(c, lc, 0, c->stream));
+                HIP_TRY(c, enqueue_two(c, lc, 0, c->stream, freeze));
                 lc += 1;
                 want -= 1;
             }
         }
-        HIP_TRY(c, enqueue_two(c, lc, 1, c->stream));
+        HIP_TRY(c, enqueue_two(c, lc, 1, c->stream, freeze));
         lc += 1;
         HIP_TRY(c, hipMemcpyAsync(&slot, &c->d_ctl->c2[lc & 1], sizeof(slot), hipMemcpyDeviceToHost,
                                   c->stream));
@@ -1160,6 +1161,50 @@ fl_status fl_get_state(fl_ctx* c, void* h, void* qx, void* qy, double* t, int on
     st = read_report(c, &r, false);
     if (t) *t = r.t;
     return st;
+}
+
+fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_launch,
+                             double* ms_per_step) {
+    if (!c) return FL_EINVAL;
+    if (!c->committed) return fail(c, FL_ESTATE, "fl_autotune_fusion before fl_commit");
+    if (!c->d_part2[0] || !c->graph2_exec)
+        return fail(c, FL_ESTATE, "fl_autotune_fusion: commit with fl_set_fusion(ctx, 2, ...) first");
+    if (trial_steps < 2) return fail(c, FL_EINVAL, "fl_autotune_fusion: trial_steps < 2");
+    HIP_TRY(c, hipSetDevice(c->device));
+    fl_status st;
+    const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+    if ((st = fold_budget(c, tl))) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    float ms1 = 0.f, ms2 = 0.f;
+    // one step per launch: frozen steps (dt = 0 streams the state, leaves it as it is)
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < trial_steps; ++r) {
+        hipError_t e = c->prec == FL_F64
+                           ? launch_step<double>(make_args<double>(c, c->nstep, tl, 1), tl.cpt, c->stream)
+                           : launch_step<float>(make_args<float>(c, c->nstep, tl, 1), tl.cpt, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "fl_autotune_fusion trial");
+        c->nstep += 1;
+    }
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventElapsedTime(&ms1, e0, e1));
+    if ((st = fold_budget(c, tl))) return st;
+    // two steps per launch, as fl_step runs them (entry, launches, settling, exit)
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    st = c->prec == FL_F64 ? fused_steps_t<double>(c, trial_steps, 1)
+                           : fused_steps_t<float>(c, trial_steps, 1);
+    if (st) return st;
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventElapsedTime(&ms2, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->fuse = (ms2 < ms1) ? 2 : 1;
+    if (steps_per_launch) *steps_per_launch = c->fuse;
+    if (ms_per_step) *ms_per_step = (c->fuse == 2 ? ms2 : ms1) / trial_steps;
+    return FL_OK;
 }
 
 size_t fl_device_bytes(const fl_ctx* c) { return c ? c->dev_bytes : 0; }

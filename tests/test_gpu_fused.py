@@ -150,3 +150,32 @@ def test_valley4096_benchmark_construction():
         print(f"CASE valley4096 cpt={cpt}", flush=True)
         got = _run(sc, "f32", (2, cpt, 0), [60])
         _same(got, ref, f"cpt={cpt}")
+
+
+def test_autotune_fusion_keeps_the_bits():
+    """Frozen trial steps of both launch modes leave the state as it is; the
+    run continues bit for bit with whichever mode was kept."""
+    sc = config_d1()
+    ref = _run(sc, "f32", 1, [400])
+    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 0))
+    f.step(100)
+    spl, ms = f.autotune_fusion(20)
+    assert spl in (1, 2) and ms > 0
+    f.step(300)
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    r = f.get_report(check=False)
+    f.close()
+    _same((h, qx, qy, r), ref)
+    g = fl.from_scenario(sc, "f32")              # committed without the two-step buffers
+    assert fl.lib().fl_autotune_fusion(g.ctx, 10, None, None) == fl.FL_ESTATE
+    g.close()
+
+
+def test_autotune_fusion_picks_two_steps_on_the_benchmark_grid():
+    """On the 16384^2 benchmark grid (dry start) two steps per launch win."""
+    sc = synth.config_d3(16384)
+    f = fl.from_scenario(sc, "f32", fusion=2)
+    spl, ms = f.autotune_fusion(20)
+    f.close()
+    assert spl == 2, ms
