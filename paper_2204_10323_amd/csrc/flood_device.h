@@ -179,7 +179,10 @@ __device__ __forceinline__ float face_q<float>(float etaL, float etaR, float zL,
     float nf = 0.5f * (nL + nR);
     float grad = (etaR - etaL) * inv_dx;
     float num = q - (gdt * hf) * grad;
-    float m73 = __builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(hf));
+    // clamped so that a film thin enough to overflow it (h_f < 3e-17, possible
+    // only with h_eps below that) still gives 0 * large = 0 for q = 0, as the
+    // division does
+    float m73 = fminf(__builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(hf)), 3.0e38f);
     float den = 1.0f + ((gdt * (nf * nf)) * fabsf(q)) * m73;
     return num * __builtin_amdgcn_rcpf(den);
 }
@@ -189,6 +192,8 @@ template <typename T>
 __device__ __forceinline__ T donor_ratio(T hp, T O) { return hp / O; }
 template <>
 __device__ __forceinline__ float donor_ratio<float>(float hp, float O) {
+    // an outflow so small that its reciprocal overflows takes the division
+    if (O < 1.0e-30f) return hp / O;
     return fminf(hp * __builtin_amdgcn_rcpf(O), 1.0f);
 }
 

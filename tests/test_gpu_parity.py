@@ -189,3 +189,34 @@ def test_closed_basin_volume_constant_gpu():
     assert abs(r.v_now / r.v0 - 1) <= 1e-13
     assert r.v_in == 0 and r.v_out == 0
     f.close()
+
+
+@pytest.mark.parametrize("fusion", [1, 2])
+def test_zero_threshold_thin_films_fp32(fusion):
+    """h_eps = 0 with films down to 1e-30 m beside deep water and zero
+    discharges: the FP32 face update (which multiplies by h_f^(-7/3)) stays
+    finite and agrees with the oracle, and so does the donor factor of cells
+    whose outflow is vanishingly small."""
+    rng = np.random.default_rng(77)
+    nx, ny = 48, 40
+    z = rng.uniform(0.0, 0.5, (ny, nx)).astype(np.float32)
+    n = rng.uniform(0.02, 0.06, (ny, nx)).astype(np.float32)
+    kind = rng.random((ny, nx))
+    h = np.where(kind < 0.4, 10.0 ** rng.uniform(-30, -18, (ny, nx)),
+                 np.where(kind < 0.7, 0.0, rng.uniform(0.05, 1.0, (ny, nx)))).astype(np.float32)
+    sc = Scenario("films", nx, ny, 1.0, z, n, h, None, None, dt_max=0.05, h_eps=0.0)
+    f = fl.from_scenario(sc, "f32", fusion=fusion)
+    o = oracle.Run(sc)
+    for chunk in (2, 2, 4):
+        f.step(chunk)
+        o.step(chunk)
+        hg = f.get_depth()
+        qx, qy = f.get_discharge()
+        assert np.isfinite(hg).all() and np.isfinite(qx).all() and np.isfinite(qy).all()
+        sh = max(np.abs(o.h).max(), 1e-3)
+        sq = max(np.abs(o.qx).max(), np.abs(o.qy).max(), 1e-3)
+        assert max_abs(hg, o.h) <= 2e-5 * sh
+        assert max_abs(qx, o.qx) <= 2e-5 * sq and max_abs(qy, o.qy) <= 2e-5 * sq
+    r = f.get_report()
+    assert r.nonfinite == 0 and r.budget_error() <= 1e-6
+    f.close()
