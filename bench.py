@@ -124,7 +124,7 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
         g.close()
     progress("ensemble: members one after another, two steps per launch, done")
     b = fl.Batch(ctxs)
-    cands = [(4, 8), (4, 16), (4, 32), (2, 16), (2, 32)]
+    cands = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32)]
     best, _ = b.autotune(cands, trial_steps)
     batch_ms = b.time(steps)
     rep = [f.get_report() for f in ctxs]

@@ -230,6 +230,19 @@ class Flood:
     def set_tiling(self, cells_per_lane: int = 0, rows_per_item: int = 0):
         _check(self.ctx, lib().fl_set_tiling(self.ctx, cells_per_lane, rows_per_item))
 
+    def _side_length(self, side: int) -> int:
+        return self.ny if side in (FL_WEST, FL_EAST) else self.nx
+
+    def set_inflow_fraction(self, side: int, f_start: float, f_end: float, slope: float, t_s, q_m3s):
+        """set_inflow on the section given as fractions of the side (fraction_section)."""
+        first, count = fraction_section(self._side_length(side), f_start, f_end)
+        self.set_inflow(side, first, count, slope, t_s, q_m3s)
+
+    def set_outflow_fraction(self, side: int, f_start: float, f_end: float, slope: float):
+        """set_outflow on the section given as fractions of the side (fraction_section)."""
+        first, count = fraction_section(self._side_length(side), f_start, f_end)
+        self.set_outflow(side, first, count, slope)
+
     def set_fusion(self, steps_per_launch: int, cells_per_lane: int = 0, rows_per_item: int = 0):
         """Steps per launch (1 or 2) and the two-step kernel's tiling (fl_set_fusion)."""
         _check(self.ctx, lib().fl_set_fusion(self.ctx, steps_per_launch, cells_per_lane,
@@ -434,6 +447,21 @@ def copy_probe(nbytes: int, reps: int = 20, variant: int = 1, device: int = 0) -
     if st != FL_OK:
         raise FloodError(st, "fl_copy_probe failed")
     return g.value
+
+
+def fraction_section(length: int, f_start: float, f_end: float):
+    """(first, count) of the cells along a side of `length` cells whose centre
+    lies at a fraction (k + 1/2) / length of the side within [f_start, f_end]:
+    the paper's way of placing a boundary section (its fraction_start and
+    fraction_end of a side, Methods).  (0, 0) when no centre lies inside."""
+    if length < 1:
+        raise ValueError("fraction_section: length must be >= 1")
+    k = np.arange(length)
+    c = (k + 0.5) / length
+    sel = np.nonzero((c >= f_start) & (c <= f_end))[0]
+    if sel.size == 0:
+        return 0, 0
+    return int(sel[0]), int(sel.size)
 
 
 def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,

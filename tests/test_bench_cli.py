@@ -46,3 +46,15 @@ def test_sweep_rejects_bad_arguments():
         discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 10, 0.0)
     with pytest.raises(ValueError):
         discharge_sweep(z, n, 1.0, (0, 0, 4, 1e-3), None, [1.0], 10, 0.1, mode="fastest")
+
+
+def test_fraction_section():
+    """Cells whose centre fraction (k + 1/2)/L lies in [f_start, f_end]."""
+    from paper_2204_10323_amd import fraction_section
+    assert fraction_section(10, 0.2, 0.5) == (2, 3)      # centres 0.25, 0.35, 0.45
+    assert fraction_section(10, 0.0, 1.0) == (0, 10)
+    assert fraction_section(10, 0.96, 1.0) == (0, 0)     # last centre is 0.95
+    assert fraction_section(7, 0.5, 0.5) == (3, 1)       # the middle cell's centre is exactly 0.5
+    assert fraction_section(4, 0.6, 0.4) == (0, 0)
+    with pytest.raises(ValueError):
+        fraction_section(0, 0.0, 1.0)

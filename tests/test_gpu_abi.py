@@ -287,3 +287,19 @@ def test_bound_workspace(fusion):
     assert np.array_equal(h, ref[0]) and np.array_equal(qx, ref[1]) and np.array_equal(qy, ref[2])
     assert r.t == ref[3].t
     assert L.fl_workspace_bytes(0, 5, 0, 0) == 0 and L.fl_workspace_bytes(5, 5, 0, 2) == 0
+
+
+def test_inflow_outflow_by_side_fractions():
+    """Sections given as fractions of a side (the paper's way) select the same cells."""
+    sc = config_d1()
+    side, first, count, slope, ts, qs = sc.inflow
+    assert (first, count) == fl.fraction_section(sc.ny, first / sc.ny, (first + count) / sc.ny)
+    h_ref, *_ = run_gpu(sc, 100, "f32")
+    f = fl.from_scenario(sc, "f32", commit=False)
+    f.set_inflow_fraction(side, first / sc.ny, (first + count) / sc.ny, slope, ts, qs)
+    f.set_outflow_fraction(EAST, 0.0, 1.0, sc.outflow[3])
+    f.commit()
+    f.step(100)
+    h = f.get_depth()
+    f.close()
+    assert np.array_equal(h, h_ref)
