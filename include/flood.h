@@ -164,7 +164,8 @@ fl_status fl_set_state(fl_ctx *ctx, const void *h, const void *qx, const void *q
 /* Device memory for the buffers fl_commit allocates, for a caller that owns
  * its memory (for example a PyTorch tensor):
  * fl_workspace_bytes gives the bytes a grid needs (0 for invalid arguments);
- * flags: FL_WS_TWO_STEP adds the buffers of fl_set_fusion(ctx, 2, ...).
+ * flags: FL_WS_TWO_STEP adds the buffers of fl_set_fusion(ctx, 2, ...),
+ * FL_WS_ACTIVE_TILES those of fl_set_active_tiles(ctx, 1).
  * fl_bind_workspace makes the following commits carve their buffers from
  * dev_ptr (256-byte aligned, on the context's device) instead of allocating;
  * the caller keeps ownership and must keep the memory alive until fl_destroy,
@@ -175,6 +176,7 @@ fl_status fl_set_state(fl_ctx *ctx, const void *h, const void *qx, const void *q
  * 0); fl_commit returns EINVAL if the workspace is smaller than its flags
  * need. */
 #define FL_WS_TWO_STEP 1u
+#define FL_WS_ACTIVE_TILES 2u
 size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t flags);
 fl_status fl_bind_workspace(fl_ctx *ctx, void *dev_ptr, size_t bytes);
 
@@ -244,6 +246,31 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
  * fl_commit.  EINVAL: steps_per_launch not 1 or 2, an unsupported tiling. */
 fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per_lane,
                         int32_t rows_per_item);
+
+/* Active-tile skipping (wet-region skipping) for fl_step, fl_time_steps,
+ * fl_advance and the forward of reverse mode, with one step per launch: a
+ * step does not recompute a work item when the item and the four items that
+ * share an edge with it held no water (h <= 0), kept their depths and carried
+ * no discharge in the step before, and the item itself also in the step
+ * before that.  Such an item's cells cannot change: every face between two
+ * cells without water is dry in eq. (3) (its water-surface height above the
+ * higher bed is <= 0), so no water moves; the outflow of eq. (5) is zero for
+ * an empty edge cell.  Items behind an inflow face (eq. 6) are always
+ * computed.  Each item records, per step, one flag byte (three steps kept).
+ * Results are the values of computing every item (a zero may differ in sign;
+ * after a non-finite depth, which stops the clock, the states may differ).
+ * Work scales with the wet area (a flood on a mostly dry DEM) instead of the
+ * grid.  Another path that moves the state (batches, frozen tiling trials,
+ * the reverse sweep) marks the flags stale; the next skipping step then
+ * computes every item for two steps.  on: 0 or 1; takes effect at the next
+ * fl_commit, which fails with EINVAL if two steps per launch are also set.
+ * EINVAL: on not 0 or 1. */
+fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
+
+/* Work items the next step computes under active-tile skipping (*next_items)
+ * and work items of a step (*total_items).  Synchronises.  ESTATE: not
+ * committed with fl_set_active_tiles(ctx, 1). */
+fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items);
 
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
  * trial_steps frozen steps (dt = 0: the state is streamed like a real step but

@@ -32,6 +32,7 @@ EXPORTS = [
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
     "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state", "fl_autotune_fusion",
+    "fl_set_active_tiles", "fl_active_items",
 ]
 
 
@@ -119,6 +120,8 @@ def lib() -> C.CDLL:
             "fl_bind_workspace": (C.c_int, [vp, vp, C.c_size_t]),
             "fl_get_state": (C.c_int, [vp, vp, vp, vp, C.POINTER(dbl), C.c_int]),
             "fl_autotune_fusion": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(dbl)]),
+            "fl_set_active_tiles": (C.c_int, [vp, i32]),
+            "fl_active_items": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -248,6 +251,16 @@ class Flood:
         _check(self.ctx, lib().fl_set_fusion(self.ctx, steps_per_launch, cells_per_lane,
                                              rows_per_item))
 
+    def set_active_tiles(self, on: bool = True):
+        """Active-tile (wet-region) skipping for one step per launch (fl_set_active_tiles)."""
+        _check(self.ctx, lib().fl_set_active_tiles(self.ctx, 1 if on else 0))
+
+    def active_items(self):
+        """(work items the next step computes, work items per step) (fl_active_items)."""
+        nxt, tot = C.c_int64(), C.c_int64()
+        _check(self.ctx, lib().fl_active_items(self.ctx, C.byref(nxt), C.byref(tot)))
+        return nxt.value, tot.value
+
     def commit(self):
         _check(self.ctx, lib().fl_commit(self.ctx))
 
@@ -310,8 +323,9 @@ class Flood:
                                             C.c_void_p(qy.ctypes.data), C.byref(t), 0))
         return h, qx, qy, t.value
 
-    def workspace_bytes(self, two_step: bool = False) -> int:
-        return int(lib().fl_workspace_bytes(self.nx, self.ny, self.prec, 1 if two_step else 0))
+    def workspace_bytes(self, two_step: bool = False, active_tiles: bool = False) -> int:
+        flags = (1 if two_step else 0) | (2 if active_tiles else 0)
+        return int(lib().fl_workspace_bytes(self.nx, self.ny, self.prec, flags))
 
     def bind_workspace(self, buf):
         """Carve the commit buffers from a caller-owned device tensor (kept
@@ -466,7 +480,7 @@ def fraction_section(length: int, f_start: float, f_end: float):
 
 def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,
                   cells_per_lane: int = 0, rows_per_item: int = 0, fusion=None,
-                  **param_over) -> Flood:
+                  active_tiles: bool = False, **param_over) -> Flood:
     """A committed context for a synthetic scenario (see the `synth` module)."""
     f = Flood(sc.nx, sc.ny, sc.dx, precision, device, stream)
     f.set_dem(sc.z)
@@ -487,6 +501,8 @@ def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, comm
         f.set_tiling(cells_per_lane, rows_per_item)
     if fusion is not None:
         f.set_fusion(*((fusion,) if isinstance(fusion, int) else tuple(fusion)))
+    if active_tiles:
+        f.set_active_tiles(True)
     if commit:
         f.commit()
     return f

@@ -87,6 +87,11 @@ struct StepArgs {
     int nstrips, nchunks, rows;   // tiling: strips along x, chunks of `rows` rows along y
     int phase;                    // step index modulo 6
     double dx, g, alpha, dt_max, h_eps, dt_fixed;
+    // active-tile skipping: per work item, one byte per step (slot = step
+    // modulo 3) that says whether the item's cells were wet or changed; NULL:
+    // every item is computed every step
+    unsigned char* act;
+    long long act_stride;         // bytes per slot (>= nstrips * nchunks)
 };
 
 // A two-step launch: the grid, boundary data and constants (with the
@@ -185,6 +190,8 @@ hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl*
 template <typename T>
 hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* partials,
                          int nparts, double* out, hipStream_t s);
+// Sets n bytes at p to v (a kernel, so that it can sit in a captured graph).
+hipError_t launch_fill_bytes(unsigned char* p, long long n, unsigned char v, hipStream_t s);
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s);

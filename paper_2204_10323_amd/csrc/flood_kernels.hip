@@ -55,10 +55,13 @@ __device__ void clock_wave(const StepArgs<T>& a) {
 }
 
 // One work item: strip s (columns), chunk c (rows).  Accumulates the ordered
-// bits of the deepest new depth and the outflow discharge leaving the grid.
-template <typename T, int CPT, bool NTS>
+// bits of the deepest new depth and the outflow discharge leaving the grid;
+// with ACT, also whether any of the item's cells is wet (h > 0, or NaN) or
+// changed its depth, or any face it stores (border faces included) carries a
+// non-zero discharge.
+template <typename T, int CPT, bool NTS, bool ACT = false>
 __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord<T>::U& hbits,
-                          double& outacc) {
+                          double& outacc, bool& moved) {
     constexpr int WL = 64 * CPT;  // loaded columns
     constexpr int WO = WL - 4;    // output columns
     const int lane = threadIdx.x & 63;
@@ -116,11 +119,30 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
             h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
         }
         if (k < j1 + 1) load_row(k + 1);
-        T hn[CPT], qxo[CPT], qyo[CPT];
+        T hn[CPT], qxo[CPT], qyo[CPT], hold[CPT];
+        if constexpr (ACT) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) hold[m] = M.h2[m];  // depth of row k-2 before the step
+        }
         M.row(a, K, G, k, h0, z0, n0, qx0, qy0, hn, qxo, qyo);
 
         const int ko = k - 2;
         const bool in_item = (ko >= j0 && ko < j1);
+        if constexpr (ACT) {
+            if (in_item) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m) {
+                    if (store_col[m])
+                        moved = moved || !(hn[m] <= T(0)) || hn[m] != hold[m] || qxo[m] != T(0) ||
+                                qyo[m] != T(0);
+                    if (G.west_face[m]) moved = moved || qxo[m] != T(0);
+                }
+            } else if (ko == -1 && south_chunk) {
+#pragma unroll
+                for (int m = 0; m < CPT; ++m)
+                    if (store_col[m]) moved = moved || qyo[m] != T(0);
+            }
+        }
         if (in_item) {
             T* const ho = a.h_out + (long long)(ko + kHalo) * P;
             T* const qxr = a.qx_out + (long long)(ko + kHalo) * P;
@@ -144,27 +166,89 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
     }
 }
 
+// Does work item (s, c), whose cells are columns [s wo, (s + 1) wo) and rows
+// [c rows, (c + 1) rows) of the grid, own a cell behind an inflow face?
+template <typename T>
+__device__ __forceinline__ bool feeds_inflow(const StepArgs<T>& a, int s, int c, int wo) {
+    if (a.in_side < 0) return false;
+    const int i0 = s * wo, i1 = min(i0 + wo, a.nx);
+    const int j0 = c * a.rows, j1 = min(j0 + a.rows, a.ny);
+    const int f0 = a.in_first, f1 = a.in_first + a.in_count;
+    switch (a.in_side) {
+    case SIDE_W: return i0 == 0 && j0 < f1 && f0 < j1;
+    case SIDE_E: return i0 <= a.nx - 1 && a.nx - 1 < i1 && j0 < f1 && f0 < j1;
+    case SIDE_S: return j0 == 0 && i0 < f1 && f0 < i1;
+    case SIDE_N: return j1 == a.ny && i0 < f1 && f0 < i1;
+    default: return false;
+    }
+}
+
+// Must item (s, c) be computed in this step (active-tile skipping)?  A step
+// leaves a cell as it is, with zero discharges on its faces, when the cell
+// and its four neighbours hold no water: h <= 0 on both sides makes a face
+// dry (h_f <= 0), so its discharge is 0 whatever the donor factors.  The
+// four neighbours of an item's cells lie in the item or in the four items
+// that share an edge with it, so the item may be skipped when those five
+// items were dry and unchanged in the previous step (flags of step n-1 are
+// 0).  The skipped item's output buffer holds its state of step n-2, which
+// equals that of step n-1 when the item's own flag of step n-2 is 0 as well.
+// Items behind an inflow face are always computed: the inflow can start at
+// any step.
+template <typename T>
+__device__ __forceinline__ bool item_needed(const StepArgs<T>& a, int s, int c, int wo) {
+    if (feeds_inflow<T>(a, s, c, wo)) return true;
+    const int lane = threadIdx.x & 63;
+    int v = 0;
+    if (lane < 6) {
+        // lanes 0-4: the item, west, east, south, north at step n-1; lane 5: the item at n-2
+        const int ds = lane == 1 ? -1 : (lane == 2 ? 1 : 0);
+        const int dc = lane == 3 ? -1 : (lane == 4 ? 1 : 0);
+        const int ss = s + ds, cc = c + dc;
+        const int sl = lane == 5 ? (a.phase + 1) % 3 : (a.phase + 2) % 3;
+        if (ss >= 0 && ss < a.nstrips && cc >= 0 && cc < a.nchunks)
+            v = a.act[sl * a.act_stride + (long long)cc * a.nstrips + ss];
+    }
+    return __ballot(v != 0) != 0ull;
+}
+
 // Work item `item` of one step (strip fastest): the marching tile, then the
-// wave's deepest cell into the next max slot and its outflow partial sum.
-template <typename T, int CPT, bool NTS>
+// wave's deepest cell into the next max slot and its outflow partial sum;
+// with ACT, first the skip test, and last the item's flag of this step.
+template <typename T, int CPT, bool NTS, bool ACT = false>
 __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
+    if constexpr (ACT) {
+        const int s = item % a.nstrips, c = item / a.nstrips;
+        if (!item_needed<T>(a, s, c, 64 * CPT - 4)) {
+            // nothing moves: no deeper cell, no outflow, flag 0
+            if ((threadIdx.x & 63) == 0) {
+                a.act[(a.phase % 3) * a.act_stride + item] = 0;
+                const int slot = part_slot<T>(a, s, c);
+                if (slot >= 0) a.part_cur[slot] = 0.0;
+            }
+            return;
+        }
+    }
     const ClockSlot ck = a.ctl->clk[a.phase & 1];
     int last, done, nonfin;
     const double dt64 = step_dt<T>(a, ck, a.ctl->hmax[a.phase % 3], a.ctl->t_end, last, done, nonfin);
     const int s = item % a.nstrips, c = item / a.nstrips;
     typename Ord<T>::U hb = 0;
     double outacc = 0.0;
-    step_item<T, CPT, NTS>(a, s, c, (T)dt64, hb, outacc);
+    bool moved = false;
+    step_item<T, CPT, NTS, ACT>(a, s, c, (T)dt64, hb, outacc, moved);
     hb = wave_max_key(hb);
     const int slot = part_slot<T>(a, s, c);
     if (slot >= 0) outacc = wave_sum(outacc);
+    bool any_moved = false;
+    if constexpr (ACT) any_moved = __ballot(moved) != 0ull;
     if ((threadIdx.x & 63) == 0) {
         if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], (unsigned long long)hb);
         if (slot >= 0) a.part_cur[slot] = outacc;
+        if constexpr (ACT) a.act[(a.phase % 3) * a.act_stride + item] = any_moved ? 1 : 0;
     }
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool ACT>
 __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     if (blockIdx.x == 0) {
         if (threadIdx.x < 64) clock_wave<T>(a);
@@ -182,7 +266,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     // derived from it: strip, rows, loop counter, border tests) scalar
     const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
-    tile_item<T, CPT, true>(a, wave);
+    tile_item<T, CPT, true, ACT>(a, wave);
 }
 
 // Persistent batch of independent members, one launch for many steps.
@@ -245,7 +329,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
         }
         const StepArgs<T>& a = S.a[(int)((S.n0 + k) % 6)];
         if (e == 0) clock_wave<T>(a);
-        else tile_item<T, CPT, false>(a, e - 1);
+        else tile_item<T, CPT, false, false>(a, e - 1);
         // release within the XCD: this wave's stores have reached L2
         __builtin_amdgcn_s_waitcnt(0);
         __asm__ volatile("" ::: "memory");
@@ -343,16 +427,39 @@ __global__ void k_volume_sum(const double* part, int nparts, double* out) {
 // ----------------------------------------------------------------- launchers
 int strip_width(int cpt) { return 64 * cpt - 4; }
 
-template <typename T>
-hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s) {
-    const int items = a.nstrips * a.nchunks;
-    const int blocks = 1 + (items + 3) / 4;
+template <typename T, bool ACT>
+hipError_t launch_step_act(const StepArgs<T>& a, int cpt, int blocks, hipStream_t s) {
     switch (cpt) {
-    case 1: hipLaunchKernelGGL((k_step<T, 1>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_step<T, 2>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<T, 4>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_step<T, 1, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<T, 2, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<T, 4, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s) {
+    const long long items = (long long)a.nstrips * a.nchunks;
+    const int blocks = (int)(1 + (items + 3) / 4);
+    if (a.act) {
+        // the flags of every item must fit in a slot
+        if (items > a.act_stride) return hipErrorInvalidValue;
+        return launch_step_act<T, true>(a, cpt, blocks, s);
+    }
+    return launch_step_act<T, false>(a, cpt, blocks, s);
+}
+
+__global__ void k_fill_bytes(unsigned char* p, long long n, unsigned char v) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_bytes(unsigned char* p, long long n, unsigned char v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long want = (n + 255) / 256;
+    const int blocks = (int)std::min<long long>(want, 2048);
+    hipLaunchKernelGGL(k_fill_bytes, dim3(blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

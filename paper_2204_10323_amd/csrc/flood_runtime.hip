@@ -76,6 +76,15 @@ struct fl_ctx {
     hipGraphExec_t graph2_exec = nullptr;
     int graph2_k = 0;
 
+    // active-tile skipping (fl_set_active_tiles): per work item and step
+    // modulo 3 one flag byte; sized for the smallest work items any tiling can
+    // have.  act_at: the step counter up to which the skipping steps kept the
+    // flags; any other path that moves the state leaves them stale, and they
+    // are set to 1 (compute everything) before the next skipping step.
+    int active = 0;
+    unsigned char* d_act = nullptr;
+    long long act_stride = 0, act_at = -1;
+
     // reverse mode (fl_adj_*): settings, checkpoints and the forward's record
     bool adj_setup = false;
     std::vector<int> gauges;
@@ -288,12 +297,24 @@ StepArgs<T> make_args(const fl_ctx* c, long long n, const Tiling& tl, int freeze
     a.dt_max = c->params.dt_max;
     a.h_eps = c->params.h_eps;
     a.dt_fixed = c->params.dt_fixed;
+    a.act = nullptr;
+    a.act_stride = 0;
     return a;
 }
 
+// One step of the context's own run: with active-tile skipping when it is on.
+template <typename T>
+hipError_t enqueue_one_t(fl_ctx* c, long long n, hipStream_t s) {
+    StepArgs<T> a = make_args<T>(c, n);
+    if (c->active) {
+        a.act = c->d_act;
+        a.act_stride = c->act_stride;
+    }
+    return launch_step<T>(a, c->cpt, s);
+}
+
 hipError_t enqueue_one(fl_ctx* c, long long n, hipStream_t s) {
-    if (c->prec == FL_F64) return launch_step<double>(make_args<double>(c, n), c->cpt, s);
-    return launch_step<float>(make_args<float>(c, n), c->cpt, s);
+    return c->prec == FL_F64 ? enqueue_one_t<double>(c, n, s) : enqueue_one_t<float>(c, n, s);
 }
 
 // Work decomposition of the two-step kernel: strip 0 outputs columns
@@ -427,7 +448,13 @@ fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
 // rounding, as do_commit allocates, with every size that depends on the
 // boundary data at its largest (sections up to the longest side, hydrographs
 // up to 4096 samples).
-size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step) {
+// Flag bytes per step slot of active-tile skipping: enough for the smallest
+// work items (one cell per lane, one row).
+long long act_slot_bytes(int nx, int ny) {
+    return (long long)((nx + strip_width(1) - 1) / strip_width(1)) * ny;
+}
+
+size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step, bool active) {
     const size_t es = elem_size(prec);
     const long long align = 256 / (long long)es;
     const long long pitch = ((nx + 8 + align - 1) / align) * align;
@@ -441,6 +468,7 @@ size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step) {
     b += 2 * ws_round(sizeof(double) * 4096);
     b += ws_round(sizeof(double) * kVolumeParts) + ws_round(sizeof(double)) + ws_round(sizeof(DevCtl));
     if (two_step) b += 4 * ws_round(sizeof(double) * side);
+    if (active) b += ws_round((size_t)(3 * act_slot_bytes(nx, ny)));
     return b;
 }
 
@@ -452,7 +480,10 @@ fl_status do_commit(fl_ctx* c) {
     free_device(c);
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
-    if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse == 2))
+    if (c->active && c->fuse == 2)
+        return fail(c, FL_EINVAL,
+                    "fl_commit: active-tile skipping runs one step per launch; set fl_set_fusion(ctx, 1, ...)");
+    if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse == 2, c->active != 0))
         return fail(c, FL_EINVAL, "fl_commit: the bound workspace is smaller than fl_workspace_bytes");
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
     c->rows = c->rows_req ? c->rows_req : default_rows(nx, ny, c->cpt);
@@ -489,6 +520,13 @@ fl_status do_commit(fl_ctx* c) {
     if ((st = dalloc(c, (void**)&c->d_vol_part, sizeof(double) * kVolumeParts))) return st;
     if ((st = dalloc(c, (void**)&c->d_vol, sizeof(double)))) return st;
     if ((st = dalloc(c, (void**)&c->d_ctl, sizeof(DevCtl)))) return st;
+    c->d_act = nullptr;
+    c->act_stride = 0;
+    c->act_at = -1;
+    if (c->active) {
+        c->act_stride = act_slot_bytes(nx, ny);
+        if ((st = dalloc(c, (void**)&c->d_act, (size_t)(3 * c->act_stride)))) return st;
+    }
 
     // cell fields
     if ((st = upload_field(c, c->d_z, c->z, ny, nx, kHalo, kHalo))) return st;
@@ -577,6 +615,10 @@ fl_status do_commit(fl_ctx* c) {
 }
 
 fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
+    if (c->active && nsteps > 0 && c->act_at != c->nstep) {
+        // flags stale: compute every item in the next two steps
+        HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
+    }
     while (nsteps > 0) {
         if (c->graph_exec && c->nstep % 6 == 0 && nsteps >= c->graph_k) {
             HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
@@ -588,6 +630,7 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
             nsteps -= 1;
         }
     }
+    if (c->active) c->act_at = c->nstep;
     return FL_OK;
 }
 
@@ -770,9 +813,9 @@ fl_status fl_init_grid(fl_ctx* c, int32_t nx, int32_t ny, double dx) {
 }
 
 size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t flags) {
-    if (nx < 1 || ny < 1 || (prec != FL_F32 && prec != FL_F64) || (flags & ~1u)) return 0;
+    if (nx < 1 || ny < 1 || (prec != FL_F32 && prec != FL_F64) || (flags & ~3u)) return 0;
     if ((long long)nx + 8 + 256 > (1LL << 28) || (long long)ny + 8 > (1LL << 30)) return 0;
-    return workspace_bytes(nx, ny, prec, (flags & 1u) != 0);
+    return workspace_bytes(nx, ny, prec, (flags & 1u) != 0, (flags & 2u) != 0);
 }
 
 fl_status fl_bind_workspace(fl_ctx* c, void* dev_ptr, size_t bytes) {
@@ -781,7 +824,7 @@ fl_status fl_bind_workspace(fl_ctx* c, void* dev_ptr, size_t bytes) {
     if (dev_ptr) {
         if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
             return fail(c, FL_EINVAL, "fl_bind_workspace: pointer not 256-byte aligned");
-        if (bytes < workspace_bytes(c->nx, c->ny, c->prec, false))
+        if (bytes < workspace_bytes(c->nx, c->ny, c->prec, false, false))
             return fail(c, FL_EINVAL, "fl_bind_workspace: smaller than fl_workspace_bytes");
     }
     HIP_TRY(c, hipSetDevice(c->device));
@@ -973,6 +1016,63 @@ fl_status fl_set_fusion(fl_ctx* c, int32_t steps_per_launch, int32_t cells_per_l
     c->cpt2_req = cells_per_lane;
     c->rows2_req = rows_per_item;
     invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_active_tiles(fl_ctx* c, int32_t on) {
+    if (!c) return FL_EINVAL;
+    if (on != 0 && on != 1) return fail(c, FL_EINVAL, "fl_set_active_tiles: on must be 0 or 1");
+    c->active = on;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) {
+    if (!c || !next_items || !total_items) return FL_EINVAL;
+    if (!c->committed || !c->active)
+        return fail(c, FL_ESTATE, "fl_active_items needs a context committed with active tiles on");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int ns = c->nstrips, nc = c->nchunks;
+    const long long items = (long long)ns * nc;
+    *total_items = items;
+    if (c->act_at != c->nstep) {  // stale flags: the next step computes everything
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        *next_items = items;
+        return FL_OK;
+    }
+    // the rule of the step kernel's skip test, for the step with counter n
+    const long long n = c->nstep;
+    std::vector<unsigned char> f1((size_t)items), f2((size_t)items);
+    HIP_TRY(c, hipMemcpyAsync(f1.data(), c->d_act + ((n + 2) % 3) * c->act_stride, (size_t)items,
+                              hipMemcpyDeviceToHost, c->stream));  // step n-1
+    HIP_TRY(c, hipMemcpyAsync(f2.data(), c->d_act + ((n + 1) % 3) * c->act_stride, (size_t)items,
+                              hipMemcpyDeviceToHost, c->stream));  // step n-2
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int wo = strip_width(c->cpt);
+    const int f0 = c->in_first, fe = c->in_first + c->in_count;
+    long long need = 0;
+    for (int cc = 0; cc < nc; ++cc)
+        for (int ss = 0; ss < ns; ++ss) {
+            const int i0 = ss * wo, i1 = std::min(i0 + wo, c->nx);
+            const int j0 = cc * c->rows, j1 = std::min(j0 + c->rows, c->ny);
+            bool in = false;
+            if (c->in_count > 0) {
+                switch (c->in_side) {
+                case FL_WEST: in = i0 == 0 && j0 < fe && f0 < j1; break;
+                case FL_EAST: in = i0 <= c->nx - 1 && c->nx - 1 < i1 && j0 < fe && f0 < j1; break;
+                case FL_SOUTH: in = j0 == 0 && i0 < fe && f0 < i1; break;
+                default: in = j1 == c->ny && i0 < fe && f0 < i1; break;
+                }
+            }
+            const long long k = (long long)cc * ns + ss;
+            bool act = in || f1[k] || f2[k];
+            if (ss > 0) act = act || f1[k - 1];
+            if (ss + 1 < ns) act = act || f1[k + 1];
+            if (cc > 0) act = act || f1[k - ns];
+            if (cc + 1 < nc) act = act || f1[k + ns];
+            need += act ? 1 : 0;
+        }
+    *next_items = need;
     return FL_OK;
 }
 
@@ -1401,6 +1501,7 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
         e = hipMemcpyAsync(gqh.data(), gq, sizeof(double) * gqh.size(), hipMemcpyDeviceToHost, c->stream);
     // back to the end of the forward run
     c->nstep = n0 + N;
+    c->act_at = -1;
     if (e == hipSuccess && (st = snapshot_end(c, true))) { cleanup(); return st; }
     cleanup();
     if (e != hipSuccess) return hip_fail(c, e, "adjoint sweep");

@@ -286,7 +286,7 @@ def test_bound_workspace(fusion):
     f.close()
     assert np.array_equal(h, ref[0]) and np.array_equal(qx, ref[1]) and np.array_equal(qy, ref[2])
     assert r.t == ref[3].t
-    assert L.fl_workspace_bytes(0, 5, 0, 0) == 0 and L.fl_workspace_bytes(5, 5, 0, 2) == 0
+    assert L.fl_workspace_bytes(0, 5, 0, 0) == 0 and L.fl_workspace_bytes(5, 5, 0, 4) == 0  # unknown flag
 
 
 def test_inflow_outflow_by_side_fractions():

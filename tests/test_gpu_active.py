@@ -1,0 +1,243 @@
+"""Active-tile skipping (fl_set_active_tiles) against computing every work item.
+
+A skipped item is one whose cells cannot change in the step, so both runs must
+hold the same values after every call: depths, discharges (a zero may differ
+in sign, which numpy's equality ignores), the clock and both volumes.  The
+cases put dry ground between wet patches, start inflows late (the items
+behind an inflow face are always computed), use work items down to one row,
+and hand the state between skipping and non-skipping paths."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2204_10323_amd as fl
+import synth
+from gpu_util import max_abs
+from synth import EAST, NORTH, SOUTH, WEST, Scenario, config_d1
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(sc, prec, chunks, active, tiling=(0, 0), **params):
+    f = fl.from_scenario(sc, prec, cells_per_lane=tiling[0], rows_per_item=tiling[1],
+                         active_tiles=active, **params)
+    out = []
+    for n in chunks:
+        if isinstance(n, float):
+            f.advance(n)
+        else:
+            f.step(n)
+        h = f.get_depth()
+        qx, qy = f.get_discharge()
+        r = f.get_report(check=False)
+        out.append((h, qx, qy, r))
+    f.close()
+    return out
+
+
+def _same(a, b, what=""):
+    for k, (x, y) in enumerate(zip(a, b)):
+        for u, v, nm in zip(x[:3], y[:3], ("h", "qx", "qy")):
+            assert np.array_equal(u, v), f"{what} call {k}: {nm} differs"
+        ra, rb = x[3], y[3]
+        assert (ra.steps, ra.t, ra.last_dt, ra.done, ra.nonfinite) == \
+            (rb.steps, rb.t, rb.last_dt, rb.done, rb.nonfinite), f"{what} call {k}"
+        assert ra.v_in == rb.v_in and ra.v_out == rb.v_out, f"{what} call {k}"
+
+
+def patchy(nx, ny, seed, t_on=1.0, sides=None):
+    """Dry terrain with a few wet patches (still water with random discharges
+    inside the patch), an inflow whose hydrograph is zero until t_on, an
+    outflow on another side."""
+    rng = np.random.default_rng(seed)
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    z = synth._f32(rng.uniform(0.0, 0.3, (ny, nx)) + 0.004 * ii + 0.002 * jj)
+    n = synth._f32(rng.uniform(0.02, 0.08, (ny, nx)))
+    h = np.zeros((ny, nx))
+    qx = np.zeros((ny, nx + 1))
+    qy = np.zeros((ny + 1, nx))
+    for _ in range(int(rng.integers(1, 4))):
+        ci, cj = rng.integers(0, nx), rng.integers(0, ny)
+        r = rng.uniform(2.0, 0.2 * max(nx, ny))
+        disc = (ii - ci) ** 2 + (jj - cj) ** 2 <= r * r
+        eta = z[disc].mean() + rng.uniform(0.1, 0.6)
+        h[disc] = np.maximum(h[disc], eta - z[disc])
+    wet = h > 0
+    qx[:, 1:nx][wet[:, :-1] & wet[:, 1:]] = rng.normal(0, 0.2, (wet[:, :-1] & wet[:, 1:]).sum())
+    qy[1:ny, :][wet[:-1, :] & wet[1:, :]] = rng.normal(0, 0.2, (wet[:-1, :] & wet[1:, :]).sum())
+    side_in, side_out = sides if sides else [(WEST, EAST), (EAST, WEST), (SOUTH, NORTH),
+                                             (NORTH, SOUTH)][int(rng.integers(0, 4))]
+    L_in = ny if side_in in (WEST, EAST) else nx
+    L_out = ny if side_out in (WEST, EAST) else nx
+    c_in = int(rng.integers(1, max(2, L_in // 3)))
+    f_in = int(rng.integers(0, L_in - c_in + 1))
+    c_out = int(rng.integers(1, L_out + 1))
+    f_out = int(rng.integers(0, L_out - c_out + 1))
+    ts = np.array([0.0, t_on, t_on + 2.0])
+    qs = np.array([0.0, 0.0, 3.0 * c_in])
+    sc = Scenario(f"patchy_{nx}x{ny}_{seed}", nx, ny, 1.0, z, n, synth._f32(h),
+                  (side_in, f_in, c_in, 1e-3, ts, qs), (side_out, f_out, c_out, 1e-3),
+                  dt_max=0.05)
+    sc.extra["qx0"] = synth._f32(qx)
+    sc.extra["qy0"] = synth._f32(qy)
+    return sc
+
+
+@pytest.mark.parametrize("prec,cpt", [("f32", 1), ("f32", 2), ("f32", 4), ("f64", 1), ("f64", 2)])
+def test_valley256_2000_steps(prec, cpt):
+    """The 256^2 valley from a dry start: a flood that grows across the grid."""
+    sc = config_d1()
+    print(f"CASE valley256 active tiles {prec} cpt={cpt}", flush=True)
+    chunks = [1, 50, 449, 1500]
+    ref = _run(sc, prec, chunks, False, (cpt, 8))
+    got = _run(sc, prec, chunks, True, (cpt, 8))
+    _same(got, ref, f"{prec} cpt={cpt}")
+
+
+def test_valley256_matches_oracle():
+    """The skipping run against the FP64 oracle at the FP32 gate."""
+    sc = config_d1()
+    got = _run(sc, "f32", [2000], True, (2, 8))[-1]
+    o = oracle.Run(sc)
+    o.step(2000)
+    assert max_abs(got[0], o.h) <= 1e-3
+    assert got[3].budget_error() <= 1e-6
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_patchy_grids_small_items(seed):
+    """Wet patches on dry ground, a late inflow, work items of 1 to 5 rows and
+    1, 2 or 4 cells per lane (several strips), CFL clock, FP32 and FP64."""
+    rng = np.random.default_rng(1000 + seed)
+    nx, ny = int(rng.integers(20, 300)), int(rng.integers(10, 120))
+    sc = patchy(nx, ny, 2000 + seed)
+    cpt = [1, 2, 4][seed % 3]
+    rows = [1, 2, 3, 5][seed % 4]
+    chunks = [1, 1, 7, 30, 3, 60]
+    for prec in ("f32", "f64"):
+        if prec == "f64" and cpt == 4:
+            continue
+        print(f"CASE patchy {nx}x{ny} seed {seed} {prec} cpt={cpt} rows={rows}", flush=True)
+        ref = _run(sc, prec, chunks, False, (cpt, rows))
+        got = _run(sc, prec, chunks, True, (cpt, rows))
+        _same(got, ref, f"patchy {nx}x{ny} {prec}")
+
+
+@pytest.mark.parametrize("side", [WEST, EAST, SOUTH, NORTH])
+def test_late_inflow_every_side(side):
+    """A dry grid whose inflow starts at t = 1 s: while it is zero only the
+    items behind the inflow faces are computed; then the flood spreads."""
+    nx, ny, cpt, rows = 200, 90, 1, 4
+    sc = patchy(nx, ny, 77, t_on=1.0, sides=(side, [EAST, WEST, NORTH, SOUTH][side]))
+    sc.h0[:] = 0
+    sc.extra["qx0"][:] = 0
+    sc.extra["qy0"][:] = 0
+    f = fl.from_scenario(sc, "f32", cells_per_lane=cpt, rows_per_item=rows, active_tiles=True)
+    f.step(10)                                  # 0.5 s: the inflow is still zero
+    nxt, tot = f.active_items()
+    wo = 64 * cpt - 4
+    ns, nc = -(-nx // wo), -(-ny // rows)
+    assert tot == ns * nc
+    s_in, first, count = sc.inflow[0], sc.inflow[1], sc.inflow[2]
+    if s_in in (WEST, EAST):
+        pinned = len({j // rows for j in range(first, first + count)})
+    else:
+        pinned = len({i // wo for i in range(first, first + count)})
+    assert nxt == pinned, (nxt, pinned)
+    assert not f.get_depth().any()
+    f.close()
+    chunks = [10, 30, 100]
+    ref = _run(sc, "f32", chunks, False, (cpt, rows))
+    got = _run(sc, "f32", chunks, True, (cpt, rows))
+    _same(got, ref, f"side {side}")
+    assert got[-1][0].max() > 0.01
+
+
+def test_dry_closed_grid_computes_nothing():
+    nx, ny = 300, 64
+    z = synth._f32(np.random.default_rng(3).uniform(0, 1, (ny, nx)))
+    n = np.full((ny, nx), 0.03, np.float32)
+    sc = Scenario("dry", nx, ny, 1.0, z, n, np.zeros_like(z), None, None, dt_max=0.05)
+    f = fl.from_scenario(sc, "f32", cells_per_lane=2, rows_per_item=8, active_tiles=True)
+    nxt, tot = f.active_items()
+    assert nxt == tot                           # before any step: everything
+    f.step(1)
+    assert f.active_items()[0] == tot           # the item's own flag two steps back is still 1
+    f.step(1)
+    assert f.active_items()[0] == 0
+    f.step(100)
+    assert f.active_items()[0] == 0
+    r = f.get_report()
+    assert r.steps == 102 and not f.get_depth().any()
+    f.close()
+
+
+def test_state_handed_between_paths():
+    """Skipping steps, then a batch run, frozen tiling trials, fl_advance and
+    skipping steps again: the flags are refreshed whenever another path moved
+    the state."""
+    sc = patchy(180, 70, 5)
+    ref = _run(sc, "f32", [5, 20, 7, 3.0, 40], False, (1, 4))
+    f = fl.from_scenario(sc, "f32", cells_per_lane=1, rows_per_item=4, active_tiles=True)
+    f.step(5)
+    b = fl.Batch([f])
+    b.run(20)
+    b.close()
+    f.autotune([(1, 4), (2, 3), (1, 2)], 3)      # frozen trial steps, then a new tiling
+    f.step(7)
+    f.advance(3.0)
+    f.step(40)
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    r = f.get_report(check=False)
+    f.close()
+    _same([(h, qx, qy, r)], [ref[-1]], "handed")
+
+
+def test_reverse_mode_forward_with_active_tiles():
+    """The forward of reverse mode steps with skipping; its series, loss and
+    gradients equal those of a context without."""
+    sc = patchy(120, 60, 9)
+    sc.dt_fixed = 0.05
+    rng = np.random.default_rng(4)
+    gauges = rng.choice(sc.nx * sc.ny, 20, replace=False).astype(np.int32)
+    res = []
+    for active in (False, True):
+        f = fl.from_scenario(sc, "f64", active_tiles=active)
+        f.adj_setup(gauges, 10, np.zeros((6, 20)), 0)
+        series, loss = f.adj_forward(60)
+        gn, gq = f.adj_backward(nsamples=3)
+        f.step(5)                                # stepping continues after the sweep
+        res.append((series, loss, gn, gq, f.get_depth()))
+        f.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_two_steps_per_launch_rejected():
+    sc = config_d1()
+    f = fl.from_scenario(sc, "f32", fusion=2, active_tiles=True, commit=False)
+    assert fl.lib().fl_commit(f.ctx) == fl.FL_EINVAL
+    f.set_fusion(1)
+    f.commit()
+    f.step(3)
+    f.close()
+
+
+def test_workspace_holds_the_flags():
+    import torch
+    sc = config_d1()
+    f = fl.from_scenario(sc, "f32", active_tiles=True, commit=False)
+    need = f.workspace_bytes(active_tiles=True)
+    assert need > f.workspace_bytes()
+    small = torch.empty(f.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    f.bind_workspace(small)
+    assert fl.lib().fl_commit(f.ctx) == fl.FL_EINVAL
+    buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+    f.bind_workspace(buf)
+    f.commit()
+    f.step(300)
+    h = f.get_depth()
+    f.close()
+    ref = _run(sc, "f32", [300], False)[-1][0]
+    assert np.array_equal(h, ref)
