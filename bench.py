@@ -196,6 +196,54 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
             "adjoint_vs_best_plain": round((min(plain_ms, plain2_ms) / 1e3) / (t2 - t0), 4)}
 
 
+# (cells per lane, rows per work item) the active-tile autotuner tries: small
+# items when few hold water (the march of one item is then the step's
+# critical path), large ones when many do
+ACTIVE_TILINGS = [(4, 32), (4, 16), (2, 16), (4, 8), (2, 8)]
+
+
+def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_depth=None,
+               sample_every: int = 50):
+    """The same workload with active-tile skipping (one step per launch, the
+    tiling autotuned on the state after the warm-up, outside the timed
+    region): time per step, the work items computed (read back every
+    `sample_every` steps in a second, untimed run) and whether the final depth
+    equals that of the run that computes every item."""
+    cells = sc.nx * sc.ny
+    stream = torch.cuda.current_stream().cuda_stream
+    f = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True)
+    f.step(warmup)
+    best, _ = f.autotune(ACTIVE_TILINGS, 20)
+    torch.cuda.synchronize()
+    ms = f.time_steps(steps)
+    end_items, total = f.active_items()
+    rep = f.get_report()
+    same = None
+    if full_depth is not None:
+        h = torch.empty_like(full_depth)
+        f.get_depth(h)
+        same = bool(torch.equal(h, full_depth))
+        del h
+    f.close()
+    progress("active tiles: timed; sampling computed items")
+    g = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True,
+                         cells_per_lane=best[0], rows_per_item=best[1])
+    g.step(warmup)
+    counts = []
+    for _ in range(steps // sample_every):
+        g.step(sample_every)
+        counts.append(g.active_items()[0])
+    g.close()
+    value = cells * steps / (ms / 1e3) / 1e9
+    return {"steps_per_launch": 1, "tiling_autotuned": list(best), "ms_per_step": round(ms / steps, 5),
+            "gcell_s_grid_equivalent": round(value, 3),
+            "vs_full_grid_headline": round(value / full_value, 2),
+            "items_per_step": total, "items_computed_last_step": end_items,
+            "items_computed_mean_sampled": round(float(sum(counts)) / max(1, len(counts)), 1),
+            "sample_every_steps": sample_every,
+            "same_depth_as_full_grid": same, "budget_error": rep.budget_error()}
+
+
 def run_sweep(fl, torch, steps: int = 4000, nx: int = 1024, members: int = 16):
     """Flooded extent against discharge: one 1024^2 valley at 5 m, constant inflows
     from 25 to 1600 m^3/s (geometric), fixed dt 0.25 s; the members run in one
@@ -211,7 +259,13 @@ def run_sweep(fl, torch, steps: int = 4000, nx: int = 1024, members: int = 16):
     out = discharge_sweep(z, n, v.dx, (synth.WEST, first, count, 5e-4),
                           (synth.EAST, 0, nx, 5e-4), qs, steps, 0.25,
                           stream=torch.cuda.current_stream().cuda_stream)
+    progress("discharge sweep: members one after another with active tiles")
+    act = discharge_sweep(z, n, v.dx, (synth.WEST, first, count, 5e-4),
+                          (synth.EAST, 0, nx, 5e-4), qs, steps, 0.25, mode="sequential",
+                          active_tiles=True, stream=torch.cuda.current_stream().cuda_stream)
     cells = nx * nx * members
+    gcell = cells * steps / (out["ms"] / 1e3) / 1e9
+    gcell_act = cells * steps / (act["ms"] / 1e3) / 1e9
     return {"grid": f"{nx}x{nx}", "dx_m": 5.0, "members": members, "steps": steps,
             "simulated_s": out["seconds"], "threshold_m": out["threshold"],
             "discharge_m3s": [round(q, 1) for q in qs],
@@ -219,7 +273,13 @@ def run_sweep(fl, torch, steps: int = 4000, nx: int = 1024, members: int = 16):
             "max_depth_m": [round(float(h), 3) for h in out["max_depth"]],
             "max_budget_error": float(out["budget_error"].max()),
             "mode": out["mode"],
-            "gcell_s": round(cells * steps / (out["ms"] / 1e3) / 1e9, 3)}
+            "gcell_s": round(gcell, 3),
+            "active_tiles_gcell_s_grid_equivalent": round(gcell_act, 3),
+            "active_tiles_vs_gcell_s": round(gcell_act / gcell, 2),
+            "active_tiles_same_results": bool(
+                np.array_equal(act["flooded_cells"], out["flooded_cells"]) and
+                np.array_equal(act["max_depth"], out["max_depth"]) and
+                np.array_equal(act["v_in"], out["v_in"]) and np.array_equal(act["v_out"], out["v_out"]))}
 
 
 def main():
@@ -246,6 +306,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=5000)
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the discharge sweep (16 discharges on a 1024^2 valley, one batch)")
+    ap.add_argument("--no-active", action="store_true",
+                    help="skip the same workload with active-tile (wet-region) skipping")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint comparison (1024^2, 5000 steps)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -268,7 +330,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     cells = sc.nx * sc.ny
 
-    def run_timed(scn, fusion=args.fusion):
+    def run_timed(scn, fusion=args.fusion, keep_depth=False):
         tiling = dict(cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item)
         if fusion == 2:
             tiling = dict(fusion=(2, args.cells_per_lane, args.rows_per_item))
@@ -283,11 +345,17 @@ def main():
         wall = time.perf_counter() - w0
         rep = f.get_report()
         dev_bytes = f.device_bytes()
+        depth = None
+        if keep_depth:
+            depth = torch.empty((scn.ny, scn.nx), dtype=torch.float32 if args.precision == "f32"
+                                else torch.float64, device="cuda")
+            f.get_depth(depth)
         f.close()
-        return ev_ms, wall, rep, dev_bytes
+        return ev_ms, wall, rep, dev_bytes, depth
 
     progress(f"inputs ready ({t_gen:.1f} s); timing {args.steps} steps")
-    ev_ms, wall, rep, dev_bytes = run_timed(sc)
+    keep = not args.no_active and args.precision == "f32"
+    ev_ms, wall, rep, dev_bytes, full_depth = run_timed(sc, keep_depth=keep)
     progress(f"timed: {ev_ms / args.steps:.4f} ms/step")
     ms_step = ev_ms / args.steps
     value = cells * args.steps / (ev_ms / 1e3) / 1e9
@@ -328,17 +396,31 @@ def main():
               "sim_time_s": rep.t, "kernel_sha256_16": kernel_hash()}
     other = 3 - args.fusion
     if not args.no_compare:
-        ev1, _, rep1, _ = run_timed(sc, other)
+        ev1, _, rep1, _, _ = run_timed(sc, other)
         extras[f"steps_per_launch_{other}_gcell_s"] = round(cells * args.steps / (ev1 / 1e3) / 1e9, 3)
         extras[f"steps_per_launch_{other}_same_clock"] = (rep1.t == rep.t and rep1.steps == rep.steps)
+    if keep:
+        progress("active tiles")
+        extras["active_tiles"] = run_active(fl, torch, sc, args.warmup, args.steps, value, full_depth)
+    del full_depth
     if args.extra_wet and args.workload == "valley16384":
         import synth
         del sc
         scw = synth.config_d3(16384, wet=True)
         for fu in ((args.fusion,) if args.no_compare else (args.fusion, other)):
-            ev2, _, rep2, _ = run_timed(scw, fu)
+            ev2, _, rep2, _, _ = run_timed(scw, fu)
             extras[f"prewetted_steps_per_launch_{fu}_gcell_s"] = round(
                 cells * args.steps / (ev2 / 1e3) / 1e9, 3)
+        if not args.no_active and args.precision == "f32":
+            f = fl.from_scenario(scw, "f32", device=0, stream=torch.cuda.current_stream().cuda_stream,
+                                 active_tiles=True)
+            f.step(args.warmup)
+            best3, _ = f.autotune(ACTIVE_TILINGS, 20)
+            ev3 = f.time_steps(args.steps)
+            extras["prewetted_active_tiles_tiling_autotuned"] = list(best3)
+            extras["prewetted_active_tiles_items_computed"] = list(f.active_items())
+            f.close()
+            extras["prewetted_active_tiles_gcell_s"] = round(cells * args.steps / (ev3 / 1e3) / 1e9, 3)
         sc = scw
     if not args.no_ensemble:
         progress("ensemble")

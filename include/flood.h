@@ -275,9 +275,12 @@ fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
  * trial_steps frozen steps (dt = 0: the state is streamed like a real step but
  * left unchanged) and keep the fastest for the following steps (the captured
- * graph is rebuilt).  best[2] receives it, *best_ms its time per step.  The
- * state, clock and budget are unchanged.  ESTATE before commit; EINVAL: a
- * candidate fl_set_tiling would reject. */
+ * graph is rebuilt).  With active tiles on, the trial steps skip work items as
+ * real steps would, so the choice fits the current wet extent (small items
+ * when few items hold water, large ones when many do); call it again as the
+ * flood grows.  best[2] receives it, *best_ms its time per step.  The state,
+ * clock and budget are unchanged.  ESTATE before commit; EINVAL: a candidate
+ * fl_set_tiling would reject. */
 fl_status fl_autotune(fl_ctx *ctx, const int32_t *candidates, int32_t ncand, int32_t trial_steps,
                       int32_t *best, double *best_ms);
 

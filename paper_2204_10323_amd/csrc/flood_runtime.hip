@@ -1098,12 +1098,29 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
     for (int k = 0; k < ncand; ++k) {
         const Tiling t = tiling_of(c, candidates[2 * k], candidates[2 * k + 1]);
         float ms = 0.f;
-        // frozen steps (dt = 0): the state is streamed like a real step but unchanged
+        // frozen steps (dt = 0): the state is streamed like a real step but
+        // unchanged.  With active tiles they skip as real steps would: the
+        // first two (untimed) compute every item and leave the flags of this
+        // tiling, which mark the items that hold water or discharge.
+        if (c->active) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
         for (int r = 0; r < 2 + trial_steps; ++r) {
             if (r == 2) HIP_TRY(c, hipEventRecord(e0, c->stream));
-            hipError_t e = c->prec == FL_F64
-                               ? launch_step<double>(make_args<double>(c, c->nstep, t, 1), t.cpt, c->stream)
-                               : launch_step<float>(make_args<float>(c, c->nstep, t, 1), t.cpt, c->stream);
+            hipError_t e;
+            if (c->prec == FL_F64) {
+                StepArgs<double> a = make_args<double>(c, c->nstep, t, 1);
+                if (c->active) {
+                    a.act = c->d_act;
+                    a.act_stride = c->act_stride;
+                }
+                e = launch_step<double>(a, t.cpt, c->stream);
+            } else {
+                StepArgs<float> a = make_args<float>(c, c->nstep, t, 1);
+                if (c->active) {
+                    a.act = c->d_act;
+                    a.act_stride = c->act_stride;
+                }
+                e = launch_step<float>(a, t.cpt, c->stream);
+            }
             if (e != hipSuccess) return hip_fail(c, e, "fl_autotune trial");
             c->nstep += 1;
         }
@@ -1131,6 +1148,7 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
     c->graph_exec = nullptr;
     c->graph = nullptr;
     if ((st = capture_graph(c))) return st;
+    c->act_at = -1;  // the flags describe the last candidate's items
     if (best) {
         best[0] = c->cpt;
         best[1] = c->rows;

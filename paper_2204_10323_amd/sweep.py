@@ -25,7 +25,7 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
                     dt: float, threshold: float = 0.1, precision: str = "f32", device: int = 0,
                     stream=None, h0: Optional[np.ndarray] = None, keep_depths: bool = False,
                     tiling: Optional[tuple] = None, trial_steps: int = 10, mode: str = "auto",
-                    **params) -> dict:
+                    active_tiles: bool = False, **params) -> dict:
     """Run one member per discharge (m^3/s) for `steps` steps of `dt` seconds.
 
     inflow_section: (side, first, count, slope); outflow_section: (side, first,
@@ -38,6 +38,9 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
     the wait between a member's steps.
     tiling: (cells_per_lane, rows_per_item) of the batch launch (mode
     "batch"), or None for the autotuner's choice.
+    active_tiles: members stepped one after another skip the work items that
+    hold no water (fl_set_active_tiles); their tiling is then autotuned with
+    skipping trial steps.  The batch launch computes every item.
     Returns per-member arrays: flooded cell count and area, deepest cell,
     inflow and outflow volume, relative volume-budget error, and the depths if
     keep_depths; the mode used and its time in milliseconds.
@@ -62,6 +65,8 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
             f.set_params(dt_fixed=dt, **params)
             if h0 is not None:
                 f.set_state(h0, None, None, 0.0)
+            if active_tiles:
+                f.set_active_tiles(True)
             f.commit()
         fp64 = precision in ("f64", "fp64", "double")
         single_cands = [t for t in SINGLE_TILINGS if not fp64 or t[0] < 4]

@@ -93,3 +93,15 @@ def test_sweep_modes_agree():
     for hb, hs in zip(b["depth"], s["depth"]):
         assert np.array_equal(hb, hs)
     assert np.array_equal(b["v_in"], s["v_in"])
+
+
+def test_sweep_active_tiles_same_bits():
+    """Members stepped with active-tile skipping give the bits of the batch."""
+    v, z, n, inflow, outflow = _valley()
+    qs = [15.0, 150.0, 600.0]
+    b = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True, mode="batch")
+    a = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True,
+                        mode="sequential", active_tiles=True)
+    for hb, ha in zip(b["depth"], a["depth"]):
+        assert np.array_equal(hb, ha)
+    assert np.array_equal(b["v_in"], a["v_in"]) and np.array_equal(b["v_out"], a["v_out"])
