@@ -41,7 +41,8 @@ class _Problem(C.Structure):
                 ("in_slope", C.c_double), ("nsamp", C.c_int32),
                 ("ts", C.POINTER(C.c_double)), ("qs", C.POINTER(C.c_double)),
                 ("out_side", C.c_int32), ("out_first", C.c_int32), ("out_count", C.c_int32),
-                ("out_slope", C.c_double)]
+                ("out_slope", C.c_double),
+                ("friction_vector", C.c_int32), ("boundary_cell_area", C.c_int32)]
 
 
 class Clock(C.Structure):
@@ -66,6 +67,8 @@ def lib():
         L.orc_volume.restype = C.c_double
         L.orc_inflow_split.argtypes = [C.c_int32, dp, dp, C.c_double, C.c_double, dp]
         L.orc_inflow_split.restype = C.c_double
+        L.orc_inflow_split_area.argtypes = [C.c_int32, dp, dp, C.c_double, C.c_double, dp]
+        L.orc_inflow_split_area.restype = C.c_double
         L.orc_hydrograph.argtypes = [C.c_int32, dp, dp, C.c_double]
         L.orc_hydrograph.restype = C.c_double
         L.orc_face_flux.argtypes = [C.c_double] * 11
@@ -92,7 +95,8 @@ class Run:
     """
 
     def __init__(self, scen, positivity: bool = True, nthreads: int = 0,
-                 n: Optional[np.ndarray] = None, qs: Optional[np.ndarray] = None):
+                 n: Optional[np.ndarray] = None, qs: Optional[np.ndarray] = None,
+                 friction_vector: bool = False, boundary_cell_area: bool = False):
         self.s = scen
         self.nx, self.ny = scen.nx, scen.ny
         self.z = np.ascontiguousarray(scen.z, dtype=np.float64)
@@ -112,6 +116,8 @@ class Run:
         p.g, p.alpha, p.dt_max, p.h_eps = scen.g, scen.alpha, scen.dt_max, scen.h_eps
         p.dt_fixed, p.t_end = scen.dt_fixed, scen.t_end
         p.positivity = 1 if positivity else 0
+        p.friction_vector = 1 if friction_vector else 0
+        p.boundary_cell_area = 1 if boundary_cell_area else 0
         self._keep = []
         if scen.inflow is not None:
             side, first, count, slope, ts, qsamp = scen.inflow
@@ -151,6 +157,16 @@ def inflow_split(zc, kc, dx: float, Q: float):
     kc = np.ascontiguousarray(kc, dtype=np.float64)
     q = np.zeros_like(zc)
     W = lib().orc_inflow_split(len(zc), _dp(zc), _dp(kc), dx, Q, _dp(q))
+    return W, q
+
+
+def inflow_split_area(zc, kc, dx: float, Q: float):
+    """Eq. (6) with eq. (5) taken literally (A = dx^2): returns (W, per-cell
+    face discharge per unit width)."""
+    zc = np.ascontiguousarray(zc, dtype=np.float64)
+    kc = np.ascontiguousarray(kc, dtype=np.float64)
+    q = np.zeros_like(zc)
+    W = lib().orc_inflow_split_area(len(zc), _dp(zc), _dp(kc), dx, Q, _dp(q))
     return W, q
 
 

@@ -29,6 +29,18 @@
  *     the last step shortened to t_end;
  *   - Q_in is evaluated at the start of the step, piecewise linear in the
  *     hydrograph samples and constant beyond them; W by 64 bisections.
+ * Two method variants, off by default, check how much results depend on two
+ * of these readings:
+ *   - friction_vector: |q| in the friction term of eq. (3) is the magnitude
+ *     of the discharge vector at the face, sqrt(q^2 + q_perp^2), where q_perp
+ *     is the mean of the start-of-step discharges on the perpendicular faces
+ *     of the two cells beside the face (four faces; those on the border of
+ *     the grid are left out of the mean).  This is the vector norm eq. (2)
+ *     writes, instead of the per-axis 1-D form;
+ *   - boundary_cell_area: eq. (5) and (6) taken literally, A = dx^2 and the
+ *     hydraulic radius = the depth, so a boundary cell passes
+ *     Q_c = dx^2 h^{2/3} sqrt(S) / n, i.e. q = dx h^{2/3} sqrt(S) / n per unit
+ *     width of its border face.
  *
  * Layout (this file's own): h, z, n are [ny][nx]; qx is [ny][nx+1] with
  * qx[j][i] the face between cells i-1 and i (i = 0 the west border, i = nx
@@ -52,6 +64,14 @@ static double pow53(double x)
     if (!(x > 0.0)) return 0.0;
     double c = cbrt(x);
     return x * (c * c);
+}
+
+/* x^(2/3) for x > 0, else 0. */
+static double pow23(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    double c = cbrt(x);
+    return c * c;
 }
 
 /* Hydrograph Q_in(t): piecewise linear, constant outside the samples. */
@@ -98,6 +118,40 @@ double orc_inflow_split(int32_t nc, const double *zc, const double *kc, double d
     return W;
 }
 
+/*
+ * Eq. (6) with eq. (5) taken literally (variant boundary_cell_area): each cell
+ * passes Q_c = dx^2 kc (W - z_c)_+^{2/3}; the sum is continuous and strictly
+ * increasing above min z.  At W = max z + (Q / (dx^2 sum kc))^{3/2} every cell
+ * passes at least its share, so that bounds W from above; 64 bisections.
+ * Writes the per-unit-width face discharge Q_c / dx of every cell into q_out
+ * and returns W.
+ */
+double orc_inflow_split_area(int32_t nc, const double *zc, const double *kc, double dx,
+                             double Q, double *q_out)
+{
+    if (nc <= 0) return 0.0;
+    if (!(Q > 0.0)) {
+        for (int32_t c = 0; c < nc; c++) q_out[c] = 0.0;
+        return zc[0];
+    }
+    double lo = zc[0], hi = zc[0], ksum = 0.0;
+    for (int32_t c = 0; c < nc; c++) {
+        if (zc[c] < lo) lo = zc[c];
+        if (zc[c] > hi) hi = zc[c];
+        ksum += kc[c];
+    }
+    hi += pow(Q / (dx * dx * ksum), 1.5);
+    for (int it = 0; it < 64; it++) {
+        double mid = 0.5 * (lo + hi), F = 0.0;
+        for (int32_t c = 0; c < nc; c++) F += dx * (dx * kc[c] * pow23(mid - zc[c]));
+        F -= Q;
+        if (F < 0.0) lo = mid; else hi = mid;
+    }
+    double W = 0.5 * (lo + hi);
+    for (int32_t c = 0; c < nc; c++) q_out[c] = dx * kc[c] * pow23(W - zc[c]);
+    return W;
+}
+
 /* Cell (i, j) of entry k of a boundary section on `side`. */
 static void side_cell(const orc_problem *p, int32_t side, int32_t k, int32_t *i, int32_t *j)
 {
@@ -124,10 +178,11 @@ static double *side_face(const orc_problem *p, double *qx, double *qy, int32_t s
 
 /*
  * Eq. (3) on one interior face between cells L and R (R on the +axis side).
- * q is the face's discharge at the start of the step.
+ * q is the face's discharge at the start of the step, qm the discharge
+ * magnitude in the friction term.
  */
-double orc_face_flux(double hL, double hR, double zL, double zR, double nL, double nR,
-                     double q, double dx, double dt, double g, double h_eps)
+static double face_flux_m(double hL, double hR, double zL, double zR, double nL, double nR,
+                          double q, double qm, double dx, double dt, double g, double h_eps)
 {
     double etaL = hL + zL, etaR = hR + zR;
     double hf = fmax(etaL, etaR) - fmax(zL, zR);
@@ -135,8 +190,44 @@ double orc_face_flux(double hL, double hR, double zL, double zR, double nL, doub
     double nf = 0.5 * (nL + nR);
     double grad = (etaR - etaL) / dx;
     double num = q - ((g * hf) * dt) * grad;
-    double den = 1.0 + (((g * dt) * (nf * nf)) * fabs(q)) / ((hf * hf) * cbrt(hf));
+    double den = 1.0 + (((g * dt) * (nf * nf)) * qm) / ((hf * hf) * cbrt(hf));
     return num / den;
+}
+
+/* Eq. (3) with the face's own |q| in the friction term (the 1-D form). */
+double orc_face_flux(double hL, double hR, double zL, double zR, double nL, double nR,
+                     double q, double dx, double dt, double g, double h_eps)
+{
+    return face_flux_m(hL, hR, zL, zR, nL, nR, q, fabs(q), dx, dt, g, h_eps);
+}
+
+/* Variant friction_vector: mean of the start-of-step y-discharges on the
+ * faces of the two cells beside the x-face qx[j][i] (faces qy[jj][i-1] and
+ * qy[jj][i] for jj = j, j + 1), border faces left out. */
+static double perp_mean_x(const double *qy0, int64_t nx, int64_t ny, int64_t i, int64_t j)
+{
+    double s = 0.0;
+    int k = 0;
+    for (int64_t jj = j; jj <= j + 1; jj++) {
+        if (jj < 1 || jj > ny - 1) continue;
+        s += qy0[jj * nx + i - 1] + qy0[jj * nx + i];
+        k += 2;
+    }
+    return k ? s / k : 0.0;
+}
+
+/* The same for the y-face qy[j][i]: x-discharges on the faces qx[j-1][ii] and
+ * qx[j][ii] for ii = i, i + 1 (the west and east faces of the two cells). */
+static double perp_mean_y(const double *qx0, int64_t nx, int64_t i, int64_t j)
+{
+    double s = 0.0;
+    int k = 0;
+    for (int64_t ii = i; ii <= i + 1; ii++) {
+        if (ii < 1 || ii > nx - 1) continue;
+        s += qx0[(j - 1) * (nx + 1) + ii] + qx0[j * (nx + 1) + ii];
+        k += 2;
+    }
+    return k ? s / k : 0.0;
 }
 
 static int orc_threads(int nthreads)
@@ -177,20 +268,48 @@ int orc_one_step(const orc_problem *p, const double *z, const double *n,
     }
 
     /* Eq. (3) on every interior face (q^n read and q* written in place). */
+    if (!p->friction_vector) {
 #pragma omp parallel for num_threads(nth) schedule(static)
-    for (int64_t j = 0; j < ny; j++) {
-        for (int64_t i = 1; i < nx; i++) {
-            int64_t L = j * nx + i - 1, R = j * nx + i;
-            double *q = &qx[j * (nx + 1) + i];
-            *q = orc_face_flux(h[L], h[R], z[L], z[R], n[L], n[R], *q, dx, dt, g, p->h_eps);
-        }
-        if (j >= 1) {
-            for (int64_t i = 0; i < nx; i++) {
-                int64_t L = (j - 1) * nx + i, R = j * nx + i;
-                double *q = &qy[j * nx + i];
+        for (int64_t j = 0; j < ny; j++) {
+            for (int64_t i = 1; i < nx; i++) {
+                int64_t L = j * nx + i - 1, R = j * nx + i;
+                double *q = &qx[j * (nx + 1) + i];
                 *q = orc_face_flux(h[L], h[R], z[L], z[R], n[L], n[R], *q, dx, dt, g, p->h_eps);
             }
+            if (j >= 1) {
+                for (int64_t i = 0; i < nx; i++) {
+                    int64_t L = (j - 1) * nx + i, R = j * nx + i;
+                    double *q = &qy[j * nx + i];
+                    *q = orc_face_flux(h[L], h[R], z[L], z[R], n[L], n[R], *q, dx, dt, g, p->h_eps);
+                }
+            }
         }
+    } else {
+        /* the perpendicular discharges are read from a copy of q^n */
+        double *qx0 = malloc(sizeof(double) * (size_t)(ny * (nx + 1)));
+        double *qy0 = malloc(sizeof(double) * (size_t)((ny + 1) * nx));
+        if (!qx0 || !qy0) { free(qx0); free(qy0); return 2; }
+        memcpy(qx0, qx, sizeof(double) * (size_t)(ny * (nx + 1)));
+        memcpy(qy0, qy, sizeof(double) * (size_t)((ny + 1) * nx));
+#pragma omp parallel for num_threads(nth) schedule(static)
+        for (int64_t j = 0; j < ny; j++) {
+            for (int64_t i = 1; i < nx; i++) {
+                int64_t L = j * nx + i - 1, R = j * nx + i;
+                double q = qx0[j * (nx + 1) + i], qp = perp_mean_x(qy0, nx, ny, i, j);
+                qx[j * (nx + 1) + i] = face_flux_m(h[L], h[R], z[L], z[R], n[L], n[R], q,
+                                                   sqrt(q * q + qp * qp), dx, dt, g, p->h_eps);
+            }
+            if (j >= 1) {
+                for (int64_t i = 0; i < nx; i++) {
+                    int64_t L = (j - 1) * nx + i, R = j * nx + i;
+                    double q = qy0[j * nx + i], qp = perp_mean_y(qx0, nx, i, j);
+                    qy[j * nx + i] = face_flux_m(h[L], h[R], z[L], z[R], n[L], n[R], q,
+                                                 sqrt(q * q + qp * qp), dx, dt, g, p->h_eps);
+                }
+            }
+        }
+        free(qx0);
+        free(qy0);
     }
 
     /* Border faces: closed walls unless an inflow or outflow section sets them. */
@@ -210,7 +329,8 @@ int orc_one_step(const orc_problem *p, const double *z, const double *n,
             kc[k] = sqrt(p->in_slope) / n[(int64_t)j * nx + i];
         }
         double Q = orc_hydrograph(p->nsamp, p->ts, p->qs, clk->t);
-        orc_inflow_split(nc, zc, kc, dx, Q, qc);
+        if (p->boundary_cell_area) orc_inflow_split_area(nc, zc, kc, dx, Q, qc);
+        else orc_inflow_split(nc, zc, kc, dx, Q, qc);
         for (int32_t k = 0; k < nc; k++) {
             int32_t i, j;
             double inward;
@@ -228,7 +348,9 @@ int orc_one_step(const orc_problem *p, const double *z, const double *n,
             double inward;
             side_cell(p, p->out_side, p->out_first + k, &i, &j);
             int64_t c = (int64_t)j * nx + i;
-            double q = sqrt(p->out_slope) / n[c] * pow53(fmax(h[c], 0.0));
+            double hc = fmax(h[c], 0.0);
+            double q = sqrt(p->out_slope) / n[c] *
+                       (p->boundary_cell_area ? dx * pow23(hc) : pow53(hc));
             double *f = side_face(p, qx, qy, p->out_side, i, j, &inward);
             *f = -inward * q;
         }

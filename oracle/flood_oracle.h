@@ -14,6 +14,9 @@ typedef struct {
     const double *ts, *qs;           /* hydrograph samples (s, m^3/s) */
     int32_t out_side, out_first, out_count;
     double out_slope;
+    /* method variants (0 = the readings in flood_oracle.c's header) */
+    int32_t friction_vector;         /* 1: |q| in eq. (3) is the discharge vector's magnitude */
+    int32_t boundary_cell_area;      /* 1: A in eq. (5)/(6) is the cell area dx^2 */
 } orc_problem;
 
 typedef struct {
@@ -30,6 +33,8 @@ int orc_one_step(const orc_problem *p, const double *z, const double *n, double 
 double orc_hydrograph(int32_t ns, const double *ts, const double *qs, double t);
 double orc_inflow_split(int32_t nc, const double *zc, const double *kc, double dx, double Q,
                         double *q_out);
+double orc_inflow_split_area(int32_t nc, const double *zc, const double *kc, double dx, double Q,
+                             double *q_out);
 double orc_face_flux(double hL, double hR, double zL, double zR, double nL, double nR, double q,
                      double dx, double dt, double g, double h_eps);
 

@@ -311,6 +311,8 @@ int orc_adj_run(const orc_problem *p, const double *z, const double *n, const do
                 double *series, double *loss, double *grad_n, double *grad_q, int32_t nthreads)
 {
     if (!p || !(p->dt_fixed > 0.0) || nsteps < 0 || obs_every < 1) return 1;
+    /* the reverse is derived for the default readings only */
+    if (p->friction_vector || p->boundary_cell_area) return 1;
     const int64_t nx = p->nx, ny = p->ny, nc = nx * ny;
     const int64_t nqx = ny * (nx + 1), nqy = (ny + 1) * nx;
     const int64_t nobs = nsteps / obs_every;

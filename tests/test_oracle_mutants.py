@@ -42,6 +42,27 @@ MUTANTS = {
 }
 
 
+# Mistakes planted in the two method variants; their pins must catch them.
+VAR_MUTANTS = {
+    "vector_mean_rows_shifted": ("for (int64_t jj = j; jj <= j + 1; jj++) {",
+                                 "for (int64_t jj = j - 1; jj <= j; jj++) {"),
+    "vector_mean_columns_shifted": ("for (int64_t ii = i; ii <= i + 1; ii++) {",
+                                    "for (int64_t ii = i - 1; ii <= i; ii++) {"),
+    "vector_mean_counts_border_faces": ("if (jj < 1 || jj > ny - 1) continue;",
+                                        "if (jj < 0 || jj > ny) continue;"),
+    "vector_uses_own_component_only": ("sqrt(q * q + qp * qp), dx, dt, g, p->h_eps);\n            }\n            if",
+                                       "fabs(q), dx, dt, g, p->h_eps);\n            }\n            if"),
+    "cell_area_outflow_exponent_5_3": ("(p->boundary_cell_area ? dx * pow23(hc) : pow53(hc));",
+                                       "(p->boundary_cell_area ? dx * pow53(hc) : pow53(hc));"),
+    "cell_area_outflow_factor_dropped": ("(p->boundary_cell_area ? dx * pow23(hc) : pow53(hc));",
+                                         "(p->boundary_cell_area ? pow23(hc) : pow53(hc));"),
+    "cell_area_inflow_face_factor_dropped": ("q_out[c] = dx * kc[c] * pow23(W - zc[c]);",
+                                             "q_out[c] = kc[c] * pow23(W - zc[c]);"),
+    "cell_area_inflow_sum_one_dx": ("F += dx * (dx * kc[c] * pow23(mid - zc[c]));",
+                                    "F += dx * kc[c] * pow23(mid - zc[c]);"),
+}
+
+
 # Mistakes planted in the reverse-mode sweep; the finite-difference pins must catch them.
 ADJ_SRC = os.path.join(ROOT, "oracle", "flood_oracle_adjoint.c")
 ADJ_MUTANTS = {
@@ -82,6 +103,13 @@ def _build_and_run_pins(tmp_path, src_path, old, new, pins, name):
 def test_pins_catch_mutant(name, tmp_path):
     old, new = MUTANTS[name]
     _build_and_run_pins(tmp_path, SRC, old, new, "test_oracle_pins.py", name)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(VAR_MUTANTS))
+def test_variant_pins_catch_mutant(name, tmp_path):
+    old, new = VAR_MUTANTS[name]
+    _build_and_run_pins(tmp_path, SRC, old, new, "test_oracle_variants.py", name)
 
 
 @pytest.mark.slow
