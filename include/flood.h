@@ -247,6 +247,30 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
 fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per_lane,
                         int32_t rows_per_item);
 
+/* Method variants, to check how much results depend on two readings of the
+ * paper (Methods, "Shallow Water Equations").  Defaults: FL_FRICTION_FACE, the
+ * face's own |q| in the friction term of eq. (3) (the per-axis 1-D form the
+ * paper describes); FL_BOUNDARY_SECTION, A in eq. (5)/(6) is the face's
+ * cross-section dx*h, so a boundary cell passes h^{5/3} sqrt(S)/n per unit
+ * width (the steady state of eq. 3 itself).
+ *   FL_FRICTION_VECTOR: |q| is the magnitude of the discharge vector at the
+ *     face (the vector norm of eq. 2), sqrt(q^2 + q_perp^2), where q_perp is
+ *     the mean of the start-of-step discharges on the perpendicular faces of
+ *     the two cells beside the face; faces on the border of the grid are left
+ *     out of the mean (4 faces inside, 2 along the border).
+ *   FL_BOUNDARY_CELL_AREA: eq. (5)/(6) as printed, A = dx^2 and the hydraulic
+ *     radius = the depth: a boundary cell passes dx^2 h^{2/3} sqrt(S)/n, i.e.
+ *     dx h^{2/3} sqrt(S)/n per unit width of its face; W of eq. (6) is then
+ *     bisected 64 times in FP64.
+ * Variants run one step per launch (fl_step, fl_advance, fl_time_steps,
+ * fl_autotune); fl_commit fails with EINVAL with two steps per launch or
+ * active tiles, fl_batch_create with a member that has a variant, and
+ * fl_adj_setup on such a context.  Takes effect at the next fl_commit.
+ * EINVAL: an unknown value. */
+typedef enum { FL_FRICTION_FACE = 0, FL_FRICTION_VECTOR = 1 } fl_friction;
+typedef enum { FL_BOUNDARY_SECTION = 0, FL_BOUNDARY_CELL_AREA = 1 } fl_boundary;
+fl_status fl_set_variant(fl_ctx *ctx, int32_t friction, int32_t boundary);
+
 /* Active-tile skipping (wet-region skipping) for fl_step, fl_time_steps,
  * fl_advance and the forward of reverse mode, with one step per launch: a
  * step does not recompute a work item when the item and the four items that

@@ -19,6 +19,8 @@ LIB_PATH = os.environ.get("FLOOD_LIB") or os.path.join(_HERE, "libflood.so")
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ESTATE, FL_ENONFINITE = range(6)
 FL_F32, FL_F64 = 0, 1
 FL_WEST, FL_EAST, FL_SOUTH, FL_NORTH = range(4)
+FL_FRICTION_FACE, FL_FRICTION_VECTOR = 0, 1
+FL_BOUNDARY_SECTION, FL_BOUNDARY_CELL_AREA = 0, 1
 STATUS_NAMES = {0: "FL_OK", 1: "FL_EINVAL", 2: "FL_ENOMEM", 3: "FL_EHIP", 4: "FL_ESTATE",
                 5: "FL_ENONFINITE"}
 
@@ -32,7 +34,7 @@ EXPORTS = [
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
     "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state", "fl_autotune_fusion",
-    "fl_set_active_tiles", "fl_active_items",
+    "fl_set_active_tiles", "fl_active_items", "fl_set_variant",
 ]
 
 
@@ -121,6 +123,7 @@ def lib() -> C.CDLL:
             "fl_get_state": (C.c_int, [vp, vp, vp, vp, C.POINTER(dbl), C.c_int]),
             "fl_autotune_fusion": (C.c_int, [vp, i32, C.POINTER(i32), C.POINTER(dbl)]),
             "fl_set_active_tiles": (C.c_int, [vp, i32]),
+            "fl_set_variant": (C.c_int, [vp, i32, i32]),
             "fl_active_items": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
@@ -250,6 +253,15 @@ class Flood:
         """Steps per launch (1 or 2) and the two-step kernel's tiling (fl_set_fusion)."""
         _check(self.ctx, lib().fl_set_fusion(self.ctx, steps_per_launch, cells_per_lane,
                                              rows_per_item))
+
+    def set_variant(self, friction: str = "face", boundary: str = "section"):
+        """Method variant (fl_set_variant): friction "face" (default) or "vector";
+        boundary "section" (default) or "cell_area"."""
+        fr = {"face": FL_FRICTION_FACE, "vector": FL_FRICTION_VECTOR}.get(friction)
+        bd = {"section": FL_BOUNDARY_SECTION, "cell_area": FL_BOUNDARY_CELL_AREA}.get(boundary)
+        if fr is None or bd is None:
+            raise ValueError("set_variant: friction 'face'|'vector', boundary 'section'|'cell_area'")
+        _check(self.ctx, lib().fl_set_variant(self.ctx, fr, bd))
 
     def set_active_tiles(self, on: bool = True):
         """Active-tile (wet-region) skipping for one step per launch (fl_set_active_tiles)."""
@@ -480,7 +492,7 @@ def fraction_section(length: int, f_start: float, f_end: float):
 
 def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, commit: bool = True,
                   cells_per_lane: int = 0, rows_per_item: int = 0, fusion=None,
-                  active_tiles: bool = False, **param_over) -> Flood:
+                  active_tiles: bool = False, variant=None, **param_over) -> Flood:
     """A committed context for a synthetic scenario (see the `synth` module)."""
     f = Flood(sc.nx, sc.ny, sc.dx, precision, device, stream)
     f.set_dem(sc.z)
@@ -503,6 +515,8 @@ def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, comm
         f.set_fusion(*((fusion,) if isinstance(fusion, int) else tuple(fusion)))
     if active_tiles:
         f.set_active_tiles(True)
+    if variant is not None:
+        f.set_variant(*variant)
     if commit:
         f.commit()
     return f

@@ -59,6 +59,14 @@ __device__ __forceinline__ T pow53(T x) {
     return x * (c * c);
 }
 
+// x^(2/3) for x > 0, else 0 (the literal reading of eq. 5).
+template <typename T>
+__device__ __forceinline__ T pow23(T x) {
+    if (!(x > T(0))) return T(0);
+    T c = cbrt_t(x);
+    return c * c;
+}
+
 // Value held by the next (lane + 1) or previous (lane - 1) lane of the wave,
 // by the wave-wide DPP shifts of GFX9 (wave_shl:1, wave_shr:1): a register
 // move the ALU does in place, no LDS round trip.  The last (first) lane keeps
@@ -187,6 +195,34 @@ __device__ __forceinline__ float face_q<float>(float etaL, float etaR, float zL,
     return num * __builtin_amdgcn_rcpf(den);
 }
 
+// Eq. (3) with the discharge magnitude of the friction term given (qm), for
+// the variant that takes the magnitude of the discharge vector at the face
+// instead of the face's own |q|; same operations as face_q otherwise.
+template <typename T>
+__device__ __forceinline__ T face_qm(T etaL, T etaR, T zL, T zR, T nL, T nR, T q, T qm, T gdt,
+                                     T inv_dx, T h_eps) {
+    T hf = fmax(etaL, etaR) - fmax(zL, zR);
+    if (hf <= h_eps) return T(0);
+    T nf = T(0.5) * (nL + nR);
+    T grad = (etaR - etaL) * inv_dx;
+    T num = q - (gdt * hf) * grad;
+    T den = T(1) + ((gdt * (nf * nf)) * qm) / ((hf * hf) * cbrt_t(hf));
+    return num / den;
+}
+template <>
+__device__ __forceinline__ float face_qm<float>(float etaL, float etaR, float zL, float zR,
+                                                float nL, float nR, float q, float qm, float gdt,
+                                                float inv_dx, float h_eps) {
+    float hf = fmaxf(etaL, etaR) - fmaxf(zL, zR);
+    if (hf <= h_eps) return 0.0f;
+    float nf = 0.5f * (nL + nR);
+    float grad = (etaR - etaL) * inv_dx;
+    float num = q - (gdt * hf) * grad;
+    float m73 = fminf(__builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(hf)), 3.0e38f);
+    float den = 1.0f + ((gdt * (nf * nf)) * qm) * m73;
+    return num * __builtin_amdgcn_rcpf(den);
+}
+
 // Donor-cell factor r = h+/O of a cell whose outflow O exceeds its depth h+.
 template <typename T>
 __device__ __forceinline__ T donor_ratio(T hp, T O) { return hp / O; }
@@ -295,9 +331,37 @@ __device__ inline double inflow_level(const double* in_z, const double* in_k, in
     return W;
 }
 
+// Eq. (6) with eq. (5) taken literally (A = dx^2, hydraulic radius = depth):
+// the level W at which the cells pass dx^2 k_c (W - z_c)_+^{2/3} in total.
+// The sum is concave in W, so it is bisected (64 times, FP64) between min z
+// and max z + (Q / (dx^2 sum k))^{3/2}, where every cell passes at least its
+// share.  One wave.
+__device__ inline double inflow_level_area(const double* in_z, const double* in_k, int nc,
+                                           double dx, double Q) {
+    const int lane = threadIdx.x & 63;
+    double lo = 1e300, hi = -1e300, ks = 0.0;
+    for (int p = lane; p < nc; p += 64) {
+        lo = fmin(lo, in_z[p]);
+        hi = fmax(hi, in_z[p]);
+        ks += in_k[p];
+    }
+    lo = -wave_max(-lo);
+    hi = wave_max(hi);
+    ks = wave_sum(ks);
+    hi += pow(Q / (dx * dx * ks), 1.5);
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double F = 0.0;
+        for (int p = lane; p < nc; p += 64) F += dx * (dx * in_k[p] * pow23(mid - in_z[p]));
+        F = wave_sum(F) - Q;
+        if (F < 0.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 // The inflow split on one wave: per-cell face discharges (per unit width)
 // into dst[first .. first+count).
-template <typename T>
+template <typename T, int VAR = 0>
 __device__ void inflow_solve(const StepArgs<T>& a, double Q, T* dst) {
     const int lane = threadIdx.x & 63;
     const int nc = a.in_count;
@@ -306,8 +370,14 @@ __device__ void inflow_solve(const StepArgs<T>& a, double Q, T* dst) {
         for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = T(0);
         return;
     }
-    const double W = inflow_level(a.in_z, a.in_k, nc, a.dx, Q);
-    for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = (T)(a.in_k[p] * pow53(W - a.in_z[p]));
+    if constexpr ((VAR & VAR_BOUNDARY_CELL_AREA) != 0) {
+        const double W = inflow_level_area(a.in_z, a.in_k, nc, a.dx, Q);
+        for (int p = lane; p < nc; p += 64)
+            dst[a.in_first + p] = (T)(a.dx * a.in_k[p] * pow23(W - a.in_z[p]));
+    } else {
+        const double W = inflow_level(a.in_z, a.in_k, nc, a.dx, Q);
+        for (int p = lane; p < nc; p += 64) dst[a.in_first + p] = (T)(a.in_k[p] * pow53(W - a.in_z[p]));
+    }
 }
 
 

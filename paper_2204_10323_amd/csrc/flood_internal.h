@@ -92,7 +92,12 @@ struct StepArgs {
     // every item is computed every step
     unsigned char* act;
     long long act_stride;         // bytes per slot (>= nstrips * nchunks)
+    // method variant: bit 0 = friction by the discharge vector's magnitude,
+    // bit 1 = boundary cells with the cell area (eq. 5 and 6 taken literally)
+    int variant;
 };
+
+enum { VAR_FRICTION_VECTOR = 1, VAR_BOUNDARY_CELL_AREA = 2 };
 
 // A two-step launch: the grid, boundary data and constants (with the
 // two-step tiling) in `a`; both ping-pong buffers, since the launch decides

@@ -27,7 +27,7 @@ namespace flood {
 // the clock to the end of this step and prepares the inflow of the next step.
 // Runs concurrently with the tiles of this step, which only read the current
 // clock slot.
-template <typename T>
+template <typename T, int VAR = 0>
 __device__ void clock_wave(const StepArgs<T>& a) {
     const int lane = threadIdx.x & 63;
     DevCtl* ctl = a.ctl;
@@ -47,7 +47,7 @@ __device__ void clock_wave(const StepArgs<T>& a) {
     ClockSlot nk = advance_clock(ck, dt, last, done, nonfin, si, a.dx, t_end);
     nk.v_out = ck.v_out + ck.dt_prev * a.dx * so;
 
-    inflow_solve<T>(a, hydrograph<T>(a, nk.t), a.qin_next);
+    inflow_solve<T, VAR>(a, hydrograph<T>(a, nk.t), a.qin_next);
     if (lane == 0) {
         ctl->hmax[(a.phase + 2) % 3] = 0ull;
         ctl->clk[nxt] = nk;
@@ -58,8 +58,8 @@ __device__ void clock_wave(const StepArgs<T>& a) {
 // bits of the deepest new depth and the outflow discharge leaving the grid;
 // with ACT, also whether any of the item's cells is wet (h > 0, or NaN) or
 // changed its depth, or any face it stores (border faces included) carries a
-// non-zero discharge.
-template <typename T, int CPT, bool NTS, bool ACT = false>
+// non-zero discharge.  VAR: method variant of the marcher and border faces.
+template <typename T, int CPT, bool NTS, bool ACT = false, int VAR = 0>
 __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord<T>::U& hbits,
                           double& outacc, bool& moved) {
     constexpr int WL = 64 * CPT;  // loaded columns
@@ -109,7 +109,7 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
         }
     };
 
-    Marcher<T, CPT> M;
+    Marcher<T, CPT, VAR> M;
     M.reset();
     load_row(j0 - 2);
     for (int k = j0 - 2; k <= j1 + 1; ++k) {
@@ -214,7 +214,7 @@ __device__ __forceinline__ bool item_needed(const StepArgs<T>& a, int s, int c, 
 // Work item `item` of one step (strip fastest): the marching tile, then the
 // wave's deepest cell into the next max slot and its outflow partial sum;
 // with ACT, first the skip test, and last the item's flag of this step.
-template <typename T, int CPT, bool NTS, bool ACT = false>
+template <typename T, int CPT, bool NTS, bool ACT = false, int VAR = 0>
 __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     if constexpr (ACT) {
         const int s = item % a.nstrips, c = item / a.nstrips;
@@ -235,7 +235,7 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     typename Ord<T>::U hb = 0;
     double outacc = 0.0;
     bool moved = false;
-    step_item<T, CPT, NTS, ACT>(a, s, c, (T)dt64, hb, outacc, moved);
+    step_item<T, CPT, NTS, ACT, VAR>(a, s, c, (T)dt64, hb, outacc, moved);
     hb = wave_max_key(hb);
     const int slot = part_slot<T>(a, s, c);
     if (slot >= 0) outacc = wave_sum(outacc);
@@ -248,10 +248,10 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     }
 }
 
-template <typename T, int CPT, bool ACT>
+template <typename T, int CPT, bool ACT, int VAR>
 __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     if (blockIdx.x == 0) {
-        if (threadIdx.x < 64) clock_wave<T>(a);
+        if (threadIdx.x < 64) clock_wave<T, VAR>(a);
         return;
     }
     // XCD-aware order: workgroups go round-robin to the 8 XCDs, so XCD x runs
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
     // derived from it: strip, rows, loop counter, border tests) scalar
     const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= a.nstrips * a.nchunks) return;
-    tile_item<T, CPT, true, ACT>(a, wave);
+    tile_item<T, CPT, true, ACT, VAR>(a, wave);
 }
 
 // Persistent batch of independent members, one launch for many steps.
@@ -339,9 +339,9 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
 
 // Inflow applied by the first step after commit (the clock slot is set by the
 // host): written into the buffer that step reads.
-template <typename T>
+template <typename T, int VAR>
 __global__ void k_prime(StepArgs<T> a) {
-    inflow_solve<T>(a, hydrograph<T>(a, a.ctl->clk[a.phase & 1].t), const_cast<T*>(a.qin));
+    inflow_solve<T, VAR>(a, hydrograph<T>(a, a.ctl->clk[a.phase & 1].t), const_cast<T*>(a.qin));
 }
 
 // Clock and budget as of now: report[] = {t, last_dt, steps, v_in, v_out, done, nonfinite}.
@@ -427,12 +427,12 @@ __global__ void k_volume_sum(const double* part, int nparts, double* out) {
 // ----------------------------------------------------------------- launchers
 int strip_width(int cpt) { return 64 * cpt - 4; }
 
-template <typename T, bool ACT>
+template <typename T, bool ACT, int VAR = 0>
 hipError_t launch_step_act(const StepArgs<T>& a, int cpt, int blocks, hipStream_t s) {
     switch (cpt) {
-    case 1: hipLaunchKernelGGL((k_step<T, 1, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_step<T, 2, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<T, 4, ACT>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_step<T, 1, ACT, VAR>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<T, 2, ACT, VAR>), dim3(blocks), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<T, 4, ACT, VAR>), dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -442,6 +442,20 @@ template <typename T>
 hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s) {
     const long long items = (long long)a.nstrips * a.nchunks;
     const int blocks = (int)(1 + (items + 3) / 4);
+    if (a.variant) {
+        // method variants run without active tiles
+        if (a.act) return hipErrorInvalidValue;
+        switch (a.variant) {
+        case VAR_FRICTION_VECTOR:
+            return launch_step_act<T, false, VAR_FRICTION_VECTOR>(a, cpt, blocks, s);
+        case VAR_BOUNDARY_CELL_AREA:
+            return launch_step_act<T, false, VAR_BOUNDARY_CELL_AREA>(a, cpt, blocks, s);
+        case VAR_FRICTION_VECTOR | VAR_BOUNDARY_CELL_AREA:
+            return launch_step_act<T, false, VAR_FRICTION_VECTOR | VAR_BOUNDARY_CELL_AREA>(a, cpt,
+                                                                                        blocks, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (a.act) {
         // the flags of every item must fit in a slot
         if (items > a.act_stride) return hipErrorInvalidValue;
@@ -465,7 +479,10 @@ hipError_t launch_fill_bytes(unsigned char* p, long long n, unsigned char v, hip
 
 template <typename T>
 hipError_t launch_prime(const StepArgs<T>& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_prime<T>), dim3(1), dim3(64), 0, s, a);
+    if (a.variant & VAR_BOUNDARY_CELL_AREA)
+        hipLaunchKernelGGL((k_prime<T, VAR_BOUNDARY_CELL_AREA>), dim3(1), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_prime<T, 0>), dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -38,13 +38,20 @@ __device__ __forceinline__ T inflow_at(const StepArgs<T>& a, const StepK<T>& K, 
 
 // Border face value (eq. 5, 6), signed toward +axis: the inflow of this step,
 // the Manning discharge of the edge cell's own depth on the outflow section,
-// a closed wall everywhere else.
-template <typename T>
+// a closed wall everywhere else.  With VAR_BOUNDARY_CELL_AREA eq. (5) is taken
+// literally: the outflow cell passes dx^2 h^{2/3} sqrt(S)/n, dx h^{2/3} sqrt(S)/n
+// per unit width of its face.
+template <typename T, int VAR = 0>
 __device__ __forceinline__ T border_q(const StepArgs<T>& a, const StepK<T>& K, int side, int p,
                                       T h_edge) {
     T v = T(0);
     if (a.in_side == side) v = inflow_at<T>(a, K, p);
-    if (a.out_side == side) v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
+    if (a.out_side == side) {
+        if constexpr ((VAR & VAR_BOUNDARY_CELL_AREA) != 0)
+            v -= a.kout[p] * (T(a.dx) * pow23(fmax(h_edge, T(0))));
+        else
+            v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
+    }
     return (side == SIDE_W || side == SIDE_S) ? v : -v;
 }
 
@@ -53,10 +60,15 @@ __device__ __forceinline__ T border_q(const StepArgs<T>& a, const StepK<T>& K, i
 // the applied discharges of its east and north faces.  The marcher keeps the
 // two rows still needed (surface, bed, roughness, depths, tentative and
 // applied discharges, donor factors) in registers.
-template <typename T, int CPT>
+// VAR selects a method variant (0: the paper's per-axis form); with
+// VAR_FRICTION_VECTOR the friction term uses sqrt(q^2 + q_perp^2), q_perp the
+// mean of the start-of-step discharges on the interior perpendicular faces of
+// the two cells beside the face, which needs the previous row's x-discharges.
+template <typename T, int CPT, int VAR = 0>
 struct Marcher {
     T eta1[CPT], z1[CPT], n1[CPT], qy1[CPT], h1[CPT], h2[CPT];
     T qsx1[CPT], qsy2[CPT], r2[CPT], qnx2[CPT], qny3[CPT];
+    T qxo1[CPT];  // start-of-step qx of row k-1 (vector friction only)
 
     __device__ __forceinline__ void reset() {
 #pragma unroll
@@ -64,6 +76,7 @@ struct Marcher {
             eta1[m] = z1[m] = n1[m] = qy1[m] = h1[m] = h2[m] = T(0);
             qsx1[m] = qsy2[m] = qnx2[m] = qny3[m] = T(0);
             r2[m] = T(1);
+            if constexpr ((VAR & VAR_FRICTION_VECTOR) != 0) qxo1[m] = T(0);
         }
     }
 
@@ -82,12 +95,36 @@ struct Marcher {
 #pragma unroll
         for (int m = 0; m < CPT; ++m) eta0[m] = h0[m] + z0[m];
         const T etaRn = from_next(eta0[0]), zRn = from_next(z0[0]), nRn = from_next(n0[0]);
+        if constexpr ((VAR & VAR_FRICTION_VECTOR) != 0) {
+            // perpendicular faces of an x-face of row k: the y-faces below
+            // (row k-1's north faces) and above (row k's), of both cells;
+            // border faces (rows -1 and ny-1) are left out of the mean
+            const T qy1Rn = from_next(qy1[0]), qy0Rn = from_next(qy0[0]);
+            const bool below = (k >= 1), above = (k <= ny - 2);
+            const T wgt = (below && above) ? T(0.25) : T(0.5);
 #pragma unroll
-        for (int m = 0; m < CPT; ++m) {
-            const T eR = (m + 1 < CPT) ? eta0[(m + 1) % CPT] : etaRn;
-            const T zR = (m + 1 < CPT) ? z0[(m + 1) % CPT] : zRn;
-            const T nR = (m + 1 < CPT) ? n0[(m + 1) % CPT] : nRn;
-            qsx0[m] = face_q<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], K.gdt, K.inv_dx, K.h_eps);
+            for (int m = 0; m < CPT; ++m) {
+                const T eR = (m + 1 < CPT) ? eta0[(m + 1) % CPT] : etaRn;
+                const T zR = (m + 1 < CPT) ? z0[(m + 1) % CPT] : zRn;
+                const T nR = (m + 1 < CPT) ? n0[(m + 1) % CPT] : nRn;
+                const T b1 = (m + 1 < CPT) ? qy1[(m + 1) % CPT] : qy1Rn;
+                const T b0 = (m + 1 < CPT) ? qy0[(m + 1) % CPT] : qy0Rn;
+                T ps = T(0);
+                if (below) ps += (qy1[m] + b1);
+                if (above) ps += (qy0[m] + b0);
+                const T qp = ps * wgt;
+                const T qm = sqrt(qx0[m] * qx0[m] + qp * qp);
+                qsx0[m] = face_qm<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], qm, K.gdt,
+                                     K.inv_dx, K.h_eps);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                const T eR = (m + 1 < CPT) ? eta0[(m + 1) % CPT] : etaRn;
+                const T zR = (m + 1 < CPT) ? z0[(m + 1) % CPT] : zRn;
+                const T nR = (m + 1 < CPT) ? n0[(m + 1) % CPT] : nRn;
+                qsx0[m] = face_q<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], K.gdt, K.inv_dx, K.h_eps);
+            }
         }
         if (G.west_strip) {
             const T hRn = from_next(h0[0]);
@@ -95,30 +132,51 @@ struct Marcher {
             for (int m = 0; m < CPT; ++m)
                 if (G.west_face[m]) {
                     const T hR = (m + 1 < CPT) ? h0[(m + 1) % CPT] : hRn;
-                    qsx0[m] = row_real ? border_q<T>(a, K, SIDE_W, k, hR) : T(0);
+                    qsx0[m] = row_real ? border_q<T, VAR>(a, K, SIDE_W, k, hR) : T(0);
                 }
         }
         if (G.east_strip) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
                 if (G.east_face[m])
-                    qsx0[m] = row_real ? border_q<T>(a, K, SIDE_E, k, h0[m]) : T(0);
+                    qsx0[m] = row_real ? border_q<T, VAR>(a, K, SIDE_E, k, h0[m]) : T(0);
         }
 
         // B: y-faces between rows k-1 and k.
         T qsy1[CPT];
+        if constexpr ((VAR & VAR_FRICTION_VECTOR) != 0) {
+            // perpendicular faces of the y-face above cell (i, k-1): the
+            // x-faces west (column i-1) and east (column i) of the cells of
+            // rows k-1 and k; west and east border faces are left out
+            const T w1n = from_prev(qxo1[CPT - 1]), w0n = from_prev(qx0[CPT - 1]);
 #pragma unroll
-        for (int m = 0; m < CPT; ++m)
-            qsy1[m] = face_q<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], K.gdt,
-                                K.inv_dx, K.h_eps);
+            for (int m = 0; m < CPT; ++m) {
+                const T w1 = (m > 0) ? qxo1[(m + CPT - 1) % CPT] : w1n;
+                const T w0 = (m > 0) ? qx0[(m + CPT - 1) % CPT] : w0n;
+                const int i = G.i0 + m;
+                const bool west = (i >= 1), east = (i <= a.nx - 2);
+                T ps = T(0);
+                if (west) ps += (w1 + w0);
+                if (east) ps += (qxo1[m] + qx0[m]);
+                const T qp = ps * ((west && east) ? T(0.25) : T(0.5));
+                const T qm = sqrt(qy1[m] * qy1[m] + qp * qp);
+                qsy1[m] = face_qm<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], qm,
+                                     K.gdt, K.inv_dx, K.h_eps);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                qsy1[m] = face_q<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], K.gdt,
+                                    K.inv_dx, K.h_eps);
+        }
         if (k - 1 == -1) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
-                qsy1[m] = G.outside[m] ? T(0) : border_q<T>(a, K, SIDE_S, G.i0 + m, h0[m]);
+                qsy1[m] = G.outside[m] ? T(0) : border_q<T, VAR>(a, K, SIDE_S, G.i0 + m, h0[m]);
         } else if (k - 1 == ny - 1) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
-                qsy1[m] = G.outside[m] ? T(0) : border_q<T>(a, K, SIDE_N, G.i0 + m, h1[m]);
+                qsy1[m] = G.outside[m] ? T(0) : border_q<T, VAR>(a, K, SIDE_N, G.i0 + m, h1[m]);
         }
 
         // C: donor scaling factor of row k-1.
@@ -164,6 +222,7 @@ struct Marcher {
             eta1[m] = eta0[m]; z1[m] = z0[m]; n1[m] = n0[m]; qy1[m] = qy0[m];
             qsx1[m] = qsx0[m]; qsy2[m] = qsy1[m]; r2[m] = r1[m];
             qnx2[m] = qnx1[m]; qny3[m] = qny2[m];
+            if constexpr ((VAR & VAR_FRICTION_VECTOR) != 0) qxo1[m] = qx0[m];
         }
     }
 };

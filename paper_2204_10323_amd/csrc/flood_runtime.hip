@@ -83,6 +83,8 @@ struct fl_ctx {
     // are set to 1 (compute everything) before the next skipping step.
     int active = 0;
     unsigned char* d_act = nullptr;
+    // method variant (fl_set_variant): bit 0 vector friction, bit 1 cell-area boundaries
+    int variant = 0;
     long long act_stride = 0, act_at = -1;
 
     // reverse mode (fl_adj_*): settings, checkpoints and the forward's record
@@ -299,6 +301,7 @@ StepArgs<T> make_args(const fl_ctx* c, long long n, const Tiling& tl, int freeze
     a.dt_fixed = c->params.dt_fixed;
     a.act = nullptr;
     a.act_stride = 0;
+    a.variant = c->variant;
     return a;
 }
 
@@ -483,6 +486,9 @@ fl_status do_commit(fl_ctx* c) {
     if (c->active && c->fuse == 2)
         return fail(c, FL_EINVAL,
                     "fl_commit: active-tile skipping runs one step per launch; set fl_set_fusion(ctx, 1, ...)");
+    if (c->variant && (c->fuse == 2 || c->active))
+        return fail(c, FL_EINVAL,
+                    "fl_commit: method variants run one step per launch without active tiles");
     if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse == 2, c->active != 0))
         return fail(c, FL_EINVAL, "fl_commit: the bound workspace is smaller than fl_workspace_bytes");
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
@@ -1015,6 +1021,17 @@ fl_status fl_set_fusion(fl_ctx* c, int32_t steps_per_launch, int32_t cells_per_l
     c->fuse = steps_per_launch;
     c->cpt2_req = cells_per_lane;
     c->rows2_req = rows_per_item;
+    invalidate(c);
+    return FL_OK;
+}
+
+fl_status fl_set_variant(fl_ctx* c, int32_t friction, int32_t boundary) {
+    if (!c) return FL_EINVAL;
+    if ((friction != FL_FRICTION_FACE && friction != FL_FRICTION_VECTOR) ||
+        (boundary != FL_BOUNDARY_SECTION && boundary != FL_BOUNDARY_CELL_AREA))
+        return fail(c, FL_EINVAL, "fl_set_variant: unknown friction or boundary form");
+    c->variant = (friction == FL_FRICTION_VECTOR ? VAR_FRICTION_VECTOR : 0) |
+                 (boundary == FL_BOUNDARY_CELL_AREA ? VAR_BOUNDARY_CELL_AREA : 0);
     invalidate(c);
     return FL_OK;
 }
@@ -1625,6 +1642,8 @@ fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, i
     if (!c->committed) return fail(c, FL_ESTATE, "fl_adj_setup before fl_commit");
     if (!(c->params.dt_fixed > 0.0))
         return fail(c, FL_EINVAL, "fl_adj_setup: the reverse mode needs a fixed time step (dt_fixed > 0)");
+    if (c->variant)
+        return fail(c, FL_EINVAL, "fl_adj_setup: the reverse mode is derived for the default method");
     if (!gauge_cells || ngauges < 1 || obs_every < 1 || ckpt_stride < 0 || (obs && nobs < 1))
         return fail(c, FL_EINVAL, "fl_adj_setup: need gauges, obs_every >= 1, ckpt_stride >= 0");
     for (int k = 0; k < ngauges; ++k)
@@ -1854,6 +1873,10 @@ fl_status fl_batch_create(fl_batch** out, int32_t nmembers, fl_ctx* const* membe
         }
         if (members[k]->device != members[0]->device || members[k]->prec != members[0]->prec) {
             g_create_error = "fl_batch_create: members must share device and precision";
+            return FL_EINVAL;
+        }
+        if (members[k]->variant) {
+            g_create_error = "fl_batch_create: batches run the default method (no fl_set_variant)";
             return FL_EINVAL;
         }
         for (int l = 0; l < k; ++l)
