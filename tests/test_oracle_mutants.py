@@ -27,16 +27,18 @@ MUTANTS = {
     "boundary_exponent_2_3": ("return x * (c * c);", "return c * c;"),
     "depth_update_sign": ("h[j * nx + i] + (dt * ((qW - qE) + (qS - qN))) / dx;",
                           "h[j * nx + i] + (dt * ((qW - qE) + (qN - qS))) / dx;"),
-    "y_faces_use_x_neighbour": ("int64_t L = (j - 1) * nx + i, R = j * nx + i;",
-                                "int64_t L = j * nx + i - (i > 0), R = j * nx + i;"),
+    "y_faces_use_x_neighbour": (
+        "int64_t L = (j - 1) * nx + i, R = j * nx + i;\n                    double *q = &qy[",
+        "int64_t L = j * nx + i - (i > 0), R = j * nx + i;\n                    double *q = &qy["),
     "donor_wrong_cell": ("if (*q > 0.0 && i >= 1) *q *= r[j * nx + i - 1];",
                          "if (*q > 0.0 && i < nx) *q *= r[j * nx + i];"),
     "budget_uses_unscaled_outflow": ("clk->v_out += dt * dx * sum_out;",
                                      "clk->v_out += 1.0001 * dt * dx * sum_out;"),
     "cfl_uses_sqrt_h_not_gh": ("dt = fmin(p->dt_max, p->alpha * dx / sqrt(g * hmax));",
                                "dt = fmin(p->dt_max, p->alpha * dx / sqrt(hmax));"),
-    "inflow_bisection_direction": ("if (F < 0.0) lo = mid; else hi = mid;",
-                                   "if (F > 0.0) lo = mid; else hi = mid;"),
+    "inflow_bisection_direction": (
+        "pow53(mid - zc[c]);\n        F -= Q;\n        if (F < 0.0) lo = mid; else hi = mid;",
+        "pow53(mid - zc[c]);\n        F -= Q;\n        if (F > 0.0) lo = mid; else hi = mid;"),
     "last_step_not_shortened": ("if (dt >= rem) { dt = rem; last = 1; }",
                                 "if (dt >= rem) { last = 1; }"),
 }
@@ -60,6 +62,9 @@ VAR_MUTANTS = {
                                              "q_out[c] = kc[c] * pow23(W - zc[c]);"),
     "cell_area_inflow_sum_one_dx": ("F += dx * (dx * kc[c] * pow23(mid - zc[c]));",
                                     "F += dx * kc[c] * pow23(mid - zc[c]);"),
+    "cell_area_inflow_bisection_direction": (
+        "pow23(mid - zc[c]));\n        F -= Q;\n        if (F < 0.0) lo = mid; else hi = mid;",
+        "pow23(mid - zc[c]));\n        F -= Q;\n        if (F > 0.0) lo = mid; else hi = mid;"),
 }
 
 
