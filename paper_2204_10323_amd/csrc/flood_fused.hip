@@ -38,6 +38,7 @@ struct Plan2 {
     ClockSlot ck1;       // clock at the start of the second step (t and nonfinite; complete in mode 3)
     double dt_a, dt_b;
     int last_a, done_a, nonfin_a, last_b, done_b, nonfin_b;
+    long long gen;       // generation of the state the launch writes (a redo: the one it replaces)
 };
 
 // Whether to run a second step with a speculated dt: always with a fixed dt,
@@ -74,6 +75,7 @@ __device__ Plan2 make_plan(const Step2Args<T>& A) {
     }
     if (!P.verified) {
         P.mode = 3;
+        P.gen = S.gen;
         P.in = S.cur ^ 1;
         P.ck0 = S.back;
         P.ck1 = S.mid;
@@ -85,6 +87,7 @@ __device__ Plan2 make_plan(const Step2Args<T>& A) {
         return P;
     }
     P.in = S.cur;
+    P.gen = S.gen + 1;
     P.ck0 = S.ck;
     P.ck1 = S.ck;
     const long long remaining = ctl->target2 - S.vsteps;
@@ -165,6 +168,7 @@ __device__ void clock2_wave(const Step2Args<T>& A, const Plan2& P) {
         N.mid = c1;
         N.dt_a = P.dt_a;
         N.cur = P.in ^ 1;
+        N.gen = P.gen;
         if (P.mode == 1) {
             N.ck = c1;
             N.dt_b = 0.0;
@@ -209,13 +213,17 @@ __device__ __forceinline__ bool needs_inflow(const StepArgs<T>& a, int s, int j0
 // marcher B with the bed and roughness of that row; B emits row k - 4.
 // Values of A's emitted rows outside the grid are replaced by zeros, which is
 // what the single-step kernel reads from the halo there.
-template <typename T, int CPT>
+// With ACT, `moved` records whether any row of the item that either step
+// emits holds water (h > 0, or NaN), changed its depth in that step, or
+// carries a non-zero discharge on a face the item stores (border faces
+// included); A's rows beyond the item count too (conservative).
+template <typename T, int CPT, bool ACT = false>
 __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
                            const T* __restrict__ qx_in, const T* __restrict__ qy_in,
                            T* __restrict__ h_out, T* __restrict__ qx_out, T* __restrict__ qy_out,
                            const StepK<T>& KA, const StepK<T>& KB, bool two, int s, int j0, int j1,
                            typename Ord<T>::U& hbA, typename Ord<T>::U& hbB, double& outA,
-                           double& outB) {
+                           double& outB, bool& moved) {
     constexpr int WL = 64 * CPT;  // loaded columns
     constexpr int WO = WL - 8;    // output columns (strip 0: two more on the left)
     const int lane = threadIdx.x & 63;
@@ -251,6 +259,23 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
+        }
+    };
+    // active-tile flag of an emitted row (ro: its row index, hold: its depth before the step)
+    auto mark = [&](int ro, const T (&hv)[CPT], const T (&hold)[CPT], const T (&qxv)[CPT],
+                    const T (&qyv)[CPT]) {
+        if (ro >= 0 && ro < ny) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (store_col[m])
+                    moved = moved || !(hv[m] <= T(0)) || hv[m] != hold[m] || qxv[m] != T(0) ||
+                            qyv[m] != T(0);
+                if (G.west_face[m]) moved = moved || qxv[m] != T(0);
+            }
+        } else if (ro == -1 && south_chunk) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (store_col[m]) moved = moved || qyv[m] != T(0);
         }
     };
     auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
@@ -290,7 +315,11 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
             h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
         }
         if (k < ke) load_row(k + 1);
-        T hA[CPT], qxA[CPT], qyA[CPT];
+        T hA[CPT], qxA[CPT], qyA[CPT], holdA[CPT];
+        if constexpr (ACT) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) holdA[m] = MA.h2[m];
+        }
         MA.row(a, KA, G, k, h0, z0, n0, qx0, qy0, hA, qxA, qyA);
         T zr[CPT], nr[CPT];
 #pragma unroll
@@ -301,6 +330,10 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
         }
         const int ra = k - 2;
         const bool a_item = (ra >= j0 && ra < j1);
+        if constexpr (ACT) {
+            if (two ? (ra >= j0 - 2 && ra < j1 + 2) : (a_item || (ra == -1 && south_chunk)))
+                mark(ra, hA, holdA, qxA, qyA);
+        }
         if (!two) {
             if (a_item) store_row(ra, hA, qxA, qyA);
             row_books<T, CPT>(a, G, store_col, ra, a_item, south_chunk, hA, qxA, qyA, true, hbA,
@@ -313,10 +346,17 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
 #pragma unroll
         for (int m = 0; m < CPT; ++m)
             if (!ra_real || G.outside[m]) hA[m] = qxA[m] = qyA[m] = T(0);
-        T hB[CPT], qxB[CPT], qyB[CPT];
+        T hB[CPT], qxB[CPT], qyB[CPT], holdB[CPT];
+        if constexpr (ACT) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) holdB[m] = MB.h2[m];
+        }
         MB.row(a, KB, G, ra, hA, zr, nr, qxA, qyA, hB, qxB, qyB);
         const int rb = ra - 2;
         const bool b_item = (rb >= j0 && rb < j1);
+        if constexpr (ACT) {
+            if (b_item || (rb == -1 && south_chunk)) mark(rb, hB, holdB, qxB, qyB);
+        }
         if (b_item) store_row(rb, hB, qxB, qyB);
         row_books<T, CPT>(a, G, store_col, rb, b_item, south_chunk, hB, qxB, qyB, true, hbB, outB);
     }
@@ -342,7 +382,34 @@ __device__ __forceinline__ void inflow_consts(const StepArgs<T>& a, double t, St
     }
 }
 
-template <typename T, int CPT>
+// Must item (s, c) be computed by a launch that writes generation gen
+// (active-tile skipping)?  Over two steps a cell depends on the cells up to
+// two away, which lie in the item and the 8 items around it (items are at
+// least two cells tall and wide), so it may be skipped when those nine items
+// were dry and unchanged in generation gen - 1, and the item itself also in
+// gen - 2 (its output buffer still holds that state).  A redo reads the same
+// slots as the launch it replaces and so skips the same items, whose output
+// buffer that launch left untouched.  Items whose loaded region meets an
+// inflow face are always computed.
+template <typename T>
+__device__ __forceinline__ bool item_needed2(const StepArgs<T>& a, int s, int c, long long gen) {
+    const int lane = threadIdx.x & 63;
+    int v = 0;
+    if (lane < 10) {
+        int ss = s + lane % 3 - 1, cc = c + lane / 3 - 1;
+        long long sl = (gen + 2) % 3;  // generation gen - 1
+        if (lane == 9) {
+            ss = s;
+            cc = c;
+            sl = (gen + 1) % 3;        // generation gen - 2
+        }
+        if (ss >= 0 && ss < a.nstrips && cc >= 0 && cc < a.nchunks)
+            v = a.act[sl * a.act_stride + (long long)cc * a.nstrips + ss];
+    }
+    return __ballot(v != 0) != 0ull;
+}
+
+template <typename T, int CPT, bool ACT>
 __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P, int item) {
     const StepArgs<T>& a = A.a;
     constexpr int WL = 64 * CPT, WO = WL - 8;
@@ -350,19 +417,36 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
     const int j0 = c * a.rows, j1 = min(j0 + a.rows, a.ny);
     // the plan is the same in every lane; keep what steers control flow scalar
     const bool two = __builtin_amdgcn_readfirstlane(P.mode) != 1;
+    const bool inflow = needs_inflow<T>(a, s, j0, j1, WO, WL);
+    if constexpr (ACT) {
+        if (!inflow && !item_needed2<T>(a, s, c, P.gen)) {
+            // nothing moves: no deeper cell, no outflow, flag 0
+            if ((threadIdx.x & 63) == 0) {
+                a.act[(P.gen % 3) * a.act_stride + item] = 0;
+                const int slot = part_slot<T>(a, s, c);
+                if (slot >= 0) {
+                    A.part_a[A.phase & 1][slot] = 0.0;
+                    A.part_b[A.phase & 1][slot] = 0.0;
+                }
+            }
+            return;
+        }
+    }
     StepK<T> KA, KB;
     step_consts<T>(a, P.dt_a, KA);
     step_consts<T>(a, P.dt_b, KB);
-    if (needs_inflow<T>(a, s, j0, j1, WO, WL)) {
+    if (inflow) {
         inflow_consts<T>(a, P.ck0.t, KA);
         if (two) inflow_consts<T>(a, P.ck1.t, KB);
     }
     const bool in1 = __builtin_amdgcn_readfirstlane(P.in) != 0;
     typename Ord<T>::U hbA = 0, hbB = 0;
     double oA = 0.0, oB = 0.0;
-    step2_item<T, CPT>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0], in1 ? A.qy[1] : A.qy[0],
-                       in1 ? A.h[0] : A.h[1], in1 ? A.qx[0] : A.qx[1], in1 ? A.qy[0] : A.qy[1], KA,
-                       KB, two, s, j0, j1, hbA, hbB, oA, oB);
+    bool moved = false;
+    step2_item<T, CPT, ACT>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0],
+                            in1 ? A.qy[1] : A.qy[0], in1 ? A.h[0] : A.h[1],
+                            in1 ? A.qx[0] : A.qx[1], in1 ? A.qy[0] : A.qy[1], KA, KB, two, s, j0,
+                            j1, hbA, hbB, oA, oB, moved);
     hbA = wave_max_key(hbA);
     if (two) hbB = wave_max_key(hbB);
     const int slot = part_slot<T>(a, s, c);
@@ -370,7 +454,10 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
         oA = wave_sum(oA);
         if (two) oB = wave_sum(oB);
     }
+    bool any_moved = false;
+    if constexpr (ACT) any_moved = __ballot(moved) != 0ull;
     if ((threadIdx.x & 63) == 0) {
+        if constexpr (ACT) a.act[(P.gen % 3) * a.act_stride + item] = any_moved ? 1 : 0;
         unsigned long long* hm = a.ctl->hm2 + 2 * (A.phase % 3);
         if (two) {
             if (hbA) atomicMax(&hm[0], (unsigned long long)hbA);
@@ -385,7 +472,7 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
     }
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool ACT>
 __global__ __launch_bounds__(256) void k_step2(Step2Args<T> A) {
     const Plan2 P = make_plan<T>(A);
     if (blockIdx.x == 0) {
@@ -402,7 +489,7 @@ __global__ __launch_bounds__(256) void k_step2(Step2Args<T> A) {
     // derived from it: strip, rows, loop counter, border tests) scalar
     const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= A.a.nstrips * A.a.nchunks) return;
-    tile2_item<T, CPT>(A, P, wave);
+    tile2_item<T, CPT, ACT>(A, P, wave);
 }
 
 template <typename T>
@@ -419,6 +506,7 @@ __global__ void k_enter2(StepArgs<T> a, int cur, long long target) {
     S.pending = 0;
     S.nclose = 0;
     S.pad = 0;
+    S.gen = 0;
     ctl->c2[0] = S;
     for (int q = 0; q < 4; ++q) ctl->hm2[q] = 0ull;
     ctl->hm2[4] = 0ull;
@@ -458,7 +546,14 @@ template <typename T, int CPT>
 static hipError_t launch_step2_cpt(const Step2Args<T>& a, hipStream_t s) {
     const long long items = (long long)a.a.nstrips * a.a.nchunks;
     const unsigned blocks = (unsigned)(1 + (items + 3) / 4);
-    hipLaunchKernelGGL((k_step2<T, CPT>), dim3(blocks), dim3(256), 0, s, a);
+    if (a.a.act) {
+        // the flags of every item must fit in a slot; the skip test needs
+        // items at least two rows tall
+        if (items > a.a.act_stride || a.a.rows < 2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step2<T, CPT, true>), dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_step2<T, CPT, false>), dim3(blocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct Clock2 {
     int pending;        // the second dt was speculated and is not checked yet
     int nclose;         // steps of the last launch whose outflow is not in ck.v_out
     int pad;
+    long long gen;      // launches that produced the claimed state (a redo keeps the count);
+                        // active-tile flags of a launch live in slot gen % 3
 };
 
 // Device control block of one context.

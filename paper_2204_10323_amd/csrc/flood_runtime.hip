@@ -337,6 +337,11 @@ Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve, int free
     Step2Args<T> A{};
     const Tiling tl{c->cpt2, c->rows2, c->nstrips2, c->nchunks2, c->npart2};
     A.a = make_args<T>(c, 0, tl, freeze);
+    if (c->active && !freeze) {
+        // active-tile skipping in the two-step launches (flags by generation)
+        A.a.act = c->d_act;
+        A.a.act_stride = c->act_stride;
+    }
     for (int p = 0; p < 2; ++p) {
         A.h[p] = (T*)c->d_h[p];
         A.qx[p] = (T*)c->d_qx[p];
@@ -452,9 +457,10 @@ fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
 // boundary data at its largest (sections up to the longest side, hydrographs
 // up to 4096 samples).
 // Flag bytes per step slot of active-tile skipping: enough for the smallest
-// work items (one cell per lane, one row).
+// work items of either kernel (one cell per lane, one row).
 long long act_slot_bytes(int nx, int ny) {
-    return (long long)((nx + strip_width(1) - 1) / strip_width(1)) * ny;
+    const int w = std::min(strip_width(1), strip_width2(1));
+    return (long long)((nx + w - 1) / w) * ny;
 }
 
 size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step, bool active) {
@@ -483,9 +489,6 @@ fl_status do_commit(fl_ctx* c) {
     free_device(c);
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
-    if (c->active && c->fuse == 2)
-        return fail(c, FL_EINVAL,
-                    "fl_commit: active-tile skipping runs one step per launch; set fl_set_fusion(ctx, 1, ...)");
     if (c->variant && (c->fuse == 2 || c->active))
         return fail(c, FL_EINVAL,
                     "fl_commit: method variants run one step per launch without active tiles");
@@ -608,6 +611,9 @@ fl_status do_commit(fl_ctx* c) {
     if (c->fuse == 2) {
         c->cpt2 = c->cpt2_req ? c->cpt2_req : (c->prec == FL_F64 ? 1 : 2);
         c->rows2 = c->rows2_req ? c->rows2_req : default_rows2(nx, ny, c->cpt2);
+        if (c->active && c->rows2 < 2)
+            return fail(c, FL_EINVAL,
+                        "fl_commit: active tiles with two steps per launch need items of >= 2 rows");
         const Tiling t2 = tiling2_of(c, c->cpt2, c->rows2);
         c->nstrips2 = t2.nstrips;
         c->nchunks2 = t2.nchunks;
@@ -653,6 +659,11 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
         const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
         if ((st = fold_budget(c, tl))) return st;
     }
+    if (c->active && !freeze) {
+        // the single-step flags do not describe the two-step work items:
+        // compute every item in the first two launches
+        HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
+    }
     HIP_TRY(c, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, c->stream));
     long long lc = 0;
     long long want = (nsteps + 1) / 2;
@@ -683,6 +694,7 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
     n2 += (n2 ^ (long long)slot.cur) & 1;
     HIP_TRY(c, launch_leave2<T>(make_args<T>(c, n2), make_args2<T>(c, 0, 0), lc, c->stream));
     c->nstep = n2;
+    c->act_at = -1;  // the single-step flags are stale now
     return FL_OK;
 }
 

@@ -140,3 +140,22 @@ def test_valley16384_active_autotune_prefers_small_items_when_dry(d3_dry):
     assert np.array_equal(f.get_depth(), g.get_depth())
     f.close()
     g.close()
+
+
+def test_valley16384_dry_1000_steps_active_tiles_two_steps(d3_dry):
+    """Active tiles with two steps per launch on the benchmark workload: the
+    same state as computing every item."""
+    import torch
+    sc = d3_dry
+    print("CASE fullsize dry 1000 steps, active tiles, two steps per launch", flush=True)
+    hs = []
+    for active in (True, False):
+        f = fl.from_scenario(sc, "f32", active_tiles=active, fusion=2)
+        f.step(1000)
+        h = torch.empty((sc.ny, sc.nx), dtype=torch.float32, device="cuda")
+        f.get_depth(h)
+        r = f.get_report()
+        f.close()
+        hs.append((h, r))
+    assert torch.equal(hs[0][0], hs[1][0])
+    assert (hs[0][1].t, hs[0][1].v_in, hs[0][1].v_out) == (hs[1][1].t, hs[1][1].v_in, hs[1][1].v_out)
