@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_step2(Step2Args<T> A) {
 }
 
 template <typename T>
-__global__ void k_enter2(StepArgs<T> a, int cur, long long target) {
+__global__ void k_enter2(StepArgs<T> a, int cur, long long target, int keep_gen) {
     if (threadIdx.x != 0) return;
     DevCtl* ctl = a.ctl;
     Clock2 S;
@@ -506,7 +506,7 @@ __global__ void k_enter2(StepArgs<T> a, int cur, long long target) {
     S.pending = 0;
     S.nclose = 0;
     S.pad = 0;
-    S.gen = 0;
+    S.gen = keep_gen ? ctl->gen2 : 0;
     ctl->c2[0] = S;
     for (int q = 0; q < 4; ++q) ctl->hm2[q] = 0ull;
     ctl->hm2[4] = 0ull;
@@ -536,6 +536,7 @@ __global__ void k_leave2(StepArgs<T> a, Step2Args<T> A, long long launches) {
         ctl->clk[a.phase & 1] = ck;
         ctl->hmax[a.phase % 3] = ctl->hm2[2 * (pl % 3) + 1];
         ctl->hmax[(a.phase + 1) % 3] = 0ull;
+        ctl->gen2 = S.gen;
     }
 }
 
@@ -568,10 +569,11 @@ hipError_t launch_step2(const Step2Args<T>& a, int cpt, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_enter2(const StepArgs<T>& single, long long target, hipStream_t s) {
+hipError_t launch_enter2(const StepArgs<T>& single, long long target, int keep_gen, hipStream_t s) {
     // the single-step state at counter n lives in buffer n % 2, i.e. the
     // buffer of single.h_in; phase = n % 6
-    hipLaunchKernelGGL((k_enter2<T>), dim3(1), dim3(64), 0, s, single, single.phase & 1, target);
+    hipLaunchKernelGGL((k_enter2<T>), dim3(1), dim3(64), 0, s, single, single.phase & 1, target,
+                       keep_gen);
     return hipGetLastError();
 }
 
@@ -585,8 +587,8 @@ hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long
 
 template hipError_t launch_step2<float>(const Step2Args<float>&, int, hipStream_t);
 template hipError_t launch_step2<double>(const Step2Args<double>&, int, hipStream_t);
-template hipError_t launch_enter2<float>(const StepArgs<float>&, long long, hipStream_t);
-template hipError_t launch_enter2<double>(const StepArgs<double>&, long long, hipStream_t);
+template hipError_t launch_enter2<float>(const StepArgs<float>&, long long, int, hipStream_t);
+template hipError_t launch_enter2<double>(const StepArgs<double>&, long long, int, hipStream_t);
 template hipError_t launch_leave2<float>(const StepArgs<float>&, const Step2Args<float>&, long long,
                                          hipStream_t);
 template hipError_t launch_leave2<double>(const StepArgs<double>&, const Step2Args<double>&,

@@ -56,6 +56,7 @@ struct DevCtl {
     Clock2 c2[2];
     unsigned long long hm2[6];
     long long target2;           // steps to claim before launches become no-ops
+    long long gen2;              // generation of the last two-step run's claimed state
 };
 
 template <typename T>
@@ -214,13 +215,14 @@ hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
 
 // Two-step launches (flood_fused.hip).  enter: the single-step state at
 // step counter n (its budget folded) becomes slot 0 of the two-step clock,
-// with `target` steps to claim.  leave: the state claimed after `launches`
+// with `target` steps to claim; keep_gen: continue the launch generation of
+// the previous two-step run (its active-tile flags still hold).  leave: the state claimed after `launches`
 // launches becomes the single-step state at counter n2 (buffer n2 % 2 must
 // hold it).
 template <typename T>
 hipError_t launch_step2(const Step2Args<T>& a, int cpt, hipStream_t s);
 template <typename T>
-hipError_t launch_enter2(const StepArgs<T>& single, long long target, hipStream_t s);
+hipError_t launch_enter2(const StepArgs<T>& single, long long target, int keep_gen, hipStream_t s);
 template <typename T>
 hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long long launches,
                          hipStream_t s);

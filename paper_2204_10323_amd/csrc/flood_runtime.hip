@@ -76,16 +76,19 @@ struct fl_ctx {
     hipGraphExec_t graph2_exec = nullptr;
     int graph2_k = 0;
 
-    // active-tile skipping (fl_set_active_tiles): per work item and step
-    // modulo 3 one flag byte; sized for the smallest work items any tiling can
-    // have.  act_at: the step counter up to which the skipping steps kept the
-    // flags; any other path that moves the state leaves them stale, and they
-    // are set to 1 (compute everything) before the next skipping step.
-    int active = 0;
+    // active-tile skipping (fl_set_active_tiles): per work item one flag byte
+    // in each of three slots; sized for the smallest work items any tiling
+    // can have.  The single-step path indexes the slots by step counter, the
+    // two-step path by its device-side launch generation.  act_mode says which
+    // path wrote them (0: stale) and act_at the step counter at which they
+    // describe the state; any other path that moves the state leaves them
+    // stale, and they are set to 1 (compute everything) before the next
+    // skipping run.
+    int active = 0, act_mode = 0;
     unsigned char* d_act = nullptr;
+    long long act_stride = 0, act_at = -1;
     // method variant (fl_set_variant): bit 0 vector friction, bit 1 cell-area boundaries
     int variant = 0;
-    long long act_stride = 0, act_at = -1;
 
     // reverse mode (fl_adj_*): settings, checkpoints and the forward's record
     bool adj_setup = false;
@@ -337,7 +340,7 @@ Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve, int free
     Step2Args<T> A{};
     const Tiling tl{c->cpt2, c->rows2, c->nstrips2, c->nchunks2, c->npart2};
     A.a = make_args<T>(c, 0, tl, freeze);
-    if (c->active && !freeze) {
+    if (c->active) {
         // active-tile skipping in the two-step launches (flags by generation)
         A.a.act = c->d_act;
         A.a.act_stride = c->act_stride;
@@ -627,7 +630,7 @@ fl_status do_commit(fl_ctx* c) {
 }
 
 fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
-    if (c->active && nsteps > 0 && c->act_at != c->nstep) {
+    if (c->active && nsteps > 0 && !(c->act_mode == 1 && c->act_at == c->nstep)) {
         // flags stale: compute every item in the next two steps
         HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
     }
@@ -642,7 +645,10 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
             nsteps -= 1;
         }
     }
-    if (c->active) c->act_at = c->nstep;
+    if (c->active) {
+        c->act_mode = 1;
+        c->act_at = c->nstep;
+    }
     return FL_OK;
 }
 
@@ -659,12 +665,11 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
         const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
         if ((st = fold_budget(c, tl))) return st;
     }
-    if (c->active && !freeze) {
-        // the single-step flags do not describe the two-step work items:
-        // compute every item in the first two launches
-        HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
-    }
-    HIP_TRY(c, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, c->stream));
+    // the flags of the previous two-step run still hold if nothing else moved
+    // the state since; otherwise compute every item in the first two launches
+    const bool keep = c->active && c->act_mode == 2 && c->act_at == c->nstep;
+    if (c->active && !keep) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
+    HIP_TRY(c, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, keep ? 1 : 0, c->stream));
     long long lc = 0;
     long long want = (nsteps + 1) / 2;
     Clock2 slot{};
@@ -694,7 +699,10 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
     n2 += (n2 ^ (long long)slot.cur) & 1;
     HIP_TRY(c, launch_leave2<T>(make_args<T>(c, n2), make_args2<T>(c, 0, 0), lc, c->stream));
     c->nstep = n2;
-    c->act_at = -1;  // the single-step flags are stale now
+    if (c->active) {
+        c->act_mode = 2;
+        c->act_at = n2;
+    }
     return FL_OK;
 }
 
@@ -1061,10 +1069,54 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
     if (!c->committed || !c->active)
         return fail(c, FL_ESTATE, "fl_active_items needs a context committed with active tiles on");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (c->fuse == 2 && c->act_mode == 2 && c->act_at == c->nstep) {
+        // the next two-step launch: the rule of the two-step kernel's skip test
+        const int ns = c->nstrips2, nc = c->nchunks2;
+        const long long items = (long long)ns * nc;
+        *total_items = items;
+        long long gen = 0;
+        std::vector<unsigned char> f1((size_t)items), f2((size_t)items);
+        HIP_TRY(c, hipMemcpyAsync(&gen, &c->d_ctl->gen2, sizeof(gen), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const long long g = gen + 1;
+        HIP_TRY(c, hipMemcpyAsync(f1.data(), c->d_act + ((g + 2) % 3) * c->act_stride, (size_t)items,
+                                  hipMemcpyDeviceToHost, c->stream));  // generation g - 1
+        HIP_TRY(c, hipMemcpyAsync(f2.data(), c->d_act + ((g + 1) % 3) * c->act_stride, (size_t)items,
+                                  hipMemcpyDeviceToHost, c->stream));  // generation g - 2
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const int wl = 64 * c->cpt2, wo = strip_width2(c->cpt2);
+        const int f0 = c->in_first, fe = c->in_first + c->in_count;
+        long long need = 0;
+        for (int cc = 0; cc < nc; ++cc)
+            for (int ss = 0; ss < ns; ++ss) {
+                const int j0 = cc * c->rows2, j1 = std::min(j0 + c->rows2, c->ny);
+                const int c0 = ss * wo - kHalo;
+                bool in = false;
+                if (c->in_count > 0) {
+                    switch (c->in_side) {
+                    case FL_WEST: in = ss == 0 && j0 - 4 < fe && j1 + 4 > f0; break;
+                    case FL_EAST:
+                        in = c->nx - 1 >= c0 && c->nx - 1 < c0 + wl && j0 - 4 < fe && j1 + 4 > f0;
+                        break;
+                    case FL_SOUTH: in = j0 <= 4 && c0 < fe && c0 + wl > f0; break;
+                    default: in = j1 + 3 >= c->ny && c0 < fe && c0 + wl > f0; break;
+                    }
+                }
+                bool act = in || f2[(size_t)cc * ns + ss];
+                for (int dc = -1; dc <= 1 && !act; ++dc)
+                    for (int ds = -1; ds <= 1 && !act; ++ds) {
+                        const int s2 = ss + ds, c2 = cc + dc;
+                        if (s2 >= 0 && s2 < ns && c2 >= 0 && c2 < nc) act = f1[(size_t)c2 * ns + s2] != 0;
+                    }
+                need += act ? 1 : 0;
+            }
+        *next_items = need;
+        return FL_OK;
+    }
     const int ns = c->nstrips, nc = c->nchunks;
     const long long items = (long long)ns * nc;
     *total_items = items;
-    if (c->act_at != c->nstep) {  // stale flags: the next step computes everything
+    if (!(c->act_mode == 1 && c->act_at == c->nstep)) {  // stale flags: the next step computes everything
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         *next_items = items;
         return FL_OK;
@@ -1325,12 +1377,29 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     float ms1 = 0.f, ms2 = 0.f;
-    // one step per launch: frozen steps (dt = 0 streams the state, leaves it as it is)
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < trial_steps; ++r) {
-        hipError_t e = c->prec == FL_F64
-                           ? launch_step<double>(make_args<double>(c, c->nstep, tl, 1), tl.cpt, c->stream)
-                           : launch_step<float>(make_args<float>(c, c->nstep, tl, 1), tl.cpt, c->stream);
+    // one step per launch: frozen steps (dt = 0 streams the state, leaves it
+    // as it is).  With active tiles they skip as real steps would, after two
+    // untimed steps that compute every item and set the flags.
+    if (c->active) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
+    const int warm = c->active ? 2 : 0;
+    for (int r = 0; r < warm + trial_steps; ++r) {
+        if (r == warm) HIP_TRY(c, hipEventRecord(e0, c->stream));
+        hipError_t e;
+        if (c->prec == FL_F64) {
+            StepArgs<double> a = make_args<double>(c, c->nstep, tl, 1);
+            if (c->active) {
+                a.act = c->d_act;
+                a.act_stride = c->act_stride;
+            }
+            e = launch_step<double>(a, tl.cpt, c->stream);
+        } else {
+            StepArgs<float> a = make_args<float>(c, c->nstep, tl, 1);
+            if (c->active) {
+                a.act = c->d_act;
+                a.act_stride = c->act_stride;
+            }
+            e = launch_step<float>(a, tl.cpt, c->stream);
+        }
         if (e != hipSuccess) return hip_fail(c, e, "fl_autotune_fusion trial");
         c->nstep += 1;
     }
@@ -1338,7 +1407,13 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     HIP_TRY(c, hipEventSynchronize(e1));
     HIP_TRY(c, hipEventElapsedTime(&ms1, e0, e1));
     if ((st = fold_budget(c, tl))) return st;
-    // two steps per launch, as fl_step runs them (entry, launches, settling, exit)
+    c->act_at = -1;
+    // two steps per launch, as fl_step runs them (entry, launches, settling,
+    // exit); with active tiles after an untimed run that sets the flags
+    if (c->active) {
+        st = c->prec == FL_F64 ? fused_steps_t<double>(c, 4, 1) : fused_steps_t<float>(c, 4, 1);
+        if (st) return st;
+    }
     HIP_TRY(c, hipEventRecord(e0, c->stream));
     st = c->prec == FL_F64 ? fused_steps_t<double>(c, trial_steps, 1)
                            : fused_steps_t<float>(c, trial_steps, 1);

@@ -307,3 +307,45 @@ def test_workspace_holds_the_flags():
     f.close()
     ref = _run(sc, "f32", [300], False)[-1][0]
     assert np.array_equal(h, ref)
+
+
+def test_two_step_short_calls_keep_their_flags():
+    """Many short two-step calls in a row: the flags carry over from one call
+    to the next (nothing else moved the state), and the state stays that of
+    computing everything."""
+    sc = patchy(240, 100, 21)
+    chunks = [4] * 25 + [3, 6, 2]
+    ref = _run(sc, "f32", chunks, False, (1, 4))
+    got = _run(sc, "f32", chunks, True, fusion=(2, 2, 8))
+    _same(got, ref, "short calls", other_decomposition=True)
+
+
+def test_two_step_dry_closed_grid_computes_nothing():
+    nx, ny = 300, 64
+    z = synth._f32(np.random.default_rng(3).uniform(0, 1, (ny, nx)))
+    n = np.full((ny, nx), 0.03, np.float32)
+    sc = Scenario("dry", nx, ny, 1.0, z, n, np.zeros_like(z), None, None, dt_max=0.05)
+    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 8), active_tiles=True)
+    f.step(10)
+    nxt, tot = f.active_items()
+    assert tot == -(-(nx - 2) // 120) * (ny // 8) and nxt == 0, (nxt, tot)
+    f.step(10)
+    assert f.active_items()[0] == 0
+    assert f.get_report().steps == 20 and not f.get_depth().any()
+    f.close()
+
+
+def test_autotune_fusion_with_active_tiles_keeps_the_bits():
+    sc = patchy(200, 90, 33)
+    ref = _run(sc, "f32", [60], False, (2, 8))
+    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 8), cells_per_lane=2, rows_per_item=8,
+                         active_tiles=True)
+    f.step(20)
+    spl, ms = f.autotune_fusion(10)
+    assert spl in (1, 2) and ms > 0
+    f.step(40)
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    r = f.get_report(check=False)
+    f.close()
+    _same([(h, qx, qy, r)], [ref[-1]], "autotune_fusion", other_decomposition=True)
