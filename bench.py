@@ -204,16 +204,18 @@ ACTIVE_TILINGS = [(4, 32), (4, 16), (2, 16), (4, 8), (2, 8)]
 
 def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_depth=None,
                sample_every: int = 50):
-    """The same workload with active-tile skipping (one step per launch, the
-    tiling autotuned on the state after the warm-up, outside the timed
-    region): time per step, the work items computed (read back every
+    """The same workload with active-tile skipping.  On the state after the
+    warm-up, outside the timed region, the autotuners pick the single-step
+    tiling and then one or two steps per launch, both by skipping trial steps.
+    Reports the time per step, the work items computed (read back every
     `sample_every` steps in a second, untimed run) and whether the final depth
     equals that of the run that computes every item."""
     cells = sc.nx * sc.ny
     stream = torch.cuda.current_stream().cuda_stream
-    f = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True)
+    f = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True, fusion=2)
     f.step(warmup)
     best, _ = f.autotune(ACTIVE_TILINGS, 20)
+    spl, _ = f.autotune_fusion(20)
     torch.cuda.synchronize()
     ms = f.time_steps(steps)
     end_items, total = f.active_items()
@@ -227,7 +229,7 @@ def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_d
     f.close()
     progress("active tiles: timed; sampling computed items")
     g = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True,
-                         cells_per_lane=best[0], rows_per_item=best[1])
+                         cells_per_lane=best[0], rows_per_item=best[1], fusion=spl)
     g.step(warmup)
     counts = []
     for _ in range(steps // sample_every):
@@ -235,7 +237,8 @@ def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_d
         counts.append(g.active_items()[0])
     g.close()
     value = cells * steps / (ms / 1e3) / 1e9
-    return {"steps_per_launch": 1, "tiling_autotuned": list(best), "ms_per_step": round(ms / steps, 5),
+    return {"steps_per_launch_autotuned": spl, "single_step_tiling_autotuned": list(best),
+            "ms_per_step": round(ms / steps, 5),
             "gcell_s_grid_equivalent": round(value, 3),
             "vs_full_grid_headline": round(value / full_value, 2),
             "items_per_step": total, "items_computed_last_step": end_items,
@@ -450,11 +453,13 @@ def main():
                 cells * args.steps / (ev2 / 1e3) / 1e9, 3)
         if not args.no_active and args.precision == "f32":
             f = fl.from_scenario(scw, "f32", device=0, stream=torch.cuda.current_stream().cuda_stream,
-                                 active_tiles=True)
+                                 active_tiles=True, fusion=2)
             f.step(args.warmup)
             best3, _ = f.autotune(ACTIVE_TILINGS, 20)
+            spl3, _ = f.autotune_fusion(20)
             ev3 = f.time_steps(args.steps)
-            extras["prewetted_active_tiles_tiling_autotuned"] = list(best3)
+            extras["prewetted_active_tiles_single_step_tiling_autotuned"] = list(best3)
+            extras["prewetted_active_tiles_steps_per_launch_autotuned"] = spl3
             extras["prewetted_active_tiles_items_computed"] = list(f.active_items())
             f.close()
             extras["prewetted_active_tiles_gcell_s"] = round(cells * args.steps / (ev3 / 1e3) / 1e9, 3)

@@ -272,28 +272,34 @@ typedef enum { FL_BOUNDARY_SECTION = 0, FL_BOUNDARY_CELL_AREA = 1 } fl_boundary;
 fl_status fl_set_variant(fl_ctx *ctx, int32_t friction, int32_t boundary);
 
 /* Active-tile skipping (wet-region skipping) for fl_step, fl_time_steps,
- * fl_advance and the forward of reverse mode, with one step per launch: a
- * step does not recompute a work item when the item and the four items that
- * share an edge with it held no water (h <= 0), kept their depths and carried
- * no discharge in the step before, and the item itself also in the step
- * before that.  Such an item's cells cannot change: every face between two
- * cells without water is dry in eq. (3) (its water-surface height above the
- * higher bed is <= 0), so no water moves; the outflow of eq. (5) is zero for
- * an empty edge cell.  Items behind an inflow face (eq. 6) are always
- * computed.  Each item records, per step, one flag byte (three steps kept).
- * Results are the values of computing every item (a zero may differ in sign;
- * after a non-finite depth, which stops the clock, the states may differ).
- * Work scales with the wet area (a flood on a mostly dry DEM) instead of the
- * grid.  Another path that moves the state (batches, frozen tiling trials,
- * the reverse sweep) marks the flags stale; the next skipping step then
- * computes every item for two steps.  on: 0 or 1; takes effect at the next
- * fl_commit, which fails with EINVAL if two steps per launch are also set.
+ * fl_advance and the forward of reverse mode, with one or two steps per
+ * launch.  A launch does not recompute a work item when no water can reach
+ * it: every face between two cells without water is dry in eq. (3) (its
+ * water-surface height above the higher bed is <= 0), so no water moves, and
+ * the outflow of eq. (5) is zero for an empty edge cell.  One step per launch
+ * skips an item when the item and the four items that share an edge with it
+ * held no water (h <= 0), kept their depths and carried no discharge in the
+ * step before, and the item itself also in the step before that.  Two steps
+ * per launch reach two cells further, so they look at the 3 x 3 items around
+ * it, by launch (a launch that redoes a guessed second step skips exactly
+ * what the launch it replaces skipped).  Items behind an inflow face (eq. 6)
+ * are always computed.  Each item records one flag byte per step or launch
+ * (three kept).  Results are the values of computing every item (a zero may
+ * differ in sign; after a non-finite depth, which stops the clock, the states
+ * may differ).  Work scales with the wet area (a flood on a mostly dry DEM)
+ * instead of the grid.  Another path that moves the state (batches, frozen
+ * tiling trials, the reverse sweep, switching between one and two steps per
+ * launch) marks the flags stale; the next skipping launch then computes
+ * every item for two launches.  fl_autotune and fl_autotune_fusion time
+ * skipping trial steps.  on: 0 or 1; takes effect at the next fl_commit,
+ * which fails with EINVAL for two steps per launch with 1-row work items.
  * EINVAL: on not 0 or 1. */
 fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
 
-/* Work items the next step computes under active-tile skipping (*next_items)
- * and work items of a step (*total_items).  Synchronises.  ESTATE: not
- * committed with fl_set_active_tiles(ctx, 1). */
+/* Work items the next launch computes under active-tile skipping
+ * (*next_items) and work items of a launch (*total_items): those of the
+ * two-step kernel after a two-step run, else of the single-step kernel.
+ * Synchronises.  ESTATE: not committed with fl_set_active_tiles(ctx, 1). */
 fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items);
 
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
