@@ -191,7 +191,8 @@ hipError_t launch_flush(const StepArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_fold(const StepArgs<T>& a, hipStream_t s);
 template <typename T>
-hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out);
+hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out,
+                        bool act);  // act: some member skips work items (active tiles)
 template <typename T>
 hipError_t launch_hmax_init(const T* h, long long pitch, int nx, int ny, DevCtl* ctl,
                             hipStream_t s);

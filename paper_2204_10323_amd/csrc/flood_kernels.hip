@@ -216,7 +216,9 @@ __device__ __forceinline__ bool item_needed(const StepArgs<T>& a, int s, int c, 
 // with ACT, first the skip test, and last the item's flag of this step.
 template <typename T, int CPT, bool NTS, bool ACT = false, int VAR = 0>
 __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
-    if constexpr (ACT) {
+    // (in a batch, members without active tiles have no flags: a.act NULL)
+    const bool act = ACT && a.act != nullptr;
+    if (act) {
         const int s = item % a.nstrips, c = item / a.nstrips;
         if (!item_needed<T>(a, s, c, 64 * CPT - 4)) {
             // nothing moves: no deeper cell, no outflow, flag 0
@@ -244,7 +246,7 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     if ((threadIdx.x & 63) == 0) {
         if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], (unsigned long long)hb);
         if (slot >= 0) a.part_cur[slot] = outacc;
-        if constexpr (ACT) a.act[(a.phase % 3) * a.act_stride + item] = any_moved ? 1 : 0;
+        if (act) a.act[(a.phase % 3) * a.act_stride + item] = any_moved ? 1 : 0;
     }
 }
 
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
 // earlier by a running wave of the same XCD (the launch is cooperative: all
 // waves are resident), so the lowest unfinished entry can always run.  A
 // wait longer than spin_limit sleeps sets *error and exits.
-template <typename T, int CPT>
+template <typename T, int CPT, bool ACT>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
     const int lane = threadIdx.x & 63;
     const int x = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15);  // XCC_ID
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
         }
         const StepArgs<T>& a = S.a[(int)((S.n0 + k) % 6)];
         if (e == 0) clock_wave<T>(a);
-        else tile_item<T, CPT, false, false>(a, e - 1);
+        else tile_item<T, CPT, false, ACT>(a, e - 1);
         // release within the XCD: this wave's stores have reached L2
         __builtin_amdgcn_s_waitcnt(0);
         __asm__ volatile("" ::: "memory");
@@ -498,10 +500,10 @@ hipError_t launch_fold(const StepArgs<T>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, bool ACT>
 hipError_t launch_batch_cpt(const BatchArgs<T>& b, int device, hipStream_t s, int* blocks_out) {
     int per_cu = 0, ncu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<T, CPT>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<T, CPT, ACT>, 256, 0);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
@@ -509,15 +511,20 @@ hipError_t launch_batch_cpt(const BatchArgs<T>& b, int device, hipStream_t s, in
     if (blocks_out) *blocks_out = blocks;
     BatchArgs<T> bb = b;
     void* args[] = {&bb};
-    return hipLaunchCooperativeKernel((const void*)k_batch<T, CPT>, dim3(blocks), dim3(256), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)k_batch<T, CPT, ACT>, dim3(blocks), dim3(256), args,
+                                      0, s);
 }
 
 template <typename T>
-hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out) {
+hipError_t launch_batch(const BatchArgs<T>& b, int cpt, int device, hipStream_t s, int* blocks_out,
+                        bool act) {
     switch (cpt) {
-    case 1: return launch_batch_cpt<T, 1>(b, device, s, blocks_out);
-    case 2: return launch_batch_cpt<T, 2>(b, device, s, blocks_out);
-    case 4: return launch_batch_cpt<T, 4>(b, device, s, blocks_out);
+    case 1: return act ? launch_batch_cpt<T, 1, true>(b, device, s, blocks_out)
+                       : launch_batch_cpt<T, 1, false>(b, device, s, blocks_out);
+    case 2: return act ? launch_batch_cpt<T, 2, true>(b, device, s, blocks_out)
+                       : launch_batch_cpt<T, 2, false>(b, device, s, blocks_out);
+    case 4: return act ? launch_batch_cpt<T, 4, true>(b, device, s, blocks_out)
+                       : launch_batch_cpt<T, 4, false>(b, device, s, blocks_out);
     default: return hipErrorInvalidValue;
     }
 }
@@ -549,8 +556,8 @@ template hipError_t launch_flush<float>(const StepArgs<float>&, hipStream_t);
 template hipError_t launch_flush<double>(const StepArgs<double>&, hipStream_t);
 template hipError_t launch_fold<float>(const StepArgs<float>&, hipStream_t);
 template hipError_t launch_fold<double>(const StepArgs<double>&, hipStream_t);
-template hipError_t launch_batch<float>(const BatchArgs<float>&, int, int, hipStream_t, int*);
-template hipError_t launch_batch<double>(const BatchArgs<double>&, int, int, hipStream_t, int*);
+template hipError_t launch_batch<float>(const BatchArgs<float>&, int, int, hipStream_t, int*, bool);
+template hipError_t launch_batch<double>(const BatchArgs<double>&, int, int, hipStream_t, int*, bool);
 template hipError_t launch_hmax_init<float>(const float*, long long, int, int, DevCtl*, hipStream_t);
 template hipError_t launch_hmax_init<double>(const double*, long long, int, int, DevCtl*,
                                              hipStream_t);

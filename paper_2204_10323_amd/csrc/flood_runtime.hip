@@ -85,6 +85,7 @@ struct fl_ctx {
     // stale, and they are set to 1 (compute everything) before the next
     // skipping run.
     int active = 0, act_mode = 0;
+    int act_cpt = 0, act_rows = 0;  // the single-step tiling (own or a batch's) the flags refer to
     unsigned char* d_act = nullptr;
     long long act_stride = 0, act_at = -1;
     // method variant (fl_set_variant): bit 0 vector friction, bit 1 cell-area boundaries
@@ -629,8 +630,13 @@ fl_status do_commit(fl_ctx* c) {
     return FL_OK;
 }
 
+// Do the flags describe the state for single-step work items of tiling (cpt, rows)?
+bool act_flags_hold(const fl_ctx* c, int cpt, int rows) {
+    return c->act_mode == 1 && c->act_at == c->nstep && c->act_cpt == cpt && c->act_rows == rows;
+}
+
 fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
-    if (c->active && nsteps > 0 && !(c->act_mode == 1 && c->act_at == c->nstep)) {
+    if (c->active && nsteps > 0 && !act_flags_hold(c, c->cpt, c->rows)) {
         // flags stale: compute every item in the next two steps
         HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
     }
@@ -648,6 +654,8 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
     if (c->active) {
         c->act_mode = 1;
         c->act_at = c->nstep;
+        c->act_cpt = c->cpt;
+        c->act_rows = c->rows;
     }
     return FL_OK;
 }
@@ -1116,7 +1124,7 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
     const int ns = c->nstrips, nc = c->nchunks;
     const long long items = (long long)ns * nc;
     *total_items = items;
-    if (!(c->act_mode == 1 && c->act_at == c->nstep)) {  // stale flags: the next step computes everything
+    if (!act_flags_hold(c, c->cpt, c->rows)) {  // stale flags: the next step computes everything
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         *next_items = items;
         return FL_OK;
@@ -1868,7 +1876,14 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         for (int m : bins[x]) {
             fl_ctx* c = b->members[m];
             const Tiling tl = tiling_of(c, b->cpt, b->rows);
-            for (int r = 0; r < 6; ++r) scen[idx].a[r] = make_args<T>(c, r, tl, freeze);
+            for (int r = 0; r < 6; ++r) {
+                scen[idx].a[r] = make_args<T>(c, r, tl, freeze);
+                if (c->active) {
+                    // the member's flags, indexed by its step counter as in its own steps
+                    scen[idx].a[r].act = c->d_act;
+                    scen[idx].a[r].act_stride = c->act_stride;
+                }
+            }
             scen[idx].n0 = c->nstep;
             scen[idx].items = tl.nstrips * tl.nchunks;
             scen[idx].first = first;
@@ -1895,6 +1910,14 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         if (fold_budget(c, own)) return bfail(b, FL_EHIP, c->err);
     }
     for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    bool any_active = false;
+    for (fl_ctx* c : b->members) {
+        if (!c->active) continue;
+        any_active = true;
+        // flags of another tiling or another path: compute every item in the first two steps
+        if (!act_flags_hold(c, b->cpt, b->rows))
+            BHIP_TRY(b, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, b->stream));
+    }
     BHIP_TRY(b, hipMemcpyAsync(b->d_scen, scen.data(), bytes, hipMemcpyHostToDevice, b->stream));
     BHIP_TRY(b, hipMemsetAsync(b->d_sync, 0, sizeof(unsigned long long) * (S + kMaxXcc), b->stream));
     BHIP_TRY(b, hipMemsetAsync(b->d_error, 0, sizeof(int), b->stream));
@@ -1910,7 +1933,7 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         BHIP_TRY(b, hipEventCreate(&e1));
         BHIP_TRY(b, hipEventRecord(e0, b->stream));
     }
-    BHIP_TRY(b, launch_batch<T>(ba, b->cpt, b->device, b->stream, &b->last_blocks));
+    BHIP_TRY(b, launch_batch<T>(ba, b->cpt, b->device, b->stream, &b->last_blocks, any_active));
     if (ms) BHIP_TRY(b, hipEventRecord(e1, b->stream));
     int error = 0;
     BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
@@ -1920,7 +1943,15 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
-    for (fl_ctx* c : b->members) c->nstep += nsteps;
+    for (fl_ctx* c : b->members) {
+        c->nstep += nsteps;
+        if (c->active) {
+            c->act_mode = 1;
+            c->act_at = c->nstep;
+            c->act_cpt = b->cpt;
+            c->act_rows = b->rows;
+        }
+    }
     for (int k = 0; k < S; ++k) {
         fl_ctx* c = b->members[b->order[k]];
         if (fold_budget(c, tiling_of(c, b->cpt, b->rows))) return bfail(b, FL_EHIP, c->err);
@@ -2039,7 +2070,12 @@ fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncan
         }
         float ms = 0.f;
         // Frozen steps (dt = 0) stream the whole state like real steps but leave it unchanged.
-        st = batch_run(b, trial_steps, 1, &ms);
+        // Members with active tiles first take two untimed steps that set their flags for
+        // this tiling, so that the timed ones skip as real steps would.
+        bool any_active = false;
+        for (fl_ctx* c : b->members) any_active = any_active || c->active;
+        if (any_active) st = batch_run(b, 2, 1, nullptr);
+        if (!st) st = batch_run(b, trial_steps, 1, &ms);
         if (st) {
             b->cpt = cpt0;
             b->rows = rows0;

@@ -38,9 +38,9 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
     the wait between a member's steps.
     tiling: (cells_per_lane, rows_per_item) of the batch launch (mode
     "batch"), or None for the autotuner's choice.
-    active_tiles: members stepped one after another skip the work items that
-    hold no water (fl_set_active_tiles); their tiling is then autotuned with
-    skipping trial steps.  The batch launch computes every item.
+    active_tiles: the members skip the work items that no water can reach
+    (fl_set_active_tiles), in the batch launch and one after another; the
+    tilings are then autotuned with skipping trial steps.
     Returns per-member arrays: flooded cell count and area, deepest cell,
     inflow and outflow volume, relative volume-budget error, and the depths if
     keep_depths; the mode used and its time in milliseconds.

@@ -349,3 +349,49 @@ def test_autotune_fusion_with_active_tiles_keeps_the_bits():
     r = f.get_report(check=False)
     f.close()
     _same([(h, qx, qy, r)], [ref[-1]], "autotune_fusion", other_decomposition=True)
+
+
+def _snap(f):
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    return h, qx, qy, f.get_report(check=False)
+
+
+@pytest.mark.parametrize("own,batch", [((1, 4), (2, 8)), ((2, 8), (2, 8))])
+def test_batch_members_with_active_tiles(own, batch):
+    """Members with and without active tiles stepped by one batch, before and
+    after steps of their own: the values of computing every item.  With the
+    same tiling in the batch and alone the flags carry over."""
+    scs = [patchy(180, 70, 41), patchy(260, 90, 42), patchy(90, 150, 43)]
+    chunks = [5, 30, 20]
+    refs = [_run(sc, "f32", chunks, False, (1, 4)) for sc in scs]
+    fs = [fl.from_scenario(sc, "f32", cells_per_lane=own[0], rows_per_item=own[1],
+                           active_tiles=(k != 1)) for k, sc in enumerate(scs)]
+    got = [[] for _ in scs]
+    for k, f in enumerate(fs):
+        f.step(chunks[0])
+        got[k].append(_snap(f))
+    b = fl.Batch(fs)
+    b.set_tiling(*batch)
+    b.run(chunks[1])
+    b.close()
+    for k, f in enumerate(fs):
+        got[k].append(_snap(f))
+        f.step(chunks[2])
+        got[k].append(_snap(f))
+        f.close()
+        _same(got[k], refs[k], f"member {k}", other_decomposition=True)
+
+
+def test_batch_autotune_with_active_members_keeps_the_bits():
+    scs = [patchy(200, 80, 51), patchy(150, 120, 52)]
+    refs = [_run(sc, "f32", [60], False, (1, 4)) for sc in scs]
+    fs = [fl.from_scenario(sc, "f32", active_tiles=True) for sc in scs]
+    b = fl.Batch(fs)
+    b.run(10)
+    b.autotune([(2, 8), (1, 4), (4, 16)], 5)
+    b.run(50)
+    b.close()
+    for f, ref in zip(fs, refs):
+        _same([_snap(f)], [ref[-1]], "batch autotune", other_decomposition=True)
+        f.close()

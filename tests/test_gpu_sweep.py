@@ -105,3 +105,15 @@ def test_sweep_active_tiles_same_bits():
     for hb, ha in zip(b["depth"], a["depth"]):
         assert np.array_equal(hb, ha)
     assert np.array_equal(b["v_in"], a["v_in"]) and np.array_equal(b["v_out"], a["v_out"])
+
+
+def test_sweep_batch_with_active_tiles_same_bits():
+    v, z, n, inflow, outflow = _valley()
+    qs = [15.0, 150.0, 600.0]
+    s = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True, mode="sequential")
+    b = discharge_sweep(z, n, v.dx, inflow, outflow, qs, 150, DT, keep_depths=True, mode="batch",
+                        active_tiles=True)
+    assert b["mode"] == "batch"
+    for hs, hb in zip(s["depth"], b["depth"]):
+        assert np.array_equal(hs, hb)
+    assert np.array_equal(s["v_in"], b["v_in"])
