@@ -131,7 +131,31 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
     b.close()
     for f in ctxs:
         f.close()
+    progress("ensemble: batch done; with active tiles")
+    # the same members from the same start with active tiles (tilings autotuned
+    # on skipping trial steps): batched, and one after another
+    actx = [fl.from_scenario(sc, "f32", stream=stream, active_tiles=True) for sc in scs]
+    ba = fl.Batch(actx)
+    best_a, _ = ba.autotune(cands + [(2, 8), (1, 8)], trial_steps)
+    batch_act_ms = ba.time(steps)
+    rep_a = [f.get_report() for f in actx]
+    ba.close()
+    for f in actx:
+        f.close()
+    seq_act_ms = 0.0
+    for sc in scs:
+        g = fl.from_scenario(sc, "f32", stream=stream, active_tiles=True)
+        g.autotune(SMALL_GRID_TILINGS, 10)
+        g.step(3)
+        seq_act_ms += g.time_steps(steps)
+        g.close()
     return {"members": members, "sides": [min(sizes), max(sizes)], "cells": cells, "steps": steps,
+            "active_tiles": {"batch_tiling_autotuned": list(best_a),
+                             "batch_gcell_s_grid_equivalent": round(cells * steps / (batch_act_ms / 1e3) / 1e9, 3),
+                             "sequential_gcell_s_grid_equivalent": round(cells * steps / (seq_act_ms / 1e3) / 1e9, 3),
+                             "batch_vs_sequential": round(seq_act_ms / batch_act_ms, 3),
+                             "batch_vs_full_batch": round(batch_ms / batch_act_ms, 3),
+                             "max_budget_error": max(r.budget_error() for r in rep_a)},
             "tiling_autotuned": list(best),
             "batch_gcell_s": round(cells * steps / (batch_ms / 1e3) / 1e9, 3),
             "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
