@@ -90,6 +90,28 @@ def cpu_baseline(sc, budget_s: float = 20.0):
                       f"from the same initial state, {el:.1f} s wall on {cores} host threads"}
 
 
+def cpu_single_thread(sc):
+    """The FP64 oracle on one host thread: the first step of the same workload;
+    with the host's CPU model."""
+    import oracle
+    o = oracle.Run(sc, nthreads=1)
+    t0 = time.perf_counter()
+    o.step(1)
+    el = time.perf_counter() - t0
+    del o
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"gcell_s": round(sc.nx * sc.ny / el / 1e9, 5), "threads": oracle.threads_used(1),
+            "sample": f"FP64 oracle, first step of the {sc.nx}x{sc.ny} workload, {el:.1f} s wall",
+            "host_cpu": model, "host_logical_cpus": os.cpu_count()}
+
+
 # (cells per lane, rows per work item) tried by the autotuner on small grids
 SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
 
@@ -509,6 +531,7 @@ def main():
         if args.extra_wet and args.workload == "valley16384":
             sc, _ = build_workload(args.workload)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
+        extras["cpu_oracle_single_thread"] = cpu_single_thread(sc)
     out["extras"] = extras
     print(json.dumps(out), flush=True)
 
