@@ -317,9 +317,11 @@ fl_status fl_autotune(fl_ctx *ctx, const int32_t *candidates, int32_t ncand, int
 /* Time one step per launch (the current tiling) against two steps per launch
  * (the current two-step tiling) over trial_steps frozen steps each (dt = 0:
  * the state is streamed but left as it is), and keep the faster for the
- * following fl_step calls; both give the same bits.  Two steps per launch pay
- * off on large grids that HBM bandwidth bounds; wet or cache-resident grids
- * can be faster with one.  *steps_per_launch receives the choice (1 or 2),
+ * following fl_step calls; both give the same bits.  With active tiles the
+ * trial steps skip as real steps would (after untimed steps that set the
+ * flags).  Two steps per launch pay off on large grids that HBM bandwidth
+ * bounds, and under active tiles when many items hold water; small,
+ * cache-resident or nearly dry grids can be faster with one.  *steps_per_launch receives the choice (1 or 2),
  * *ms_per_step its time per step.  ESTATE: not committed, or committed
  * without fl_set_fusion(ctx, 2, ...) (the two-step buffers).  EINVAL:
  * trial_steps < 2. */
@@ -367,14 +369,16 @@ fl_status fl_adj_backward(fl_ctx *ctx, const void *dl_dseries, double *grad_n, i
  * precision, any sizes) stepped together by ONE persistent launch.  Members
  * run the same kernels as fl_step, so each member's result is bitwise the
  * result of stepping it alone; a member's step k waits only for its own step
- * k-1, never for the other members.  The batch borrows its members: they
- * must outlive it and stay committed.  Motivated by the what-if and
+ * k-1, never for the other members.  Members with active tiles skip the work
+ * items no water can reach, in the batch as in their own steps; members
+ * without are computed in full.  The batch borrows its members: they must
+ * outlive it and stay committed.  Motivated by the what-if and
  * parameter-space ensembles the paper points to (Broader Impacts, Future
  * Work). */
 
 /* Create a batch of nmembers committed contexts.  EINVAL: no members,
- * mixed devices or precisions, a context listed twice.  ESTATE: a member not
- * committed. */
+ * mixed devices or precisions, a context listed twice, a member with a method
+ * variant (fl_set_variant).  ESTATE: a member not committed. */
 fl_status fl_batch_create(fl_batch **batch, int32_t nmembers, fl_ctx *const *members);
 
 /* Work decomposition of the batch launch: cells per lane along x (1, 2, 4;
@@ -383,8 +387,10 @@ fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t r
 
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
  * trial_steps frozen steps (dt = 0: the state is streamed like a real step
- * but left unchanged) and keep the fastest.  best[2] receives it, *best_ms
- * its time per step.  The members' states and clocks are unchanged. */
+ * but left unchanged) and keep the fastest.  Members with active tiles first
+ * take two untimed frozen steps per candidate, so that the timed ones skip
+ * as real steps would.  best[2] receives it, *best_ms its time per step.  The
+ * members' states and clocks are unchanged. */
 fl_status fl_batch_autotune(fl_batch *batch, const int32_t *candidates, int32_t ncand,
                             int32_t trial_steps, int32_t *best, double *best_ms);
 
