@@ -291,9 +291,15 @@ fl_status fl_set_variant(fl_ctx *ctx, int32_t friction, int32_t boundary);
  * tiling trials, the reverse sweep, switching between one and two steps per
  * launch) marks the flags stale; the next skipping launch then computes
  * every item for two launches.  fl_autotune and fl_autotune_fusion time
- * skipping trial steps.  on: 0 or 1; takes effect at the next fl_commit,
- * which fails with EINVAL for two steps per launch with 1-row work items.
- * EINVAL: on not 0 or 1. */
+ * skipping trial steps.
+ * on: 0 off; 1 on, each work item of a single-step launch makes the skip
+ * test itself (one wave per item); 2 on, single-step launches first select
+ * the items to compute (one thread per item, an ordered list) and a
+ * persistent grid computes the list, which is faster when few items hold
+ * water.  fl_autotune times both and keeps the faster with the tiling.  Two
+ * steps per launch and batches always use the per-item test.  Takes effect
+ * at the next fl_commit, which fails with EINVAL for two steps per launch
+ * with 1-row work items.  EINVAL: on not 0, 1 or 2. */
 fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
 
 /* Work items the next launch computes under active-tile skipping

@@ -263,9 +263,12 @@ class Flood:
             raise ValueError("set_variant: friction 'face'|'vector', boundary 'section'|'cell_area'")
         _check(self.ctx, lib().fl_set_variant(self.ctx, fr, bd))
 
-    def set_active_tiles(self, on: bool = True):
-        """Active-tile (wet-region) skipping for one step per launch (fl_set_active_tiles)."""
-        _check(self.ctx, lib().fl_set_active_tiles(self.ctx, 1 if on else 0))
+    def set_active_tiles(self, on=True):
+        """Active-tile (wet-region) skipping (fl_set_active_tiles): False/0 off,
+        True/1 the per-item skip test, 2 single-step launches select a list of
+        items first."""
+        mode = 2 if on == 2 else (1 if on else 0)
+        _check(self.ctx, lib().fl_set_active_tiles(self.ctx, mode))
 
     def active_items(self):
         """(work items the next step computes, work items per step) (fl_active_items)."""
@@ -514,7 +517,7 @@ def from_scenario(sc, precision: str = "f32", device: int = 0, stream=None, comm
     if fusion is not None:
         f.set_fusion(*((fusion,) if isinstance(fusion, int) else tuple(fusion)))
     if active_tiles:
-        f.set_active_tiles(True)
+        f.set_active_tiles(active_tiles)
     if variant is not None:
         f.set_variant(*variant)
     if commit:

@@ -95,6 +95,9 @@ struct StepArgs {
     // every item is computed every step
     unsigned char* act;
     long long act_stride;         // bytes per slot (>= nstrips * nchunks)
+    int* act_list;                // the items a step computes (filled by the selection kernel)
+    unsigned* act_count;          // [2]: list length of the step, by step parity; then [2][8]
+                                  // work counters of the list kernel's block groups
     // method variant: bit 0 = friction by the discharge vector's magnitude,
     // bit 1 = boundary cells with the cell area (eq. 5 and 6 taken literally)
     int variant;
@@ -184,6 +187,10 @@ struct AdjArgs {
 // Host-side launchers (flood_kernels.hip, flood_adjoint.hip).
 template <typename T>
 hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s);
+// Size the persistent grid of the active-tile step for cells-per-lane cpt
+// (an occupancy query; call it outside graph capture before the first such launch).
+template <typename T>
+hipError_t prepare_step_list(int cpt);
 template <typename T>
 hipError_t launch_prime(const StepArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -213,12 +213,13 @@ __device__ __forceinline__ bool item_needed(const StepArgs<T>& a, int s, int c, 
 
 // Work item `item` of one step (strip fastest): the marching tile, then the
 // wave's deepest cell into the next max slot and its outflow partial sum;
-// with ACT, first the skip test, and last the item's flag of this step.
-template <typename T, int CPT, bool NTS, bool ACT = false, int VAR = 0>
+// with ACT, first the skip test (unless SELECTED: the selection kernel made
+// it), and last the item's flag of this step.
+template <typename T, int CPT, bool NTS, bool ACT = false, int VAR = 0, bool SELECTED = false>
 __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
     // (in a batch, members without active tiles have no flags: a.act NULL)
     const bool act = ACT && a.act != nullptr;
-    if (act) {
+    if (act && !SELECTED) {
         const int s = item % a.nstrips, c = item / a.nstrips;
         if (!item_needed<T>(a, s, c, 64 * CPT - 4)) {
             // nothing moves: no deeper cell, no outflow, flag 0
@@ -247,6 +248,115 @@ __device__ __forceinline__ void tile_item(const StepArgs<T>& a, int item) {
         if (hb) atomicMax(&a.ctl->hmax[(a.phase + 1) % 3], (unsigned long long)hb);
         if (slot >= 0) a.part_cur[slot] = outacc;
         if (act) a.act[(a.phase % 3) * a.act_stride + item] = any_moved ? 1 : 0;
+    }
+}
+
+// Active tiles, per step: the skip test of every work item (one thread per
+// item), an ordered compaction of the items that must be computed, and a
+// persistent grid over that list.
+template <typename T, int CPT>
+__device__ __forceinline__ bool select_need(const StepArgs<T>& a, long long item) {
+    const int s = (int)(item % a.nstrips), c = (int)(item / a.nstrips);
+    if (feeds_inflow<T>(a, s, c, 64 * CPT - 4)) return true;
+    const unsigned char* f1 = a.act + ((a.phase + 2) % 3) * a.act_stride;  // step n-1
+    const unsigned char* f2 = a.act + ((a.phase + 1) % 3) * a.act_stride;  // step n-2
+    return f1[item] || f2[item] || (s > 0 && f1[item - 1]) || (s + 1 < a.nstrips && f1[item + 1]) ||
+           (c > 0 && f1[item - a.nstrips]) || (c + 1 < a.nchunks && f1[item + a.nstrips]);
+}
+
+// Items of this block that must be computed, and the ranks of its waves'.
+__device__ __forceinline__ unsigned block_rank(bool need, unsigned& rank_in_block) {
+    __shared__ unsigned wave_n[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long mask = __ballot(need);
+    if (lane == 0) wave_n[w] = (unsigned)__popcll(mask);
+    __syncthreads();
+    unsigned before = 0, total = 0;
+    for (int k = 0; k < 4; ++k) {
+        before += (k < w) ? wave_n[k] : 0u;
+        total += wave_n[k];
+    }
+    rank_in_block = before + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    return total;
+}
+
+// Pass 1: skipped items get flag 0 and a zero outflow partial; each block
+// counts the items that must be computed.
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_select_count(StepArgs<T> a, unsigned* block_n) {
+    const long long items = (long long)a.nstrips * a.nchunks;
+    const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool need = false;
+    if (item < items) {
+        need = select_need<T, CPT>(a, item);
+        if (!need) {
+            a.act[(a.phase % 3) * a.act_stride + item] = 0;
+            const int slot = part_slot<T>(a, (int)(item % a.nstrips), (int)(item / a.nstrips));
+            if (slot >= 0) a.part_cur[slot] = 0.0;
+        }
+    }
+    unsigned rank;
+    const unsigned n = block_rank(need, rank);
+    if (threadIdx.x == 0) block_n[blockIdx.x] = n;
+}
+
+// Pass 2: the items that must be computed, in raster order, at the offset the
+// counts of the blocks before give; the last block writes the total.
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void k_select_scatter(StepArgs<T> a, const unsigned* block_n) {
+    __shared__ unsigned part[256];
+    const long long items = (long long)a.nstrips * a.nchunks;
+    const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned off = 0;
+    for (unsigned b = threadIdx.x; b < blockIdx.x; b += blockDim.x) off += block_n[b];
+    part[threadIdx.x] = off;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < (unsigned)w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    const unsigned base = part[0];
+    const bool need = item < items && select_need<T, CPT>(a, item);
+    unsigned rank;
+    const unsigned n = block_rank(need, rank);
+    if (need) a.act_list[base + rank] = (int)item;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) a.act_count[a.phase & 1] = base + n;
+    // the step's work counters of the list kernel (one per group of blocks)
+    if (blockIdx.x == 0 && threadIdx.x < 8) a.act_count[2 + (a.phase & 1) * 8 + threadIdx.x] = 0u;
+}
+
+// Pass 3: a persistent grid (block 0: the clock) that fits the device at
+// once, so its size does not depend on the list and the launch can be
+// captured.  Blocks go round-robin to the 8 XCDs; XCD x takes the x-th eighth
+// of the list, a run of neighbouring items (shared halo rows meet in one L2)
+// of the same length on every XCD wherever the water is.  (Fewer than 8
+// blocks: each block takes its own share.)  Each wave takes one item by its
+// index, then further ones from the group's counter as it finishes, so items
+// of uneven cost spread over the waves as they free up.
+// occupancy of the one-wave-per-item kernel (the loop must not cost a wave per SIMD)
+template <typename T, int CPT>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 ? (CPT == 4 ? 3 : CPT == 2 ? 5 : 7)
+                                                   : (CPT == 4 ? 1 : CPT == 2 ? 3 : 4)))
+void k_step_list(StepArgs<T> a) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 64) clock_wave<T>(a);
+        return;
+    }
+    const unsigned count = a.act_count[a.phase & 1];
+    const unsigned nblk = gridDim.x - 1, b = blockIdx.x - 1;
+    const unsigned groups = nblk < 8u ? nblk : 8u;
+    const unsigned g = b % groups, per = (nblk - g + groups - 1u) / groups;  // blocks of group g
+    const unsigned lo = (unsigned)((unsigned long long)count * g / groups);
+    const unsigned hi = (unsigned)((unsigned long long)count * (g + 1u) / groups);
+    const unsigned nw = per * 4u;
+    unsigned* next = a.act_count + 2 + (a.phase & 1) * 8 + g;
+    unsigned idx = lo + (b / groups) * 4u + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    while (idx < hi) {
+        const int item = __builtin_amdgcn_readfirstlane(a.act_list[idx]);
+        tile_item<T, CPT, true, true, 0, true>(a, item);
+        unsigned k = 0;
+        if ((threadIdx.x & 63) == 0) k = atomicAdd(next, 1u);
+        idx = lo + nw + __builtin_amdgcn_readfirstlane(k);
     }
 }
 
@@ -429,6 +539,56 @@ __global__ void k_volume_sum(const double* part, int nparts, double* out) {
 // ----------------------------------------------------------------- launchers
 int strip_width(int cpt) { return 64 * cpt - 4; }
 
+// Blocks of k_step_list<T, CPT> the current device holds at once (queried
+// once; prepare_step_list does it outside any graph capture).
+template <typename T, int CPT>
+int& list_resident() {
+    static int resident = 0;
+    return resident;
+}
+
+template <typename T, int CPT>
+hipError_t query_list_resident() {
+    int& resident = list_resident<T, CPT>();
+    if (resident > 0) return hipSuccess;
+    int per_cu = 0, ncu = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_list<T, CPT>, 256, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * std::max(1, ncu);
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t prepare_step_list(int cpt) {
+    switch (cpt) {
+    case 1: return query_list_resident<T, 1>();
+    case 2: return query_list_resident<T, 2>();
+    case 4: return query_list_resident<T, 4>();
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The selection kernel, then the persistent list kernel with as many blocks
+// as the device holds at once (but no more than the items need).
+template <typename T, int CPT>
+hipError_t launch_step_list(const StepArgs<T>& a, long long items, hipStream_t s) {
+    hipError_t e = query_list_resident<T, CPT>();
+    if (e != hipSuccess) return e;
+    const int resident = list_resident<T, CPT>();
+    const unsigned sel_blocks = (unsigned)std::max<long long>(1, (items + 255) / 256);
+    // the per-block counts live after the list's `items` entries (capacity act_stride + blocks)
+    unsigned* block_n = reinterpret_cast<unsigned*>(a.act_list + a.act_stride);
+    hipLaunchKernelGGL((k_select_count<T, CPT>), dim3(sel_blocks), dim3(256), 0, s, a, block_n);
+    hipLaunchKernelGGL((k_select_scatter<T, CPT>), dim3(sel_blocks), dim3(256), 0, s, a,
+                       (const unsigned*)block_n);
+    const long long want = (items + 3) / 4;
+    const unsigned blocks = (unsigned)(1 + std::min<long long>(want, resident));
+    hipLaunchKernelGGL((k_step_list<T, CPT>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, bool ACT, int VAR = 0>
 hipError_t launch_step_act(const StepArgs<T>& a, int cpt, int blocks, hipStream_t s) {
     switch (cpt) {
@@ -459,9 +619,19 @@ hipError_t launch_step(const StepArgs<T>& a, int cpt, hipStream_t s) {
         }
     }
     if (a.act) {
-        // the flags of every item must fit in a slot
+        // the flags (and list entries) of every item must fit in a slot
         if (items > a.act_stride) return hipErrorInvalidValue;
-        return launch_step_act<T, true>(a, cpt, blocks, s);
+        // with a list: the selection kernels and a persistent grid over the
+        // items to compute (best when few items hold water); without: one
+        // wave per item that makes the skip test itself
+        if (!a.act_list) return launch_step_act<T, true>(a, cpt, blocks, s);
+        if (!a.act_count) return hipErrorInvalidValue;
+        switch (cpt) {
+        case 1: return launch_step_list<T, 1>(a, items, s);
+        case 2: return launch_step_list<T, 2>(a, items, s);
+        case 4: return launch_step_list<T, 4>(a, items, s);
+        default: return hipErrorInvalidValue;
+        }
     }
     return launch_step_act<T, false>(a, cpt, blocks, s);
 }
@@ -548,6 +718,8 @@ hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* pa
     return hipGetLastError();
 }
 
+template hipError_t prepare_step_list<float>(int);
+template hipError_t prepare_step_list<double>(int);
 template hipError_t launch_step<float>(const StepArgs<float>&, int, hipStream_t);
 template hipError_t launch_step<double>(const StepArgs<double>&, int, hipStream_t);
 template hipError_t launch_prime<float>(const StepArgs<float>&, hipStream_t);

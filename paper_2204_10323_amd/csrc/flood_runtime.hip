@@ -87,6 +87,9 @@ struct fl_ctx {
     int active = 0, act_mode = 0;
     int act_cpt = 0, act_rows = 0;  // the single-step tiling (own or a batch's) the flags refer to
     unsigned char* d_act = nullptr;
+    int* d_act_list = nullptr;        // items a single-step launch computes (selection kernel)
+    int act_list_mode = 0;            // 1: single-step launches select a list first (fl_autotune)
+    unsigned* d_act_count = nullptr;  // [2] their number, by step parity; [2 + 8 p + g] work counters
     long long act_stride = 0, act_at = -1;
     // method variant (fl_set_variant): bit 0 vector friction, bit 1 cell-area boundaries
     int variant = 0;
@@ -309,14 +312,21 @@ StepArgs<T> make_args(const fl_ctx* c, long long n, const Tiling& tl, int freeze
     return a;
 }
 
+// The flags and list of active-tile skipping, for a single-step launch.
+template <typename T>
+void set_act(const fl_ctx* c, StepArgs<T>& a) {
+    if (!c->active) return;
+    a.act = c->d_act;
+    a.act_stride = c->act_stride;
+    a.act_list = c->act_list_mode ? c->d_act_list : nullptr;
+    a.act_count = c->d_act_count;
+}
+
 // One step of the context's own run: with active-tile skipping when it is on.
 template <typename T>
 hipError_t enqueue_one_t(fl_ctx* c, long long n, hipStream_t s) {
     StepArgs<T> a = make_args<T>(c, n);
-    if (c->active) {
-        a.act = c->d_act;
-        a.act_stride = c->act_stride;
-    }
+    set_act<T>(c, a);
     return launch_step<T>(a, c->cpt, s);
 }
 
@@ -467,6 +477,13 @@ long long act_slot_bytes(int nx, int ny) {
     return (long long)((nx + w - 1) / w) * ny;
 }
 
+// Entries of the active-tile list: one per work item, then one count per
+// block of 256 items of the selection kernels.
+long long act_list_ints(int nx, int ny) {
+    const long long items = act_slot_bytes(nx, ny);
+    return items + (items + 255) / 256 + 1;
+}
+
 size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step, bool active) {
     const size_t es = elem_size(prec);
     const long long align = 256 / (long long)es;
@@ -481,7 +498,9 @@ size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step, bool ac
     b += 2 * ws_round(sizeof(double) * 4096);
     b += ws_round(sizeof(double) * kVolumeParts) + ws_round(sizeof(double)) + ws_round(sizeof(DevCtl));
     if (two_step) b += 4 * ws_round(sizeof(double) * side);
-    if (active) b += ws_round((size_t)(3 * act_slot_bytes(nx, ny)));
+    if (active)
+        b += ws_round((size_t)(3 * act_slot_bytes(nx, ny))) +
+             ws_round(sizeof(int) * (size_t)act_list_ints(nx, ny)) + ws_round(18 * sizeof(unsigned));
     return b;
 }
 
@@ -534,11 +553,15 @@ fl_status do_commit(fl_ctx* c) {
     if ((st = dalloc(c, (void**)&c->d_vol, sizeof(double)))) return st;
     if ((st = dalloc(c, (void**)&c->d_ctl, sizeof(DevCtl)))) return st;
     c->d_act = nullptr;
+    c->d_act_list = nullptr;
+    c->d_act_count = nullptr;
     c->act_stride = 0;
     c->act_at = -1;
     if (c->active) {
         c->act_stride = act_slot_bytes(nx, ny);
         if ((st = dalloc(c, (void**)&c->d_act, (size_t)(3 * c->act_stride)))) return st;
+        if ((st = dalloc(c, (void**)&c->d_act_list, sizeof(int) * (size_t)act_list_ints(nx, ny)))) return st;
+        if ((st = dalloc(c, (void**)&c->d_act_count, 18 * sizeof(unsigned)))) return st;
     }
 
     // cell fields
@@ -611,6 +634,13 @@ fl_status do_commit(fl_ctx* c) {
     HIP_TRY(c, hipMemcpyAsync(&c->v0, c->d_vol, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->v0 *= c->dx * c->dx;
+    if (c->active) {
+        // size the active-tile step's persistent grids before any capture
+        for (int cp : {1, 2, 4}) {
+            if (c->prec == FL_F64 && cp == 4) continue;
+            HIP_TRY(c, c->prec == FL_F64 ? prepare_step_list<double>(cp) : prepare_step_list<float>(cp));
+        }
+    }
     if ((st = capture_graph(c))) return st;
     if (c->fuse == 2) {
         c->cpt2 = c->cpt2_req ? c->cpt2_req : (c->prec == FL_F64 ? 1 : 2);
@@ -1066,8 +1096,9 @@ fl_status fl_set_variant(fl_ctx* c, int32_t friction, int32_t boundary) {
 
 fl_status fl_set_active_tiles(fl_ctx* c, int32_t on) {
     if (!c) return FL_EINVAL;
-    if (on != 0 && on != 1) return fail(c, FL_EINVAL, "fl_set_active_tiles: on must be 0 or 1");
-    c->active = on;
+    if (on < 0 || on > 2) return fail(c, FL_EINVAL, "fl_set_active_tiles: on must be 0, 1 or 2");
+    c->active = on != 0;
+    c->act_list_mode = on == 2 ? 1 : 0;
     invalidate(c);
     return FL_OK;
 }
@@ -1183,8 +1214,12 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     double bt = 1e300;
-    int bk = 0;
-    for (int k = 0; k < ncand; ++k) {
+    int bk = 0, bmode = c->act_list_mode;
+    const int list_mode0 = c->act_list_mode;
+    // under active tiles each tiling is timed with and without the selected list
+    for (int kk = 0; kk < ncand * (c->active ? 2 : 1); ++kk) {
+        const int k = c->active ? kk / 2 : kk;
+        if (c->active) c->act_list_mode = kk % 2;
         const Tiling t = tiling_of(c, candidates[2 * k], candidates[2 * k + 1]);
         float ms = 0.f;
         // frozen steps (dt = 0): the state is streamed like a real step but
@@ -1197,17 +1232,11 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
             hipError_t e;
             if (c->prec == FL_F64) {
                 StepArgs<double> a = make_args<double>(c, c->nstep, t, 1);
-                if (c->active) {
-                    a.act = c->d_act;
-                    a.act_stride = c->act_stride;
-                }
+                set_act<double>(c, a);
                 e = launch_step<double>(a, t.cpt, c->stream);
             } else {
                 StepArgs<float> a = make_args<float>(c, c->nstep, t, 1);
-                if (c->active) {
-                    a.act = c->d_act;
-                    a.act_stride = c->act_stride;
-                }
+                set_act<float>(c, a);
                 e = launch_step<float>(a, t.cpt, c->stream);
             }
             if (e != hipSuccess) return hip_fail(c, e, "fl_autotune trial");
@@ -1220,10 +1249,12 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
         if (ms < bt) {
             bt = ms;
             bk = k;
+            bmode = c->act_list_mode;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    c->act_list_mode = c->active ? bmode : list_mode0;
     c->cpt = candidates[2 * bk];
     c->rows = c->rows_req = candidates[2 * bk + 1];
     const Tiling t = tiling_of(c, c->cpt, c->rows);
@@ -1395,17 +1426,11 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
         hipError_t e;
         if (c->prec == FL_F64) {
             StepArgs<double> a = make_args<double>(c, c->nstep, tl, 1);
-            if (c->active) {
-                a.act = c->d_act;
-                a.act_stride = c->act_stride;
-            }
+            set_act<double>(c, a);
             e = launch_step<double>(a, tl.cpt, c->stream);
         } else {
             StepArgs<float> a = make_args<float>(c, c->nstep, tl, 1);
-            if (c->active) {
-                a.act = c->d_act;
-                a.act_stride = c->act_stride;
-            }
+            set_act<float>(c, a);
             e = launch_step<float>(a, tl.cpt, c->stream);
         }
         if (e != hipSuccess) return hip_fail(c, e, "fl_autotune_fusion trial");

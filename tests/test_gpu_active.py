@@ -93,14 +93,16 @@ def patchy(nx, ny, seed, t_on=1.0, sides=None):
     return sc
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("prec,cpt", [("f32", 1), ("f32", 2), ("f32", 4), ("f64", 1), ("f64", 2)])
-def test_valley256_2000_steps(prec, cpt):
-    """The 256^2 valley from a dry start: a flood that grows across the grid."""
+def test_valley256_2000_steps(prec, cpt, mode):
+    """The 256^2 valley from a dry start: a flood that grows across the grid
+    (mode 1: per-item skip test; mode 2: selected list)."""
     sc = config_d1()
-    print(f"CASE valley256 active tiles {prec} cpt={cpt}", flush=True)
+    print(f"CASE valley256 active tiles {prec} cpt={cpt} mode {mode}", flush=True)
     chunks = [1, 50, 449, 1500]
     ref = _run(sc, prec, chunks, False, (cpt, 8))
-    got = _run(sc, prec, chunks, True, (cpt, 8))
+    got = _run(sc, prec, chunks, mode, (cpt, 8))
     _same(got, ref, f"{prec} cpt={cpt}")
 
 
@@ -127,14 +129,17 @@ def test_patchy_grids_small_items(seed):
     for prec in ("f32", "f64"):
         if prec == "f64" and cpt == 4:
             continue
-        print(f"CASE patchy {nx}x{ny} seed {seed} {prec} cpt={cpt} rows={rows}", flush=True)
         ref = _run(sc, prec, chunks, False, (cpt, rows))
-        got = _run(sc, prec, chunks, True, (cpt, rows))
-        _same(got, ref, f"patchy {nx}x{ny} {prec}")
+        for mode in (1, 2):
+            print(f"CASE patchy {nx}x{ny} seed {seed} {prec} cpt={cpt} rows={rows} mode {mode}",
+                  flush=True)
+            got = _run(sc, prec, chunks, mode, (cpt, rows))
+            _same(got, ref, f"patchy {nx}x{ny} {prec} mode {mode}")
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("side", [WEST, EAST, SOUTH, NORTH])
-def test_late_inflow_every_side(side):
+def test_late_inflow_every_side(side, mode):
     """A dry grid whose inflow starts at t = 1 s: while it is zero only the
     items behind the inflow faces are computed; then the flood spreads."""
     nx, ny, cpt, rows = 200, 90, 1, 4
@@ -142,7 +147,7 @@ def test_late_inflow_every_side(side):
     sc.h0[:] = 0
     sc.extra["qx0"][:] = 0
     sc.extra["qy0"][:] = 0
-    f = fl.from_scenario(sc, "f32", cells_per_lane=cpt, rows_per_item=rows, active_tiles=True)
+    f = fl.from_scenario(sc, "f32", cells_per_lane=cpt, rows_per_item=rows, active_tiles=mode)
     f.step(10)                                  # 0.5 s: the inflow is still zero
     nxt, tot = f.active_items()
     wo = 64 * cpt - 4
@@ -158,17 +163,18 @@ def test_late_inflow_every_side(side):
     f.close()
     chunks = [10, 30, 100]
     ref = _run(sc, "f32", chunks, False, (cpt, rows))
-    got = _run(sc, "f32", chunks, True, (cpt, rows))
+    got = _run(sc, "f32", chunks, mode, (cpt, rows))
     _same(got, ref, f"side {side}")
     assert got[-1][0].max() > 0.01
 
 
-def test_dry_closed_grid_computes_nothing():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_dry_closed_grid_computes_nothing(mode):
     nx, ny = 300, 64
     z = synth._f32(np.random.default_rng(3).uniform(0, 1, (ny, nx)))
     n = np.full((ny, nx), 0.03, np.float32)
     sc = Scenario("dry", nx, ny, 1.0, z, n, np.zeros_like(z), None, None, dt_max=0.05)
-    f = fl.from_scenario(sc, "f32", cells_per_lane=2, rows_per_item=8, active_tiles=True)
+    f = fl.from_scenario(sc, "f32", cells_per_lane=2, rows_per_item=8, active_tiles=mode)
     nxt, tot = f.active_items()
     assert nxt == tot                           # before any step: everything
     f.step(1)
@@ -182,13 +188,14 @@ def test_dry_closed_grid_computes_nothing():
     f.close()
 
 
-def test_state_handed_between_paths():
-    """Skipping steps, then a batch run, frozen tiling trials, fl_advance and
-    skipping steps again: the flags are refreshed whenever another path moved
-    the state."""
+@pytest.mark.parametrize("mode", [1, 2])
+def test_state_handed_between_paths(mode):
+    """Skipping steps, then a batch run, frozen tiling trials (which may switch
+    the skip mode), fl_advance and skipping steps again: the flags are
+    refreshed whenever another path moved the state."""
     sc = patchy(180, 70, 5)
     ref = _run(sc, "f32", [5, 20, 7, 3.0, 40], False, (1, 4))
-    f = fl.from_scenario(sc, "f32", cells_per_lane=1, rows_per_item=4, active_tiles=True)
+    f = fl.from_scenario(sc, "f32", cells_per_lane=1, rows_per_item=4, active_tiles=mode)
     f.step(5)
     b = fl.Batch([f])
     b.run(20)

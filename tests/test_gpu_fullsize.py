@@ -159,3 +159,22 @@ def test_valley16384_dry_1000_steps_active_tiles_two_steps(d3_dry):
         hs.append((h, r))
     assert torch.equal(hs[0][0], hs[1][0])
     assert (hs[0][1].t, hs[0][1].v_in, hs[0][1].v_out) == (hs[1][1].t, hs[1][1].v_in, hs[1][1].v_out)
+
+
+def test_valley16384_dry_active_tiles_list_mode(d3_dry):
+    """Active tiles with the selected list (mode 2), 2 cells per lane x 8 rows,
+    on the benchmark workload: the same depths as computing every item."""
+    import torch
+    sc = d3_dry
+    print("CASE fullsize dry 1000 steps, active tiles list mode", flush=True)
+    hs = []
+    for kw in (dict(active_tiles=2, cells_per_lane=2, rows_per_item=8), dict(fusion=2)):
+        f = fl.from_scenario(sc, "f32", **kw)
+        f.step(1000)
+        h = torch.empty((sc.ny, sc.nx), dtype=torch.float32, device="cuda")
+        f.get_depth(h)
+        r = f.get_report()
+        f.close()
+        hs.append((h, r))
+    assert torch.equal(hs[0][0], hs[1][0])
+    assert (hs[0][1].t, hs[0][1].v_in) == (hs[1][1].t, hs[1][1].v_in)
