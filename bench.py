@@ -245,7 +245,7 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
 # (cells per lane, rows per work item) the active-tile autotuner tries: small
 # items when few hold water (the march of one item is then the step's
 # critical path), large ones when many do
-ACTIVE_TILINGS = [(4, 32), (4, 16), (2, 16), (4, 8), (2, 8)]
+ACTIVE_TILINGS = [(4, 32), (4, 16), (2, 16), (4, 8), (2, 8), (1, 8)]
 
 
 def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_depth=None,
