@@ -300,22 +300,52 @@ __global__ __launch_bounds__(256) void k_select_count(StepArgs<T> a, unsigned* b
     if (threadIdx.x == 0) block_n[blockIdx.x] = n;
 }
 
+// Between passes 1 and 2 when there are many blocks: one block turns the
+// per-block counts into exclusive offsets in place (a running scan over
+// chunks of 256).
+__global__ __launch_bounds__(256) void k_select_prefix(unsigned* block_n, unsigned nblocks) {
+    __shared__ unsigned sc[256];
+    unsigned carry = 0;
+    for (unsigned b0 = 0; b0 < nblocks; b0 += 256) {
+        const unsigned b = b0 + threadIdx.x;
+        const unsigned v = b < nblocks ? block_n[b] : 0u;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (unsigned d = 1; d < 256; d <<= 1) {  // inclusive scan
+            const unsigned add = threadIdx.x >= d ? sc[threadIdx.x - d] : 0u;
+            __syncthreads();
+            sc[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (b < nblocks) block_n[b] = carry + sc[threadIdx.x] - v;
+        carry += sc[255];
+        __syncthreads();
+    }
+}
+
 // Pass 2: the items that must be computed, in raster order, at the offset the
-// counts of the blocks before give; the last block writes the total.
+// counts of the blocks before give (summed here, or taken from
+// k_select_prefix when `prefixed`); the last block writes the total.
 template <typename T, int CPT>
-__global__ __launch_bounds__(256) void k_select_scatter(StepArgs<T> a, const unsigned* block_n) {
+__global__ __launch_bounds__(256) void k_select_scatter(StepArgs<T> a, const unsigned* block_n,
+                                                        int prefixed) {
     __shared__ unsigned part[256];
     const long long items = (long long)a.nstrips * a.nchunks;
     const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned off = 0;
-    for (unsigned b = threadIdx.x; b < blockIdx.x; b += blockDim.x) off += block_n[b];
-    part[threadIdx.x] = off;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < (unsigned)w) part[threadIdx.x] += part[threadIdx.x + w];
+    unsigned base;
+    if (prefixed) {
+        base = block_n[blockIdx.x];
+    } else {
+        unsigned off = 0;
+        for (unsigned b = threadIdx.x; b < blockIdx.x; b += blockDim.x) off += block_n[b];
+        part[threadIdx.x] = off;
         __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < (unsigned)w) part[threadIdx.x] += part[threadIdx.x + w];
+            __syncthreads();
+        }
+        base = part[0];
     }
-    const unsigned base = part[0];
     const bool need = item < items && select_need<T, CPT>(a, item);
     unsigned rank;
     const unsigned n = block_rank(need, rank);
@@ -581,8 +611,11 @@ hipError_t launch_step_list(const StepArgs<T>& a, long long items, hipStream_t s
     // the per-block counts live after the list's `items` entries (capacity act_stride + blocks)
     unsigned* block_n = reinterpret_cast<unsigned*>(a.act_list + a.act_stride);
     hipLaunchKernelGGL((k_select_count<T, CPT>), dim3(sel_blocks), dim3(256), 0, s, a, block_n);
+    // few blocks: each scatter block sums the counts before it; many: scan them first
+    const int prefixed = sel_blocks > 2048 ? 1 : 0;
+    if (prefixed) hipLaunchKernelGGL(k_select_prefix, dim3(1), dim3(256), 0, s, block_n, sel_blocks);
     hipLaunchKernelGGL((k_select_scatter<T, CPT>), dim3(sel_blocks), dim3(256), 0, s, a,
-                       (const unsigned*)block_n);
+                       (const unsigned*)block_n, prefixed);
     const long long want = (items + 3) / 4;
     const unsigned blocks = (unsigned)(1 + std::min<long long>(want, resident));
     hipLaunchKernelGGL((k_step_list<T, CPT>), dim3(blocks), dim3(256), 0, s, a);

@@ -161,14 +161,17 @@ def test_valley16384_dry_1000_steps_active_tiles_two_steps(d3_dry):
     assert (hs[0][1].t, hs[0][1].v_in, hs[0][1].v_out) == (hs[1][1].t, hs[1][1].v_in, hs[1][1].v_out)
 
 
-def test_valley16384_dry_active_tiles_list_mode(d3_dry):
-    """Active tiles with the selected list (mode 2), 2 cells per lane x 8 rows,
-    on the benchmark workload: the same depths as computing every item."""
+@pytest.mark.parametrize("cpt", [2, 1])
+def test_valley16384_dry_active_tiles_list_mode(d3_dry, cpt):
+    """Active tiles with the selected list (mode 2), 2 or 1 cells per lane x 8
+    rows (272,384 or 561,152 work items: the latter scans the selection
+    kernels' block counts first), on the benchmark workload: the same depths
+    as computing every item."""
     import torch
     sc = d3_dry
-    print("CASE fullsize dry 1000 steps, active tiles list mode", flush=True)
+    print(f"CASE fullsize dry 1000 steps, active tiles list mode cpt={cpt}", flush=True)
     hs = []
-    for kw in (dict(active_tiles=2, cells_per_lane=2, rows_per_item=8), dict(fusion=2)):
+    for kw in (dict(active_tiles=2, cells_per_lane=cpt, rows_per_item=8), dict(fusion=2)):
         f = fl.from_scenario(sc, "f32", **kw)
         f.step(1000)
         h = torch.empty((sc.ny, sc.nx), dtype=torch.float32, device="cuda")
