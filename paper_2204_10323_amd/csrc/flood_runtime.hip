@@ -124,6 +124,18 @@ fl_status hip_fail(fl_ctx* c, hipError_t e, const char* what) {
     return fail(c, FL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// A HIP event destroyed when it goes out of scope, so that an early error
+// return does not leak it.
+struct Event {
+    hipEvent_t e = nullptr;
+    Event() = default;
+    Event(const Event&) = delete;
+    Event& operator=(const Event&) = delete;
+    ~Event() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 #define HIP_TRY(c, call)                                                  \
     do {                                                                  \
         hipError_t e_ = (call);                                           \
@@ -1210,9 +1222,9 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
     fl_status st;
     Tiling cur{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
     if ((st = fold_budget(c, cur))) return st;
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    Event e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0.e));
+    HIP_TRY(c, hipEventCreate(&e1.e));
     double bt = 1e300;
     int bk = 0, bmode = c->act_list_mode;
     const int list_mode0 = c->act_list_mode;
@@ -1228,7 +1240,7 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
         // tiling, which mark the items that hold water or discharge.
         if (c->active) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
         for (int r = 0; r < 2 + trial_steps; ++r) {
-            if (r == 2) HIP_TRY(c, hipEventRecord(e0, c->stream));
+            if (r == 2) HIP_TRY(c, hipEventRecord(e0.e, c->stream));
             hipError_t e;
             if (c->prec == FL_F64) {
                 StepArgs<double> a = make_args<double>(c, c->nstep, t, 1);
@@ -1242,9 +1254,9 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
             if (e != hipSuccess) return hip_fail(c, e, "fl_autotune trial");
             c->nstep += 1;
         }
-        HIP_TRY(c, hipEventRecord(e1, c->stream));
-        HIP_TRY(c, hipEventSynchronize(e1));
-        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        HIP_TRY(c, hipEventRecord(e1.e, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1.e));
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0.e, e1.e));
         if ((st = fold_budget(c, t))) return st;
         if (ms < bt) {
             bt = ms;
@@ -1252,8 +1264,6 @@ fl_status fl_autotune(fl_ctx* c, const int32_t* candidates, int32_t ncand, int32
             bmode = c->act_list_mode;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     c->act_list_mode = c->active ? bmode : list_mode0;
     c->cpt = candidates[2 * bk];
     c->rows = c->rows_req = candidates[2 * bk + 1];
@@ -1296,17 +1306,15 @@ fl_status fl_time_steps(fl_ctx* c, int64_t nsteps, double* elapsed_ms) {
     if (!c || !elapsed_ms) return FL_EINVAL;
     if (!c->committed) return fail(c, FL_ESTATE, "fl_time_steps before fl_commit");
     HIP_TRY(c, hipSetDevice(c->device));
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    Event e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0.e));
+    HIP_TRY(c, hipEventCreate(&e1.e));
+    HIP_TRY(c, hipEventRecord(e0.e, c->stream));
     fl_status st = run_steps(c, nsteps);
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventRecord(e1.e, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1.e));
     float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0.e, e1.e));
     *elapsed_ms = ms;
     return st;
 }
@@ -1412,9 +1420,9 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     fl_status st;
     const Tiling tl{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
     if ((st = fold_budget(c, tl))) return st;
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    Event e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0.e));
+    HIP_TRY(c, hipEventCreate(&e1.e));
     float ms1 = 0.f, ms2 = 0.f;
     // one step per launch: frozen steps (dt = 0 streams the state, leaves it
     // as it is).  With active tiles they skip as real steps would, after two
@@ -1422,7 +1430,7 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     if (c->active) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
     const int warm = c->active ? 2 : 0;
     for (int r = 0; r < warm + trial_steps; ++r) {
-        if (r == warm) HIP_TRY(c, hipEventRecord(e0, c->stream));
+        if (r == warm) HIP_TRY(c, hipEventRecord(e0.e, c->stream));
         hipError_t e;
         if (c->prec == FL_F64) {
             StepArgs<double> a = make_args<double>(c, c->nstep, tl, 1);
@@ -1436,9 +1444,9 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
         if (e != hipSuccess) return hip_fail(c, e, "fl_autotune_fusion trial");
         c->nstep += 1;
     }
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
-    HIP_TRY(c, hipEventElapsedTime(&ms1, e0, e1));
+    HIP_TRY(c, hipEventRecord(e1.e, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1.e));
+    HIP_TRY(c, hipEventElapsedTime(&ms1, e0.e, e1.e));
     if ((st = fold_budget(c, tl))) return st;
     c->act_at = -1;
     // two steps per launch, as fl_step runs them (entry, launches, settling,
@@ -1447,15 +1455,13 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
         st = c->prec == FL_F64 ? fused_steps_t<double>(c, 4, 1) : fused_steps_t<float>(c, 4, 1);
         if (st) return st;
     }
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    HIP_TRY(c, hipEventRecord(e0.e, c->stream));
     st = c->prec == FL_F64 ? fused_steps_t<double>(c, trial_steps, 1)
                            : fused_steps_t<float>(c, trial_steps, 1);
     if (st) return st;
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
-    HIP_TRY(c, hipEventElapsedTime(&ms2, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(c, hipEventRecord(e1.e, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1.e));
+    HIP_TRY(c, hipEventElapsedTime(&ms2, e0.e, e1.e));
     c->fuse = (ms2 < ms1) ? 2 : 1;
     if (steps_per_launch) *steps_per_launch = c->fuse;
     if (ms_per_step) *ms_per_step = (c->fuse == 2 ? ms2 : ms1) / trial_steps;
@@ -1952,22 +1958,18 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     ba.done = b->d_sync + kMaxXcc;
     ba.error = b->d_error;
     ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: only a broken co-residency could reach it
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Event e0, e1;
     if (ms) {
-        BHIP_TRY(b, hipEventCreate(&e0));
-        BHIP_TRY(b, hipEventCreate(&e1));
-        BHIP_TRY(b, hipEventRecord(e0, b->stream));
+        BHIP_TRY(b, hipEventCreate(&e0.e));
+        BHIP_TRY(b, hipEventCreate(&e1.e));
+        BHIP_TRY(b, hipEventRecord(e0.e, b->stream));
     }
     BHIP_TRY(b, launch_batch<T>(ba, b->cpt, b->device, b->stream, &b->last_blocks, any_active));
-    if (ms) BHIP_TRY(b, hipEventRecord(e1, b->stream));
+    if (ms) BHIP_TRY(b, hipEventRecord(e1.e, b->stream));
     int error = 0;
     BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
-    if (ms) {
-        BHIP_TRY(b, hipEventElapsedTime(ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-    }
+    if (ms) BHIP_TRY(b, hipEventElapsedTime(ms, e0.e, e1.e));
     for (fl_ctx* c : b->members) {
         c->nstep += nsteps;
         if (c->active) {
