@@ -402,8 +402,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py: the flood step runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the step is not sharded over several GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -16,8 +16,7 @@
  *     carries Q_in) and Manning outflow at each outflow cell;
  *   - all other border faces are closed walls (left unchanged, Appendix
  *     "Code structure", halo exchange paragraph).
- * Readings of silent or garbled points (each is listed with its reason in the
- * design notes of the repository):
+ * Readings of points the paper leaves silent or garbled:
  *   - a dt multiplies the gravity term in the numerator of eq. (3);
  *   - |q| in the friction term is the same face's own discharge (1-D form);
  *   - h_f = max(eta_L, eta_R) - max(z_L, z_R), eta = h + z;

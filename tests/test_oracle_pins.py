@@ -140,7 +140,7 @@ def test_inflow_split_equal_bed():
     hhat = (Q / (dx * kc.sum())) ** 0.6
     assert abs((W - zc[0]) / hhat - 1) <= 1e-12
     assert abs(q.sum() * dx / Q - 1) <= 1e-12
-    # equal roughness as well: the survey's closed form (Q n / (N dx sqrt S))^(3/5)
+    # equal roughness as well: the wide-section normal depth (Q n / (N dx sqrt S))^(3/5)
     W2, q2 = oracle.inflow_split(zc, np.full(nc, math.sqrt(S) / 0.03), dx, Q)
     assert abs((W2 - zc[0]) / (Q * 0.03 / (nc * dx * math.sqrt(S))) ** 0.6 - 1) <= 1e-12
 
