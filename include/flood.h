@@ -32,6 +32,11 @@
  *         (j = 0 is the south border, j = ny the north border).
  *   Element type of every field is float for FL_F32 contexts and double for
  *   FL_F64 contexts.  Row strides are in elements.
+ *   A pointer passed with on_device = 1 (and the memory of fl_bind_workspace)
+ *   must be device or managed memory of the context's device: anything else
+ *   is refused with EINVAL before it is read or written.  Host pointers may be
+ *   any host memory.  The interface takes no sizes for arrays: each must hold
+ *   the rows and columns its call describes.
  *
  * Ownership: every fl_set_* call copies its input; the caller keeps its
  * buffers.  Device memory of a context belongs to the context and is freed by

@@ -161,22 +161,61 @@ def _torch_stream_ptr():
     return None
 
 
-def _as_input(a, dtype):
-    """(pointer, row_stride, on_device, keepalive) for a 2-D numpy array or torch tensor."""
+def _check_shape(a, shape, name):
+    if shape is not None and tuple(a.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(a.shape)}, expected {tuple(shape)}")
+
+
+def _as_input(a, dtype, shape=None, name="array", packed=False):
+    """(pointer, row_stride, on_device, keepalive) for a 2-D numpy array or
+    torch tensor read by the library: converted to the element type (a copy
+    if needed), checked against `shape`, rows contiguous, and with `packed`
+    the row stride equal to the row length (calls that take no stride)."""
     try:
         import torch
         if isinstance(a, torch.Tensor):
+            _check_shape(a, shape, name)
             tdt = torch.float64 if dtype == np.float64 else torch.float32
             if a.is_cuda:
-                t = a.to(tdt)
-                if t.stride(1) != 1:
+                t = a.detach().to(tdt)
+                if (packed and not t.is_contiguous()) or t.stride(-1) != 1:
                     t = t.contiguous()
-                return C.c_void_p(t.data_ptr()), t.stride(0), 1, t
+                return C.c_void_p(t.data_ptr()), t.stride(0) if t.dim() > 1 else t.numel(), 1, t
             a = a.detach().cpu().numpy()
     except ImportError:
         pass
     arr = np.ascontiguousarray(a, dtype=dtype)
+    _check_shape(arr, shape, name)
     return C.c_void_p(arr.ctypes.data), arr.shape[-1] if arr.ndim > 1 else arr.size, 0, arr
+
+
+def _as_output(a, dtype, shape, name, packed=False):
+    """(pointer, row_stride, on_device) of an array the library writes in
+    place: it must already have the element type and shape, rows contiguous,
+    and with `packed` no gaps between rows (no copy is made, so a mismatch
+    is an error rather than a result written into a temporary)."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            _check_shape(a, shape, name)
+            tdt = torch.float64 if dtype == np.float64 else torch.float32
+            if a.dtype != tdt:
+                raise ValueError(f"{name}: dtype {a.dtype}, expected {tdt}")
+            if a.stride(-1) != 1 or (packed and not a.is_contiguous()):
+                raise ValueError(f"{name}: must be contiguous")
+            stride = a.stride(0) if a.dim() > 1 else a.numel()
+            if a.is_cuda:
+                return C.c_void_p(a.data_ptr()), stride, 1
+            return C.c_void_p(a.data_ptr()), stride, 0
+    except ImportError:
+        pass
+    if not isinstance(a, np.ndarray) or a.dtype != np.dtype(dtype):
+        raise ValueError(f"{name}: a numpy array of {np.dtype(dtype)} (or a tensor) is needed")
+    _check_shape(a, shape, name)
+    if a.strides[-1] != a.itemsize or (packed and not a.flags.c_contiguous):
+        raise ValueError(f"{name}: must be contiguous")
+    stride = a.strides[0] // a.itemsize if a.ndim > 1 else a.size
+    return C.c_void_p(a.ctypes.data), stride, 0
 
 
 class Flood:
@@ -201,11 +240,11 @@ class Flood:
 
     # -- inputs
     def set_dem(self, z):
-        p, stride, dev, keep = _as_input(z, self.dtype)
+        p, stride, dev, keep = _as_input(z, self.dtype, (self.ny, self.nx), "z")
         _check(self.ctx, lib().fl_set_dem(self.ctx, p, stride, dev))
 
     def set_manning(self, n):
-        p, stride, dev, keep = _as_input(n, self.dtype)
+        p, stride, dev, keep = _as_input(n, self.dtype, (self.ny, self.nx), "n")
         _check(self.ctx, lib().fl_set_manning(self.ctx, p, stride, dev))
 
     def set_inflow(self, side: int, first: int, count: int, slope: float, t_s, q_m3s):
@@ -224,13 +263,19 @@ class Flood:
         _check(self.ctx, lib().fl_set_params(self.ctx, C.byref(p)))
 
     def set_state(self, h, qx=None, qy=None, t: float = 0.0):
-        ph, _, dev, k1 = _as_input(h, self.dtype)
+        """Initial state (fl_set_state): h [ny, nx], qx [ny, nx+1] and qy
+        [ny+1, nx] (None: zero), all in host memory or all on the device."""
+        ph, _, dev, k1 = _as_input(h, self.dtype, (self.ny, self.nx), "h", packed=True)
         px = py = None
         k2 = k3 = None
         if qx is not None:
-            px, _, d2, k2 = _as_input(qx, self.dtype)
+            px, _, d2, k2 = _as_input(qx, self.dtype, (self.ny, self.nx + 1), "qx", packed=True)
+            if d2 != dev:
+                raise ValueError("set_state: h and qx must both be host or both device arrays")
         if qy is not None:
-            py, _, d3, k3 = _as_input(qy, self.dtype)
+            py, _, d3, k3 = _as_input(qy, self.dtype, (self.ny + 1, self.nx), "qy", packed=True)
+            if d3 != dev:
+                raise ValueError("set_state: h and qy must both be host or both device arrays")
         _check(self.ctx, lib().fl_set_state(self.ctx, ph, px, py, float(t), dev))
 
     def set_tiling(self, cells_per_lane: int = 0, rows_per_item: int = 0):
@@ -313,7 +358,7 @@ class Flood:
     # -- outputs
     def get_depth(self, out=None) -> np.ndarray:
         if out is not None:
-            p, stride, dev, keep = _as_input(out, self.dtype)
+            p, stride, dev = _as_output(out, self.dtype, (self.ny, self.nx), "out")
             _check(self.ctx, lib().fl_get_depth(self.ctx, p, stride, dev))
             return out
         h = np.empty((self.ny, self.nx), dtype=self.dtype)
@@ -349,6 +394,8 @@ class Flood:
             _check(self.ctx, lib().fl_bind_workspace(self.ctx, None, 0))
             self._ws = None
             return
+        if not getattr(buf, "is_cuda", False) or not buf.is_contiguous():
+            raise ValueError("bind_workspace: a contiguous device tensor is needed")
         nbytes = buf.numel() * buf.element_size()
         _check(self.ctx, lib().fl_bind_workspace(self.ctx, C.c_void_p(buf.data_ptr()), nbytes))
         self._ws = buf
@@ -368,8 +415,8 @@ class Flood:
             st = lib().fl_adj_setup(self.ctx, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
                                     obs_every, None, 0, 0, ckpt_stride)
         else:
-            p, _, dev, keep = _as_input(obs, self.dtype)
             nobs = obs.shape[0]
+            p, _, dev, keep = _as_input(obs, self.dtype, (nobs, len(g)), "obs", packed=True)
             st = lib().fl_adj_setup(self.ctx, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
                                     obs_every, p, nobs, dev, ckpt_stride)
         _check(self.ctx, st)
@@ -379,8 +426,9 @@ class Flood:
         """Run nsteps keeping checkpoints; returns (series, loss)."""
         loss = C.c_double()
         nobs = nsteps // self._obs_every
+        self._nobs = nobs
         if out is not None:
-            p, _, dev, keep = _as_input(out, self.dtype)
+            p, _, dev = _as_output(out, self.dtype, (nobs, self._ngauges), "out", packed=True)
             _check(self.ctx, lib().fl_adj_forward(self.ctx, int(nsteps), p, dev, C.byref(loss)))
             return out, loss.value
         series = np.empty((nobs, self._ngauges), dtype=self.dtype)
@@ -395,10 +443,12 @@ class Flood:
         pdl = None
         keep = None
         if dl_dseries is not None:
-            pdl, _, _, keep = _as_input(dl_dseries, self.dtype)
+            shape = (getattr(self, "_nobs", dl_dseries.shape[0]), self._ngauges)
+            pdl, _, _, keep = _as_input(dl_dseries, self.dtype, shape, "dl_dseries", packed=True)
         if grad_n_out is not None:
-            _check(self.ctx, lib().fl_adj_backward(self.ctx, pdl,
-                                                   C.cast(C.c_void_p(grad_n_out.data_ptr()), dp), 1,
+            pg, _, gdev = _as_output(grad_n_out, np.float64, (self.ny, self.nx), "grad_n_out",
+                                     packed=True)
+            _check(self.ctx, lib().fl_adj_backward(self.ctx, pdl, C.cast(pg, dp), gdev,
                                                    gq.ctypes.data_as(dp)))
             return grad_n_out, gq[:nsamples]
         gn = np.zeros((self.ny, self.nx), dtype=np.float64)

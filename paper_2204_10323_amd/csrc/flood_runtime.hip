@@ -155,6 +155,20 @@ double get_elem(const fl_ctx* c, const unsigned char* base, size_t idx) {
     return v;
 }
 
+// A pointer the caller declares to be on the device must be device (or
+// managed) memory of the context's device; anything else would be read or
+// written as device memory by a copy.  A host pointer makes the query fail:
+// that error is cleared here so that it is not reported by a later call.
+fl_status need_device(fl_ctx* c, const void* p, const char* what) {
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) (void)hipGetLastError();
+    if (e != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) ||
+        at.device != c->device)
+        return fail(c, FL_EINVAL, std::string(what) + ": not device memory of the context's device");
+    return FL_OK;
+}
+
 // Copy ny rows of `cols` elements with stride `stride` from host or device
 // memory into a dense host vector.
 fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int cols, int on_device,
@@ -163,6 +177,7 @@ fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int 
     out.resize((size_t)rows_ * cols * es);
     if (on_device) {
         HIP_TRY(c, hipSetDevice(c->device));
+        if (fl_status st = need_device(c, src, "input array")) return st;
         HIP_TRY(c, hipMemcpy2D(out.data(), cols * es, src, (size_t)stride * es, cols * es, rows_,
                                hipMemcpyDeviceToHost));
     } else {
@@ -904,6 +919,8 @@ fl_status fl_bind_workspace(fl_ctx* c, void* dev_ptr, size_t bytes) {
             return fail(c, FL_EINVAL, "fl_bind_workspace: smaller than fl_workspace_bytes");
     }
     HIP_TRY(c, hipSetDevice(c->device));
+    if (dev_ptr)
+        if (fl_status st = need_device(c, dev_ptr, "fl_bind_workspace")) return st;
     if (c->stream) HIP_TRY(c, hipStreamSynchronize(c->stream));
     free_device(c);
     c->ws = static_cast<unsigned char*>(dev_ptr);
@@ -1358,6 +1375,8 @@ fl_status fl_get_depth(fl_ctx* c, void* dst, int64_t row_stride, int on_device) 
     if (!c->committed) return fail(c, FL_ESTATE, "fl_get_depth before fl_commit");
     if (!dst || row_stride < c->nx) return fail(c, FL_EINVAL, "fl_get_depth: NULL or row_stride < nx");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (on_device)
+        if (fl_status st = need_device(c, dst, "fl_get_depth")) return st;
     const size_t es = esz(c);
     const unsigned char* src = static_cast<const unsigned char*>(c->d_h[c->nstep & 1]) +
                                ((size_t)kHalo * c->pitch + kHalo) * es;
@@ -1372,6 +1391,10 @@ fl_status fl_get_discharge(fl_ctx* c, void* qx, void* qy, int on_device) {
     if (!c->committed) return fail(c, FL_ESTATE, "fl_get_discharge before fl_commit");
     if (!qx || !qy) return fail(c, FL_EINVAL, "fl_get_discharge: NULL output");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (on_device) {
+        if (fl_status st = need_device(c, qx, "fl_get_discharge qx")) return st;
+        if (fl_status st = need_device(c, qy, "fl_get_discharge qy")) return st;
+    }
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -1776,6 +1799,8 @@ fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, i
         if (gauge_cells[k] < 0 || (long long)gauge_cells[k] >= (long long)c->nx * c->ny)
             return fail(c, FL_EINVAL, "fl_adj_setup: gauge cell outside the grid");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (obs && obs_on_device)
+        if (fl_status st = need_device(c, obs, "fl_adj_setup obs")) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     free_adjoint(c);
     c->gauges.assign(gauge_cells, gauge_cells + ngauges);
@@ -1823,6 +1848,8 @@ fl_status fl_adj_forward(fl_ctx* c, int64_t nsteps, void* series, int on_device,
     if (!c->committed || !c->adj_setup) return fail(c, FL_ESTATE, "fl_adj_forward needs fl_commit and fl_adj_setup");
     if (nsteps < 1) return fail(c, FL_EINVAL, "fl_adj_forward: nsteps < 1");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (series && on_device)
+        if (fl_status st = need_device(c, series, "fl_adj_forward series")) return st;
     return c->prec == FL_F64 ? adj_forward_t<double>(c, nsteps, series, on_device, loss)
                              : adj_forward_t<float>(c, nsteps, series, on_device, loss);
 }
@@ -1838,6 +1865,8 @@ fl_status fl_adj_backward(fl_ctx* c, const void* dl_dseries, double* grad_n, int
     if (!dl_dseries && !c->d_obs)
         return fail(c, FL_EINVAL, "fl_adj_backward: no observations set and no dL/dseries given");
     HIP_TRY(c, hipSetDevice(c->device));
+    if (grad_on_device)
+        if (fl_status st = need_device(c, grad_n, "fl_adj_backward grad_n")) return st;
     return c->prec == FL_F64 ? adj_backward_t<double>(c, dl_dseries, grad_n, grad_on_device, grad_q)
                              : adj_backward_t<float>(c, dl_dseries, grad_n, grad_on_device, grad_q);
 }

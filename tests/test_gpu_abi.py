@@ -129,6 +129,53 @@ def test_device_inputs_and_outputs():
     assert np.array_equal(out.cpu().numpy(), h_host)
 
 
+def test_device_pointers_are_checked():
+    """Host memory passed where a call is told it gets device memory is
+    refused (EINVAL) before any copy touches it, the context keeps its state
+    and no runtime error is left pending: the run afterwards is bitwise the
+    run without the refused calls.  The binding refuses mismatched shapes,
+    element types and mixed host/device state before calling the library."""
+    import torch
+    sc = random_tiny(20, 12, 3)
+    ref = run_gpu(sc, 25, "f32")
+    f = fl.from_scenario(sc, "f32")
+    L = fl.lib()
+    c = f.ctx
+    host = np.zeros((sc.ny, sc.nx), np.float32)
+    hp = C.c_void_p(host.ctypes.data)
+    assert L.fl_set_dem(c, hp, sc.nx, 1) == fl.FL_EINVAL
+    assert b"device memory" in L.fl_last_error(c)
+    assert L.fl_set_state(c, hp, None, None, 0.0, 1) == fl.FL_EINVAL
+    assert L.fl_get_depth(c, hp, sc.nx, 1) == fl.FL_EINVAL
+    qx = np.zeros((sc.ny, sc.nx + 1), np.float32)
+    qy = np.zeros((sc.ny + 1, sc.nx), np.float32)
+    assert L.fl_get_discharge(c, C.c_void_p(qx.ctypes.data), C.c_void_p(qy.ctypes.data), 1) == fl.FL_EINVAL
+    need = f.workspace_bytes()
+    raw = np.zeros(need + 512, np.uint8)
+    off = (-raw.ctypes.data) % 256
+    assert L.fl_bind_workspace(c, C.c_void_p(raw.ctypes.data + off), need) == fl.FL_EINVAL
+    with pytest.raises(ValueError):
+        f.get_depth(np.zeros((sc.ny, sc.nx), np.float64))              # element type
+    with pytest.raises(ValueError):
+        f.get_depth(torch.zeros((sc.ny, sc.nx + 1), device="cuda"))    # shape
+    with pytest.raises(ValueError):
+        f.get_depth(torch.zeros((sc.nx, sc.ny), device="cuda").t())    # columns not contiguous
+    with pytest.raises(ValueError):
+        f.set_dem(np.zeros((sc.ny + 1, sc.nx), np.float32))
+    with pytest.raises(ValueError):
+        f.set_state(torch.zeros((sc.ny, sc.nx), device="cuda"), qx, qy)  # mixed host/device
+    with pytest.raises(ValueError):
+        f.bind_workspace(torch.zeros(need, dtype=torch.uint8))           # host tensor
+    f.step(25)
+    out = torch.empty((sc.ny, sc.nx), device="cuda", dtype=torch.float32)
+    f.get_depth(out)
+    qx2, qy2 = f.get_discharge()
+    r = f.get_report()
+    f.close()
+    assert np.array_equal(out.cpu().numpy(), ref[0])
+    assert np.array_equal(qx2, ref[1]) and np.array_equal(qy2, ref[2]) and r.t == ref[3].t
+
+
 def test_nonfinite_is_detected_and_stops_the_clock():
     """An inflow of 1e38 m^3/s overflows the depth: the sentinel trips, the report
     says ENONFINITE and later steps do not advance the clock."""
