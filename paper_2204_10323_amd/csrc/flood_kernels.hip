@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "flood_march.h"
 
@@ -570,23 +571,24 @@ __global__ void k_volume_sum(const double* part, int nparts, double* out) {
 int strip_width(int cpt) { return 64 * cpt - 4; }
 
 // Blocks of k_step_list<T, CPT> the current device holds at once (queried
-// once; prepare_step_list does it outside any graph capture).
+// once; prepare_step_list does it outside any graph capture).  Threads that
+// query it together store the same value.
 template <typename T, int CPT>
-int& list_resident() {
-    static int resident = 0;
+std::atomic<int>& list_resident() {
+    static std::atomic<int> resident{0};
     return resident;
 }
 
 template <typename T, int CPT>
 hipError_t query_list_resident() {
-    int& resident = list_resident<T, CPT>();
-    if (resident > 0) return hipSuccess;
+    std::atomic<int>& resident = list_resident<T, CPT>();
+    if (resident.load(std::memory_order_relaxed) > 0) return hipSuccess;
     int per_cu = 0, ncu = 0, dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_list<T, CPT>, 256, 0);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * std::max(1, ncu);
+    resident.store(std::max(1, per_cu) * std::max(1, ncu), std::memory_order_relaxed);
     return hipSuccess;
 }
 
@@ -606,7 +608,7 @@ template <typename T, int CPT>
 hipError_t launch_step_list(const StepArgs<T>& a, long long items, hipStream_t s) {
     hipError_t e = query_list_resident<T, CPT>();
     if (e != hipSuccess) return e;
-    const int resident = list_resident<T, CPT>();
+    const int resident = list_resident<T, CPT>().load(std::memory_order_relaxed);
     const unsigned sel_blocks = (unsigned)std::max<long long>(1, (items + 255) / 256);
     // the per-block counts live after the list's `items` entries (capacity act_stride + blocks)
     unsigned* block_n = reinterpret_cast<unsigned*>(a.act_list + a.act_stride);
