@@ -62,6 +62,24 @@ def test_einval_cases():
     f.close()
 
 
+def test_grid_size_limits():
+    """The largest grids the 32-bit per-row addressing allows are accepted (no
+    memory is taken before commit); one column or row more is refused, and
+    the workspace size of the largest grid does not overflow."""
+    L = fl.lib()
+    f = _ctx()
+    c = f.ctx
+    nx_max = (1 << 28) - 8 - 256
+    assert L.fl_init_grid(c, nx_max, 4, 1.0) == fl.FL_OK
+    assert L.fl_init_grid(c, nx_max + 1, 4, 1.0) == fl.FL_EINVAL
+    assert b"too large" in L.fl_last_error(c)
+    assert L.fl_init_grid(c, 4, (1 << 30) - 8, 1.0) == fl.FL_OK
+    assert L.fl_init_grid(c, 4, (1 << 30) - 7, 1.0) == fl.FL_EINVAL
+    w = L.fl_workspace_bytes(nx_max, 4, 1, 3)
+    assert w >= 8 * 8 * nx_max * 4 and w < 1 << 40
+    f.close()
+
+
 def test_estate_order():
     L = fl.lib()
     f = _ctx()
