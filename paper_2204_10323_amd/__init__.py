@@ -487,10 +487,19 @@ class Batch:
         if st != FL_OK:
             raise FloodError(st, lib().fl_batch_last_error(self.b).decode())
 
+    def _live(self):
+        # the C batch borrows its members: a closed member must not be stepped
+        if not getattr(self, "b", None):
+            raise ValueError("the batch is closed")
+        if any(m.ctx is None for m in self.members):
+            raise ValueError("a member of the batch was closed")
+
     def set_tiling(self, cells_per_lane: int, rows_per_item: int):
+        self._live()
         self._check(lib().fl_batch_set_tiling(self.b, cells_per_lane, rows_per_item))
 
     def autotune(self, candidates, trial_steps: int = 20):
+        self._live()
         flat = [int(v) for pair in candidates for v in pair]
         arr = (C.c_int32 * len(flat))(*flat)
         best = (C.c_int32 * 2)()
@@ -500,9 +509,11 @@ class Batch:
         return (best[0], best[1]), ms.value
 
     def run(self, nsteps: int):
+        self._live()
         self._check(lib().fl_batch_run(self.b, int(nsteps)))
 
     def time(self, nsteps: int) -> float:
+        self._live()
         ms = C.c_double()
         self._check(lib().fl_batch_time(self.b, int(nsteps), C.byref(ms)))
         return ms.value

@@ -142,5 +142,14 @@ def test_batch_create_errors():
         b.run(1)
     assert ei.value.status == fl.FL_ESTATE
     b.close()
+    with pytest.raises(ValueError):
+        b.run(1)                    # the batch is closed
+    f.commit()
+    h = fl.from_scenario(sc, "f32")
+    b2 = fl.Batch([f, h])
+    h.close()                       # a member closed while the batch still borrows it
+    with pytest.raises(ValueError):
+        b2.run(1)
+    b2.close()
     for x in (f, g, u):
         x.close()
