@@ -310,7 +310,8 @@ fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
 /* Work items the next launch computes under active-tile skipping
  * (*next_items) and work items of a launch (*total_items): those of the
  * two-step kernel after a two-step run, else of the single-step kernel.
- * Synchronises.  ESTATE: not committed with fl_set_active_tiles(ctx, 1). */
+ * Synchronises.  ESTATE: not committed with active tiles on (mode 1 or 2).
+ * EINVAL: a NULL output. */
 fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items);
 
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
