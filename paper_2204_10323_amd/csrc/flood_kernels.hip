@@ -110,6 +110,33 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
         }
     };
 
+    auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
+        T* const ho = a.h_out + (long long)(r + kHalo) * P;
+        T* const qxr = a.qx_out + (long long)(r + kHalo) * P;
+        T* const qyr = a.qy_out + (long long)(r + kHalo) * P;
+        if (all_store) {
+            stv<T, CPT, NTS>(at_byte(ho, boff), hv);
+            stv<T, CPT, NTS>(at_byte(qxr, boff), qxv);
+            stv<T, CPT, NTS>(at_byte(qyr, boff), qyv);
+        } else if (any_store) {
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (store_col[m]) {
+                    ho[ucol + m] = hv[m];
+                    qxr[ucol + m] = qxv[m];
+                    qyr[ucol + m] = qyv[m];
+                }
+        }
+    };
+    // With plain stores (the persistent batch), FP32, without active tiles
+    // (where the registers allow): an output row is stored at the start of the
+    // next row's turn, before that turn's loads, so that waiting for the loads
+    // covers the stores too instead of stalling on stores issued just before.
+    constexpr bool kDefer = !NTS && !ACT && sizeof(T) == 4;
+    T sh[CPT], sqx[CPT], sqy[CPT];
+    int srow = 0;
+    bool spend = false;
+
     Marcher<T, CPT, VAR> M;
     M.reset();
     load_row(j0 - 2);
@@ -118,6 +145,10 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
+        }
+        if (kDefer && spend) {
+            store_row(srow, sh, sqx, sqy);
+            spend = false;
         }
         if (k < j1 + 1) load_row(k + 1);
         T hn[CPT], qxo[CPT], qyo[CPT], hold[CPT];
@@ -145,26 +176,21 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
             }
         }
         if (in_item) {
-            T* const ho = a.h_out + (long long)(ko + kHalo) * P;
-            T* const qxr = a.qx_out + (long long)(ko + kHalo) * P;
-            T* const qyr = a.qy_out + (long long)(ko + kHalo) * P;
-            if (all_store) {
-                stv<T, CPT, NTS>(at_byte(ho, boff), hn);
-                stv<T, CPT, NTS>(at_byte(qxr, boff), qxo);
-                stv<T, CPT, NTS>(at_byte(qyr, boff), qyo);
-            } else if (any_store) {
+            if constexpr (kDefer) {
 #pragma unroll
-                for (int m = 0; m < CPT; ++m)
-                    if (store_col[m]) {
-                        ho[ucol + m] = hn[m];
-                        qxr[ucol + m] = qxo[m];
-                        qyr[ucol + m] = qyo[m];
-                    }
+                for (int m = 0; m < CPT; ++m) {
+                    sh[m] = hn[m]; sqx[m] = qxo[m]; sqy[m] = qyo[m];
+                }
+                srow = ko;
+                spend = true;
+            } else {
+                store_row(ko, hn, qxo, qyo);
             }
         }
         row_books<T, CPT>(a, G, store_col, ko, in_item, south_chunk, hn, qxo, qyo, true, hbits,
                           outacc);
     }
+    if (kDefer && spend) store_row(srow, sh, sqx, sqy);
 }
 
 // Does work item (s, c), whose cells are columns [s wo, (s + 1) wo) and rows
