@@ -5,6 +5,7 @@ baseline), and its figures are consistent with each other."""
 import json
 import math
 import os
+import re
 import subprocess
 import sys
 
@@ -44,8 +45,17 @@ def test_bench_json_line():
     assert rf["algorithmic_bytes_per_launch"] == 32 * cells * spl
     assert math.isclose(rf["achieved"], rf["algorithmic_bytes_per_launch"] / (rf["launch_ms"] / 1e3) / 1e9,
                         rel_tol=2e-3)
-    # the committed PMC summary was taken on these kernel sources
-    assert rf["traffic"] is not None and rf["traffic"] > 32 * cells
+    # traffic comes from the committed PMC summary of the dominant kernel, and
+    # only while that summary was taken on the current kernel sources
+    sys.path.insert(0, ROOT)
+    import bench
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(bench.PMC_SUMMARY[spl]).read(), re.S)
+    summary = json.loads(m.group(1))
+    fresh = summary.get("kernel_sha256_16") == d["extras"]["kernel_sha256_16"]
+    if fresh:
+        assert rf["traffic"] == summary["hbm_bytes_per_launch"] and rf["traffic"] > 32 * cells
+    else:
+        assert rf["traffic"] is None
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
     assert cb["unit"] == d["unit"] and "oracle" in cb["sample"]
