@@ -2,13 +2,17 @@
 """Benchmark of the flood step on one MI355X.
 
 Default workload: the 16384 x 16384 synthetic valley at dx = 1 m (268 M cells),
-dry start, CFL time step, FP32 state -- one "step" is one full time step of
-the method (device clock, boundary conditions, eq. 3 face update, donor
-scaling, eq. 4 depth update, deepest-cell reduction), captured in HIP graphs.
-Prints one JSON line: Gcell-updates/s, the HBM roofline of the step kernel,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+pre-wetted to the 30th percentile of the bed (every face carries water and runs
+the face update of eq. 3), CFL time step, FP32 state.  One "step" is one full
+time step of the method (device clock, boundary conditions, eq. 3 face update,
+donor scaling, eq. 4 depth update, deepest-cell reduction), two per launch,
+captured in HIP graphs.  Prints one JSON line: Gcell-updates/s, the HBM
+roofline of the step kernel, and the FP64 CPU oracle timed on a bounded sample
+of the same workload; `extras` holds the dry start of the same grid, active
+tiles, the ensemble, the adjoint, the discharge sweep, the method variants and
+the measured copy ceilings.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload valley16384]
 """
 import argparse
 import hashlib
@@ -29,7 +33,8 @@ CSRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc")
 KERNEL_SRCS = ["flood_device.h", "flood_march.h", "flood_kernels.hip", "flood_fused.hip"]
 # committed PMC summaries of the dominant kernel, by steps per launch
 PMC_SUMMARY = {1: os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md"),
-               2: os.path.join(ROOT, "profiles", "k_step2_valley16384_pmc.md")}
+               2: os.path.join(ROOT, "profiles", "k_step2_valley16384_prewetted_pmc.md")}
+PROBE_LIB = os.path.join(ROOT, "bench_probe.so")
 
 
 def kernel_hash() -> str:
@@ -39,9 +44,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells: int, fusion: int):
+def measured_traffic(cells: int, fusion: int, workload: str):
     """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary, if it was taken on the current kernel sources; else None."""
+    summary, if it was taken on the current kernel sources and this workload;
+    else None."""
     try:
         txt = open(PMC_SUMMARY[fusion]).read()
     except (OSError, KeyError):
@@ -50,17 +56,36 @@ def measured_traffic(cells: int, fusion: int):
     if not m:
         return None
     d = json.loads(m.group(1))
-    if d.get("kernel_sha256_16") != kernel_hash() or d.get("cells") != cells:
+    if (d.get("kernel_sha256_16") != kernel_hash() or d.get("cells") != cells or
+            d.get("workload") != workload):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def probe_stream(nbytes: int, reps: int, variant: int) -> float:
+    """GB/s (read + write) of a plain stream (bench_probe.so): 1 kernel copy,
+    4 read only, 5 write only, 7 the HIP runtime's device-to-device copy."""
+    import ctypes as C
+    L = C.CDLL(PROBE_LIB)
+    L.probe_stream.restype = C.c_int
+    L.probe_stream.argtypes = [C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    g = C.c_double()
+    st = L.probe_stream(0, int(nbytes), int(reps), int(variant), C.byref(g))
+    if st != 0:
+        raise RuntimeError(f"probe_stream variant {variant} failed with status {st}")
+    return g.value
+
+
+WORKLOAD_NAMES = {"valley16384": "valley_16384x16384_dx1m_dry_start",
+                  "valley16384_wet": "valley_16384x16384_dx1m_prewetted"}
 
 
 def build_workload(name: str):
     import synth
     if name == "valley16384":
-        return synth.config_d3(16384, wet=False), "valley_16384x16384_dx1m_dry_start"
+        return synth.config_d3(16384, wet=False), WORKLOAD_NAMES[name]
     if name == "valley16384_wet":
-        return synth.config_d3(16384, wet=True), "valley_16384x16384_dx1m_prewetted"
+        return synth.config_d3(16384, wet=True), WORKLOAD_NAMES[name]
     if name == "valley2048":
         return synth.config_d2(), "valley_2048x2048_dx5m_dry_start"
     if name == "valley256":
@@ -114,6 +139,8 @@ def cpu_single_thread(sc):
 
 # (cells per lane, rows per work item) tried by the autotuner on small grids
 SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
+# ... and by the batch autotuner on the 64-member ensemble
+BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32)]
 
 
 def progress(msg: str):
@@ -146,7 +173,7 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
         g.close()
     progress("ensemble: members one after another, two steps per launch, done")
     b = fl.Batch(ctxs)
-    cands = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32)]
+    cands = BATCH_TILINGS
     best, _ = b.autotune(cands, trial_steps)
     batch_ms = b.time(steps)
     rep = [f.get_report() for f in ctxs]
@@ -278,8 +305,9 @@ def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_d
                          cells_per_lane=best[0], rows_per_item=best[1], fusion=spl)
     g.step(warmup)
     counts = []
-    for _ in range(steps // sample_every):
-        g.step(sample_every)
+    every = max(1, min(sample_every, steps))
+    for _ in range(steps // every):
+        g.step(every)
         counts.append(g.active_items()[0])
     g.close()
     value = cells * steps / (ms / 1e3) / 1e9
@@ -288,8 +316,9 @@ def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_d
             "gcell_s_grid_equivalent": round(value, 3),
             "vs_full_grid_headline": round(value / full_value, 2),
             "items_per_step": total, "items_computed_last_step": end_items,
-            "items_computed_mean_sampled": round(float(sum(counts)) / max(1, len(counts)), 1),
-            "sample_every_steps": sample_every,
+            "items_computed_mean_sampled": (round(float(sum(counts)) / len(counts), 1)
+                                            if counts else None),
+            "sample_every_steps": every,
             "same_depth_as_full_grid": same, "budget_error": rep.budget_error()}
 
 
@@ -371,7 +400,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="valley16384")
+    ap.add_argument("--workload", default="valley16384_wet", choices=sorted(WORKLOAD_NAMES),
+                    help="valley16384_wet: pre-wetted start (default); valley16384: dry start")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--fusion", type=int, default=2, choices=[1, 2],
                     help="time steps per launch (2: two-step kernel, the default)")
@@ -383,8 +413,9 @@ def main():
     ap.add_argument("--steps-per-graph", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--extra-wet", action="store_true",
-                    help="also time the pre-wetted start of the same grid")
+    ap.add_argument("--no-other-start", action="store_true",
+                    help="skip the other start of the same grid (dry start when the headline is "
+                         "pre-wetted, and the reverse)")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched-ensemble comparison (64 uneven grids)")
     ap.add_argument("--ensemble-steps", type=int, default=5000)
@@ -393,12 +424,11 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the method-variant comparison (2048^2 valley, 20000 steps each)")
     ap.add_argument("--no-active", action="store_true",
-                    help="skip the same workload with active-tile (wet-region) skipping")
+                    help="skip the same workloads with active-tile (wet-region) skipping")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint comparison (1024^2, 5000 steps)")
-    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
-                    help="also run the plain streaming copy of this many GiB (roofline "
-                         "calibration: practical ceiling and PMC scale)")
+    ap.add_argument("--copy-gib", type=float, default=16.0,
+                    help="size of the plain streams that measure the copy ceilings (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -415,39 +445,54 @@ def main():
     sc, wname = build_workload(args.workload)
     t_gen = time.perf_counter() - t_gen
     cells = sc.nx * sc.ny
+    stream = torch.cuda.current_stream().cuda_stream
+    f32 = args.precision == "f32"
 
     def run_timed(scn, fusion=args.fusion, keep_depth=False):
         tiling = dict(cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item)
         if fusion == 2:
             tiling = dict(fusion=(2, args.cells_per_lane, args.rows_per_item))
-        f = fl.from_scenario(scn, args.precision, device=0,
-                             stream=torch.cuda.current_stream().cuda_stream,
+        f = fl.from_scenario(scn, args.precision, device=0, stream=stream,
                              steps_per_graph=args.steps_per_graph, **tiling)
-        f.step(args.warmup)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        ev_ms = f.time_steps(args.steps)     # HIP events on the stream the kernel runs on
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        rep = f.get_report()
-        dev_bytes = f.device_bytes()
-        depth = None
-        if keep_depth:
-            depth = torch.empty((scn.ny, scn.nx), dtype=torch.float32 if args.precision == "f32"
-                                else torch.float64, device="cuda")
-            f.get_depth(depth)
-        f.close()
+        try:
+            f.step(args.warmup)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            ev_ms = f.time_steps(args.steps)     # HIP events on the stream the kernel runs on
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            rep = f.get_report()
+            dev_bytes = f.device_bytes()
+            depth = None
+            if keep_depth:
+                depth = torch.empty((scn.ny, scn.nx), dtype=torch.float32 if f32 else torch.float64,
+                                    device="cuda")
+                f.get_depth(depth)
+        finally:
+            f.close()
         return ev_ms, wall, rep, dev_bytes, depth
 
-    progress(f"inputs ready ({t_gen:.1f} s); timing {args.steps} steps")
-    keep = not args.no_active and args.precision == "f32"
+    def gcell(ms):
+        return round(cells * args.steps / (ms / 1e3) / 1e9, 3)
+
+    progress(f"inputs ready ({t_gen:.1f} s); timing {args.steps} steps of {wname}")
+    keep = not args.no_active and f32
     ev_ms, wall, rep, dev_bytes, full_depth = run_timed(sc, keep_depth=keep)
     progress(f"timed: {ev_ms / args.steps:.4f} ms/step")
     ms_step = ev_ms / args.steps
     value = cells * args.steps / (ev_ms / 1e3) / 1e9
     bpc = BYTES_PER_CELL[args.precision]
-    achieved = bpc * cells / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(cells, args.fusion) if args.precision == "f32" else None
+    # Roofline of the dominant kernel.  One launch makes `fusion` steps but
+    # reads the state (h, z, n, qx, qy) once and writes it (h, qx, qy) once:
+    # its algorithmic bytes are one pass, bpc x cells, whatever the steps per
+    # launch.  Its duration: the timed region over the working launches (the
+    # region also holds the launch that settles the last speculated step and
+    # the read-back of the step count, so this slightly overstates it).
+    launches = max(1, -(-args.steps // args.fusion))
+    launch_ms = ev_ms / launches
+    alg_bytes = bpc * cells
+    achieved = alg_bytes / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(cells, args.fusion, wname) if f32 else None
     out = {
         "metric": "Gcell-updates/s + % of HBM BW; batched & adjoint vs plain step, same GPU",
         "value": round(value, 3),
@@ -464,18 +509,20 @@ def main():
         "config": {"workload": wname, "grid": f"{sc.nx}x{sc.ny}", "dx_m": sc.dx,
                    "cells": cells, "dt": "CFL alpha 0.7, device-side", "dt_max_s": sc.dt_max,
                    "inflow_cells": sc.inflow[2], "outflow": "east edge",
+                   "steps_per_launch": args.fusion,
                    "steps_in_run": args.warmup + args.steps, "parallelism": "single GPU"},
-        # algorithmic bytes = 32 B (FP32) per cell-update x the cell-updates one
-        # launch makes (cells x steps per launch), over the launch's duration;
-        # traffic = HBM bytes per launch measured by PMC counters
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "steps_per_launch": args.fusion,
-                     "algorithmic_bytes_per_launch": bpc * cells * args.fusion,
-                     "launch_ms": round(ms_step * args.fusion, 5),
-                     # the bytes the launch actually moves, as a fraction of the peak
-                     "traffic_frac": (round(traffic / (ms_step * args.fusion / 1e3) / 1e9 /
-                                            HBM_PEAK_GBS, 4) if traffic else None)},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "launches_timed": launches,
+                     "launch_ms": round(launch_ms, 5),
+                     # the bytes the launch actually moves (PMC), as a fraction of the peak
+                     "traffic_frac": (round(traffic / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None),
+                     # what a kernel making one pass per step would have to move
+                     # for the same rate: a cell-update equivalent, not HBM bytes
+                     "one_pass_per_step_equivalent_gbs": round(achieved * args.fusion, 1)},
     }
     extras = {"wall_s_timed_region": round(wall, 4), "input_generation_s": round(t_gen, 1),
               "device_bytes": dev_bytes, "budget_error": rep.budget_error(),
@@ -483,33 +530,33 @@ def main():
     other = 3 - args.fusion
     if not args.no_compare:
         ev1, _, rep1, _, _ = run_timed(sc, other)
-        extras[f"steps_per_launch_{other}_gcell_s"] = round(cells * args.steps / (ev1 / 1e3) / 1e9, 3)
+        extras[f"steps_per_launch_{other}_gcell_s"] = gcell(ev1)
         extras[f"steps_per_launch_{other}_same_clock"] = (rep1.t == rep.t and rep1.steps == rep.steps)
     if keep:
         progress("active tiles")
         extras["active_tiles"] = run_active(fl, torch, sc, args.warmup, args.steps, value, full_depth)
     del full_depth
-    if args.extra_wet and args.workload == "valley16384":
+    if not args.no_other_start:
         import synth
+        oname = "valley16384" if args.workload == "valley16384_wet" else "valley16384_wet"
+        key = "dry_start" if oname == "valley16384" else "prewetted"
+        progress(f"{key}: same grid")
         del sc
-        scw = synth.config_d3(16384, wet=True)
-        for fu in ((args.fusion,) if args.no_compare else (args.fusion, other)):
-            ev2, _, rep2, _, _ = run_timed(scw, fu)
-            extras[f"prewetted_steps_per_launch_{fu}_gcell_s"] = round(
-                cells * args.steps / (ev2 / 1e3) / 1e9, 3)
-        if not args.no_active and args.precision == "f32":
-            f = fl.from_scenario(scw, "f32", device=0, stream=torch.cuda.current_stream().cuda_stream,
-                                 active_tiles=True, fusion=2)
-            f.step(args.warmup)
-            best3, _ = f.autotune(ACTIVE_TILINGS, 20)
-            spl3, _ = f.autotune_fusion(20)
-            ev3 = f.time_steps(args.steps)
-            extras["prewetted_active_tiles_single_step_tiling_autotuned"] = list(best3)
-            extras["prewetted_active_tiles_steps_per_launch_autotuned"] = spl3
-            extras["prewetted_active_tiles_items_computed"] = list(f.active_items())
-            f.close()
-            extras["prewetted_active_tiles_gcell_s"] = round(cells * args.steps / (ev3 / 1e3) / 1e9, 3)
-        sc = scw
+        sco, _ = build_workload(oname)
+        d = {"workload": WORKLOAD_NAMES[oname]}
+        keep_o = not args.no_active and f32
+        ev2, _, rep2, _, depth_o = run_timed(sco, args.fusion, keep_depth=keep_o)
+        d[f"steps_per_launch_{args.fusion}_gcell_s"] = gcell(ev2)
+        d["budget_error"] = rep2.budget_error()
+        if not args.no_compare:
+            ev3, _, _, _, _ = run_timed(sco, other)
+            d[f"steps_per_launch_{other}_gcell_s"] = gcell(ev3)
+        if keep_o:
+            d["active_tiles"] = run_active(fl, torch, sco, args.warmup, args.steps,
+                                           cells * args.steps / (ev2 / 1e3) / 1e9, depth_o)
+        del depth_o, sco
+        extras[key] = d
+        sc = None
     if not args.no_ensemble:
         progress("ensemble")
         extras["ensemble"] = run_ensemble(fl, torch, args.ensemble_steps)
@@ -522,13 +569,23 @@ def main():
     if not args.no_variants:
         progress("method variants")
         extras["method_variants"] = run_variants(fl, torch)
-    if args.copy_probe_gib > 0:
-        nbytes = int(args.copy_probe_gib * (1 << 30))
-        extras["copy_probe_bytes"] = nbytes
-        extras["copy_probe_gbs"] = {v: round(fl.copy_probe(nbytes, 10, v), 1) for v in (1, 3)}
+    if args.copy_gib > 0:
+        progress("copy ceilings")
+        torch.cuda.empty_cache()
+        nbytes = int(args.copy_gib * (1 << 30))
+        cc = {"bytes": nbytes,
+              "kernel_copy_gbs": round(probe_stream(nbytes, 10, 1), 1),
+              "hip_memcpy_d2d_gbs": round(probe_stream(nbytes, 10, 7), 1),
+              "read_only_gbs": round(probe_stream(nbytes, 10, 4), 1),
+              "write_only_gbs": round(probe_stream(nbytes, 10, 5), 1)}
+        best_copy = max(cc["kernel_copy_gbs"], cc["hip_memcpy_d2d_gbs"])
+        cc["step_launch_traffic_vs_best_copy"] = (
+            round(traffic / (launch_ms / 1e3) / 1e9 / best_copy, 4) if traffic else None)
+        cc["step_launch_algorithmic_vs_best_copy"] = round(achieved / best_copy, 4)
+        extras["copy_ceilings"] = cc
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
-        if args.extra_wet and args.workload == "valley16384":
+        if sc is None:
             sc, _ = build_workload(args.workload)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
         extras["cpu_oracle_single_thread"] = cpu_single_thread(sc)

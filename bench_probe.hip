@@ -1,11 +1,10 @@
-// Plain streaming copy used to calibrate the roofline: the practical HBM
-// ceiling of a read-once/write-once kernel on this GPU, and the scale of the
-// FETCH_SIZE / WRITE_SIZE counters for a copy of known size.
+// Bandwidth probes of the benchmark (not part of libflood): plain streams that
+// calibrate the roofline -- the practical HBM ceiling of a read-once /
+// write-once kernel on this GPU, the HIP runtime's own device-to-device copy
+// as an independent reference, and the scale of the FETCH_SIZE / WRITE_SIZE
+// counters for a copy of known size.  Built into bench_probe.so, loaded only
+// by bench.py.
 #include <hip/hip_runtime.h>
-
-#include <string>
-
-#include "../../include/flood.h"
 
 namespace {
 
@@ -55,21 +54,32 @@ __global__ __launch_bounds__(256) void k_write(v4f* __restrict__ dst, long long 
 
 }  // namespace
 
-extern "C" fl_status fl_copy_probe(int device, size_t bytes, int reps, int variant, double* gbps) {
-    if (!gbps || reps < 1 || bytes < 4096 || variant < 0 || variant > 6) return FL_EINVAL;
-    if (hipSetDevice(device) != hipSuccess) return FL_EHIP;
+enum { P_OK = 0, P_EINVAL = 1, P_ENOMEM = 2, P_EHIP = 3 };
+
+// Achieved bandwidth (bytes read + bytes written per second, GB/s) of
+// `reps` repetitions of a stream over `bytes` bytes on `device`, timed with HIP
+// events on the probe's own stream after one untimed repetition.
+// variant: 0 copy, 1 copy unrolled x4, 2 non-temporal copy, 3 non-temporal
+// copy unrolled x4, 4 read-only stream, 5 write-only stream, 6 copy unrolled
+// x4 with 4x more workgroups, 7 hipMemcpyAsync device to device (the
+// runtime's own copy).  Allocates and frees its two buffers.  Returns 0, or
+// 1 bad argument (bytes < 4096, reps < 1, unknown variant), 2 no memory,
+// 3 a HIP error.
+extern "C" int probe_stream(int device, size_t bytes, int reps, int variant, double* gbps) {
+    if (!gbps || reps < 1 || bytes < 4096 || variant < 0 || variant > 7) return P_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return P_EHIP;
     const long long n = (long long)(bytes / sizeof(v4f));
     void *a = nullptr, *b = nullptr;
-    if (hipMalloc(&a, n * sizeof(v4f)) != hipSuccess) return FL_ENOMEM;
+    if (hipMalloc(&a, n * sizeof(v4f)) != hipSuccess) return P_ENOMEM;
     if (hipMalloc(&b, n * sizeof(v4f)) != hipSuccess) {
         (void)hipFree(a);
-        return FL_ENOMEM;
+        return P_ENOMEM;
     }
     hipStream_t s;
     hipEvent_t e0, e1;
-    fl_status st = FL_OK;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) st = FL_EHIP;
-    if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = FL_EHIP;
+    int st = P_OK;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) st = P_EHIP;
+    if (!st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = P_EHIP;
     if (!st) {
         (void)hipMemsetAsync(a, 0, n * sizeof(v4f), s);
         int dev_cu = 256;
@@ -85,6 +95,7 @@ extern "C" fl_status fl_copy_probe(int device, size_t bytes, int reps, int varia
             case 3: hipLaunchKernelGGL((k_copy<4, true>), dim3(blocks), dim3(256), 0, s, src, dst, n); break;
             case 4: hipLaunchKernelGGL(k_read, dim3(blocks), dim3(256), 0, s, src, dst, n); break;
             case 5: hipLaunchKernelGGL(k_write, dim3(blocks), dim3(256), 0, s, dst, n); break;
+            case 7: (void)hipMemcpyAsync(dst, src, n * sizeof(v4f), hipMemcpyDeviceToDevice, s); break;
             default: hipLaunchKernelGGL((k_copy<4, false>), dim3(blocks), dim3(256), 0, s, src, dst, n); break;
             }
         };
@@ -92,9 +103,9 @@ extern "C" fl_status fl_copy_probe(int device, size_t bytes, int reps, int varia
         (void)hipEventRecord(e0, s);
         for (int r = 0; r < reps; ++r) launch();
         (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) st = FL_EHIP;
+        if (hipEventSynchronize(e1) != hipSuccess) st = P_EHIP;
         float ms = 0.f;
-        if (!st && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = FL_EHIP;
+        if (!st && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = P_EHIP;
         const double moved = (variant == 4 || variant == 5) ? 1.0 : 2.0;
         if (!st) *gbps = moved * (double)n * sizeof(v4f) * reps / (ms * 1e-3) / 1e9;
         (void)hipEventDestroy(e0);

@@ -122,9 +122,11 @@ void fl_default_params(fl_params *p);
  */
 fl_status fl_create(fl_ctx **ctx, int device, void *hip_stream, fl_precision prec);
 
-/* Grid of nx x ny cells of side dx metres.  EINVAL: nx or ny < 1, dx <= 0 or
- * not finite, nx + 264 > 2^28 or ny + 8 > 2^30.  Resets everything set
- * before (DEM, roughness, boundaries, state). */
+/* Grid of nx x ny cells of side dx metres: the raster of square cells on
+ * which eqs. (3)-(4) are discretised (Methods, "Shallow Water Equations"),
+ * with dx the DEM's "resolution" input (Appendix, "Inputs").  EINVAL: nx or
+ * ny < 1, dx <= 0 or not finite, nx + 264 > 2^28 or ny + 8 > 2^30.  Resets
+ * everything set before (DEM, roughness, boundaries, state). */
 fl_status fl_init_grid(fl_ctx *ctx, int32_t nx, int32_t ny, double dx);
 
 /* Bed elevation z (metres, "unpadded_dem"), ny rows of row_stride elements,
@@ -186,13 +188,22 @@ size_t fl_workspace_bytes(int32_t nx, int32_t ny, fl_precision prec, uint32_t fl
 fl_status fl_bind_workspace(fl_ctx *ctx, void *dev_ptr, size_t bytes);
 
 /* Validate, allocate device memory, upload, reset clock and budget, capture
- * the multi-step graph.  Must follow fl_init_grid, fl_set_dem and
- * fl_set_manning (ESTATE otherwise).  Any fl_set_* after commit needs a new
- * commit before stepping. */
+ * the multi-step graph: the set-up the paper's run_simulation performs before
+ * stepping (Appendix, "Code structure": DEM, Manning matrix, boundary
+ * conditions of eqs. 5-6, initial state).  Must follow fl_init_grid,
+ * fl_set_dem and fl_set_manning (ESTATE otherwise).  Any fl_set_* after
+ * commit needs a new commit before stepping.  The context's device memory
+ * (or the bound workspace) holds the state; nothing is allocated by later
+ * steps. */
 fl_status fl_commit(fl_ctx *ctx);
 
-/* Enqueue nsteps steps (graph replays plus single launches).  ESTATE before
- * commit.  EINVAL: nsteps < 0. */
+/* Enqueue nsteps steps (graph replays plus single launches).  Each step is
+ * the explicit update of Methods, "Shallow Water Equations": boundary faces
+ * (eqs. 5, 6), interior faces (eq. 3), donor scaling, depths (eq. 4), with dt
+ * from the device clock (the paper's time step, Methods and Appendix,
+ * "Inputs").  Asynchronous on the context's stream, except with two steps per
+ * launch (fl_set_fusion), which synchronises before it returns.  ESTATE
+ * before commit.  EINVAL: nsteps < 0. */
 fl_status fl_step(fl_ctx *ctx, int64_t nsteps);
 
 /* Advance the simulated time by `seconds` (the last step shortened to land on
@@ -201,13 +212,20 @@ fl_status fl_step(fl_ctx *ctx, int64_t nsteps);
  * depth stopped the clock: ENONFINITE). */
 fl_status fl_advance(fl_ctx *ctx, double seconds);
 
-/* Copy the current depth into dst (ny rows of row_stride elements). */
+/* Copy the current depth h (the water height of eq. 4; the "height of the
+ * water" output, Appendix, "Outputs") into dst (ny rows of row_stride
+ * elements, host or device memory owned by the caller).  Synchronises.
+ * EINVAL: NULL dst or row_stride < nx; ESTATE before commit. */
 fl_status fl_get_depth(fl_ctx *ctx, void *dst, int64_t row_stride, int on_device);
 
-/* Copy the current discharges, border faces included (layout above). */
+/* Copy the current face discharges q_x, q_y of eq. (3) (the "flux in the x
+ * and y directions" output, Appendix, "Outputs"), border faces included, in
+ * the layout above; caller-owned host or device memory.  Synchronises.
+ * EINVAL: a NULL output; ESTATE before commit. */
 fl_status fl_get_discharge(fl_ctx *ctx, void *qx, void *qy, int on_device);
 
-/* The whole state in the layout fl_set_state takes: depth h (ny x nx), qx
+/* The whole state of eqs. (3)-(4) (Appendix, "Outputs": h, q_x, q_y) in the
+ * layout fl_set_state takes: depth h (ny x nx), qx
  * (ny x (nx+1)) and qy ((ny+1) x nx) with the border faces, and the time t;
  * any of them may be NULL (qx and qy together).  Host or device memory.
  * Synchronises.  ENONFINITE if a depth became non-finite (the outputs are
@@ -419,15 +437,6 @@ const char *fl_batch_last_error(const fl_batch *batch);
 
 /* Free the batch (not its members).  NULL is a no-op. */
 void fl_batch_destroy(fl_batch *batch);
-
-/* Roofline calibration: a plain streaming copy of `bytes` bytes (16-byte
- * vectors, grid-stride) repeated `reps` times on device `device`; returns the
- * achieved bandwidth in GB/s (bytes read + bytes written per second).
- * variant: 0 copy, 1 copy unrolled x4, 2 non-temporal copy, 3 non-temporal
- * copy unrolled x4, 4 read-only stream, 5 write-only stream, 6 copy unrolled
- * x4 with 4x more workgroups.  Allocates and frees its own two buffers.
- * EINVAL: bytes < 4096, reps < 1 or bad variant. */
-fl_status fl_copy_probe(int device, size_t bytes, int reps, int variant, double *gbps);
 
 #ifdef __cplusplus
 }

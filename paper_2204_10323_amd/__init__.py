@@ -6,9 +6,11 @@ works without a GPU; loading the library raises if it has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
+import weakref
 from typing import Optional, Tuple
 
 import numpy as np
@@ -29,7 +31,7 @@ EXPORTS = [
     "fl_default_params", "fl_create", "fl_init_grid", "fl_set_dem", "fl_set_manning",
     "fl_set_inflow", "fl_set_outflow", "fl_set_params", "fl_set_state", "fl_commit", "fl_step",
     "fl_advance", "fl_get_depth", "fl_get_discharge", "fl_get_report", "fl_last_error",
-    "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes", "fl_copy_probe",
+    "fl_destroy", "fl_time_steps", "fl_set_tiling", "fl_device_bytes",
     "fl_batch_create", "fl_batch_set_tiling", "fl_batch_autotune", "fl_batch_run",
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
@@ -63,6 +65,26 @@ class fl_report(C.Structure):
 
 
 _lib = None
+
+# Open contexts and batches.  At interpreter exit they are closed by an atexit
+# hook, batches first (they borrow their members), while the HIP runtime is
+# still up; after that no finalizer makes a HIP call (objects collected during
+# interpreter shutdown are left to the process exit).
+_open_ctxs: "weakref.WeakSet" = weakref.WeakSet()
+_open_batches: "weakref.WeakSet" = weakref.WeakSet()
+_exiting = False
+
+
+@atexit.register
+def _close_all():
+    global _exiting
+    try:
+        for b in list(_open_batches):
+            b.close()
+        for f in list(_open_ctxs):
+            f.close()
+    finally:
+        _exiting = True
 
 
 def lib() -> C.CDLL:
@@ -104,7 +126,6 @@ def lib() -> C.CDLL:
             "fl_time_steps": (C.c_int, [vp, i64, C.POINTER(dbl)]),
             "fl_set_tiling": (C.c_int, [vp, i32, i32]),
             "fl_device_bytes": (C.c_size_t, [vp]),
-            "fl_copy_probe": (C.c_int, [C.c_int, C.c_size_t, C.c_int, C.c_int, C.POINTER(dbl)]),
             "fl_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
             "fl_batch_set_tiling": (C.c_int, [vp, i32, i32]),
             "fl_batch_autotune": (C.c_int, [vp, C.POINTER(i32), i32, i32, C.POINTER(i32),
@@ -236,6 +257,7 @@ class Flood:
         if st != FL_OK:
             raise FloodError(st, lib().fl_last_error(None).decode())
         self.ctx = h
+        _open_ctxs.add(self)
         _check(self.ctx, lib().fl_init_grid(self.ctx, self.nx, self.ny, self.dx))
 
     # -- inputs
@@ -463,8 +485,11 @@ class Flood:
         if getattr(self, "ctx", None):
             lib().fl_destroy(self.ctx)
             self.ctx = None
+        _open_ctxs.discard(self)
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -482,6 +507,7 @@ class Batch:
         if st != FL_OK:
             raise FloodError(st, lib().fl_batch_last_error(None).decode())
         self.b = h
+        _open_batches.add(self)
 
     def _check(self, st):
         if st != FL_OK:
@@ -522,21 +548,15 @@ class Batch:
         if getattr(self, "b", None):
             lib().fl_batch_destroy(self.b)
             self.b = None
+        _open_batches.discard(self)
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
             pass
-
-
-def copy_probe(nbytes: int, reps: int = 20, variant: int = 1, device: int = 0) -> float:
-    """Achieved GB/s (read + write) of a plain streaming copy of nbytes (fl_copy_probe)."""
-    g = C.c_double()
-    st = lib().fl_copy_probe(device, int(nbytes), int(reps), int(variant), C.byref(g))
-    if st != FL_OK:
-        raise FloodError(st, "fl_copy_probe failed")
-    return g.value
 
 
 def fraction_section(length: int, f_start: float, f_end: float):

@@ -447,10 +447,14 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<T> a) {
 // for each member one clock entry and its tile items.  Entries of step k of a
 // member wait only until that member's step k-1 is complete (its depth
 // maximum and clock then exist), so members do not wait for each other and no
-// grid-wide barrier is needed.  Every entry that is waited on was dequeued
-// earlier by a running wave of the same XCD (the launch is cooperative: all
-// waves are resident), so the lowest unfinished entry can always run.  A
-// wait longer than spin_limit sleeps sets *error and exits.
+// grid-wide barrier is needed.  No co-residency is needed either: a wave
+// takes an entry only while it runs, and an entry waits only for entries of
+// lower queue index, which running waves of the same XCD took before it; so
+// the lowest unfinished entry never waits and always completes, and a wave
+// that has not started yet holds nothing anyone waits for.  Every XCD gets
+// workgroups (the grid is a multiple of the CU count and workgroups go
+// round-robin to the XCDs), and each of them drains its XCD's queue.  A wait
+// longer than spin_limit sleeps sets *error and exits.
 template <typename T, int CPT, bool ACT>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs<T> B) {
     const int lane = threadIdx.x & 63;
@@ -740,10 +744,9 @@ hipError_t launch_batch_cpt(const BatchArgs<T>& b, int device, hipStream_t s, in
     if (e != hipSuccess) return e;
     const int blocks = std::max(1, per_cu) * ncu;
     if (blocks_out) *blocks_out = blocks;
-    BatchArgs<T> bb = b;
-    void* args[] = {&bb};
-    return hipLaunchCooperativeKernel((const void*)k_batch<T, CPT, ACT>, dim3(blocks), dim3(256), args,
-                                      0, s);
+    // an ordinary launch: the queue needs no co-residency (see k_batch)
+    hipLaunchKernelGGL((k_batch<T, CPT, ACT>), dim3(blocks), dim3(256), 0, s, b);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -1986,7 +1986,7 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     ba.next = b->d_sync;
     ba.done = b->d_sync + kMaxXcc;
     ba.error = b->d_error;
-    ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: only a broken co-residency could reach it
+    ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: a wait that long means a broken hand-over
     Event e0, e1;
     if (ms) {
         BHIP_TRY(b, hipEventCreate(&e0.e));
