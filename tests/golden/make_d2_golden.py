@@ -3,8 +3,9 @@ FP64 CPU oracle.  Calls only the oracle and the seeded input generator.
 
     python tests/golden/make_d2_golden.py        # ~20 min on 8 cores
 
-Stores (d2_2048_20000.npz): the depth on every 16th cell in each direction,
-a dense 96 x 96 block around the channel at mid-valley, the clock, the volume
+Stores (d2_2048_20000.npz): the depth of every cell (the oracle's FP64 value
+rounded once to float32 for storage, an error below 5e-7 m for depths under
+10 m, far inside the 1e-3 m gate it is compared at), the clock, the volume
 budget, and a hash of the float32 inputs so a changed generator is detected.
 """
 import hashlib
@@ -20,8 +21,6 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-STRIDE, OFF = 16, 8
-
 
 def input_hash(sc) -> str:
     h = hashlib.sha256()
@@ -33,15 +32,6 @@ def input_hash(sc) -> str:
     return h.hexdigest()
 
 
-def dense_block(sc):
-    """96 x 96 cells centred on the channel at x = Lx/2."""
-    i0 = sc.nx // 2 - 48
-    d = synth.channel_distance(synth.Valley(sc.nx, sc.ny, sc.dx, 5e-4, 2.0, 40.0, 0.3, seed=2,
-                                            meander=True))
-    j_c = int(np.argmin(np.abs(d[:, sc.nx // 2])))
-    return j_c - 48, i0
-
-
 def main():
     sc = synth.config_d2()
     o = oracle.Run(sc)
@@ -50,11 +40,9 @@ def main():
         o.step(sc.steps // 20)
         print(f"{(k + 1) * sc.steps // 20} steps, t = {o.clock.t:.1f} s, "
               f"{time.time() - t0:.0f} s wall", flush=True)
-    j0, i0 = dense_block(sc)
     np.savez_compressed(
         os.path.join(HERE, "d2_2048_20000.npz"),
-        h_sample=o.h[OFF::STRIDE, OFF::STRIDE], h_block=o.h[j0:j0 + 96, i0:i0 + 96],
-        block_origin=np.array([j0, i0]), stride=np.array([STRIDE, OFF]),
+        h_full=o.h.astype(np.float32),
         t=np.array(o.clock.t), steps=np.array(o.clock.steps), v_in=np.array(o.clock.v_in),
         v_out=np.array(o.clock.v_out), v0=np.array(o.v0), volume=np.array(o.volume()),
         hmax=np.array(o.h.max()), input_sha256=np.array(input_hash(sc)))

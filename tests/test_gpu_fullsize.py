@@ -7,8 +7,10 @@ oracle runs that window; the test shows the window is large enough from each
 side's own output (the oracle's outer band stays bitwise dry; the GPU grid
 outside the window is exactly zero) and compares every cell.
 
-Pre-wetted start: every cell carries water, so the oracle runs the whole
-268 M-cell grid, for two steps.
+Pre-wetted start (the benchmark's headline workload): every cell carries
+water, so the oracle runs the whole 268 M-cell grid, for 24 steps; and 1000
+steps against the oracle's stored values on a lattice of cells and dense
+blocks (tests/golden/make_d3wet_golden.py).
 """
 import numpy as np
 import pytest
@@ -71,28 +73,36 @@ def test_valley16384_dry_1000_steps_full_grid(d3_dry, spl):
     assert abs(r.v_in / o.clock.v_in - 1) <= 1e-5
 
 
-def test_valley16384_prewetted_two_steps_full_grid(d3_dry):
-    sc = d3_dry
+def _prewetted(sc):
     z = sc.z
-    sub = z[::16, ::16]
-    eta0 = np.float32(np.percentile(sub, 30))
+    eta0 = np.float32(np.percentile(z[::16, ::16], 30))
     h0 = np.maximum(eta0 - z, np.float32(0)).astype(np.float32)
-    wet = Scenario("d3wet", sc.nx, sc.ny, sc.dx, z, sc.n, h0, sc.inflow, sc.outflow,
-                   dt_max=sc.dt_max)
-    print("CASE fullsize prewetted 2 steps", flush=True)
-    f = fl.from_scenario(wet, "f32", fusion=2)    # one two-step launch
-    f.step(2)
+    return Scenario("d3wet", sc.nx, sc.ny, sc.dx, z, sc.n, h0, sc.inflow, sc.outflow,
+                    dt_max=sc.dt_max)
+
+
+def test_valley16384_prewetted_24_steps_full_grid(d3_dry):
+    """The benchmark's headline workload and launch configuration (two steps per
+    launch, default tiling, speculated second dt): 12 launches, every cell and
+    face against the oracle run on the whole grid."""
+    wet = _prewetted(d3_dry)
+    print("CASE fullsize prewetted 24 steps", flush=True)
+    f = fl.from_scenario(wet, "f32", fusion=2)
+    f.step(24)
     h = f.get_depth()
     qx, qy = f.get_discharge()
     r = f.get_report()
     f.close()
     del f
     o = oracle.Run(wet)
-    o.step(2)
+    o.step(24)
     assert (o.h > 0).mean() > 0.2
-    assert max_abs(h, o.h) <= 1e-4
-    assert rel_err(qx, o.qx) <= 1e-4 and rel_err(qy, o.qy) <= 1e-4
-    assert abs(r.t / o.clock.t - 1) <= 1e-6
+    eh, eqx, eqy = max_abs(h, o.h), rel_err(qx, o.qx), rel_err(qy, o.qy)
+    print(f"max|dh| = {eh:.3e} m, qx rel {eqx:.3e}, qy rel {eqy:.3e}", flush=True)
+    assert eh <= 1e-4
+    assert eqx <= 1e-4 and eqy <= 1e-4
+    assert r.steps == 24 and abs(r.t / o.clock.t - 1) <= 1e-6
+    assert abs(r.v_in / o.clock.v_in - 1) <= 1e-5
     assert r.budget_error() <= 1e-6
 
 
