@@ -429,6 +429,22 @@ fl_status fl_batch_autotune(fl_batch *batch, const int32_t *candidates, int32_t 
  * launch fails or a wait ran into its limit. */
 fl_status fl_batch_run(fl_batch *batch, int64_t nsteps);
 
+/* fl_batch_run for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and the same results, bit for bit, but the launch's scratch (member
+ * descriptors, queue heads, per-member completion counters, the error flag)
+ * lives in a library-owned static device array of 1 MiB per GPU, cleared by
+ * a kernel at each call, and the descriptors are staged through pinned host
+ * memory that fl_batch_create allocated; the call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  The array is held until
+ * the process ends and is shared by every call on that GPU: calls that
+ * overlap on one GPU (from several threads or streams) race and must not be
+ * issued.  Synchronises like fl_batch_run.  EINVAL: nsteps < 0, or more than
+ * FL_NOALLOC_MAX_MEMBERS members; ESTATE: a member not committed; EHIP as
+ * fl_batch_run. */
+#define FL_NOALLOC_MAX_MEMBERS 256
+fl_status fl_batch_run_noalloc(fl_batch *batch, int64_t nsteps);
+
 /* fl_batch_run bracketed by HIP events; returns the launch's milliseconds. */
 fl_status fl_batch_time(fl_batch *batch, int64_t nsteps, double *elapsed_ms);
 

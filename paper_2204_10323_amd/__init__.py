@@ -23,6 +23,7 @@ FL_F32, FL_F64 = 0, 1
 FL_WEST, FL_EAST, FL_SOUTH, FL_NORTH = range(4)
 FL_FRICTION_FACE, FL_FRICTION_VECTOR = 0, 1
 FL_BOUNDARY_SECTION, FL_BOUNDARY_CELL_AREA = 0, 1
+FL_NOALLOC_MAX_MEMBERS = 256   # members fl_batch_run_noalloc's device scratch holds
 STATUS_NAMES = {0: "FL_OK", 1: "FL_EINVAL", 2: "FL_ENOMEM", 3: "FL_EHIP", 4: "FL_ESTATE",
                 5: "FL_ENONFINITE"}
 
@@ -36,7 +37,7 @@ EXPORTS = [
     "fl_batch_time", "fl_batch_last_error", "fl_batch_destroy",
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
     "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state", "fl_autotune_fusion",
-    "fl_set_active_tiles", "fl_active_items", "fl_set_variant",
+    "fl_set_active_tiles", "fl_active_items", "fl_set_variant", "fl_batch_run_noalloc",
 ]
 
 
@@ -131,6 +132,7 @@ def lib() -> C.CDLL:
             "fl_batch_autotune": (C.c_int, [vp, C.POINTER(i32), i32, i32, C.POINTER(i32),
                                             C.POINTER(dbl)]),
             "fl_batch_run": (C.c_int, [vp, i64]),
+            "fl_batch_run_noalloc": (C.c_int, [vp, i64]),
             "fl_batch_time": (C.c_int, [vp, i64, C.POINTER(dbl)]),
             "fl_batch_last_error": (C.c_char_p, [vp]),
             "fl_batch_destroy": (None, [vp]),
@@ -537,6 +539,12 @@ class Batch:
     def run(self, nsteps: int):
         self._live()
         self._check(lib().fl_batch_run(self.b, int(nsteps)))
+
+    def run_noalloc(self, nsteps: int):
+        """fl_batch_run_noalloc: the same steps with the library's static device
+        scratch (no allocation during the call)."""
+        self._live()
+        self._check(lib().fl_batch_run_noalloc(self.b, int(nsteps)))
 
     def time(self, nsteps: int) -> float:
         self._live()

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,9 +16,42 @@
 
 using namespace flood;
 
+// Device scratch of fl_batch_run_noalloc: the batch's member descriptors, the
+// per-XCD queue heads, the per-member completion counters and the error flag,
+// for callers that cannot allocate.  One copy per GPU, held until the process
+// ends; every fl_batch_run_noalloc call on a GPU uses it (overlapping calls on
+// one GPU race).  Host code must not pass `scratch` itself to a kernel: its
+// device address comes from hipGetSymbolAddress (scratch_ptr below).
+constexpr size_t kScratchBytes = 1u << 20;   // 1 MiB
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+// Device address of `scratch` per device, taken once per device (at the first
+// fl_create on it, with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 size_t elem_size(fl_precision p) { return p == FL_F64 ? sizeof(double) : sizeof(float); }
 
@@ -854,6 +888,11 @@ fl_status fl_create(fl_ctx** out, int device, void* hip_stream, fl_precision pre
     e = hipSetDevice(device);
     if (e != hipSuccess) {
         g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return FL_EHIP;
+    }
+    e = scratch_setup(device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("fl_create: device scratch address: ") + hipGetErrorString(e);
         return FL_EHIP;
     }
     fl_ctx* c = new (std::nothrow) fl_ctx();
@@ -1886,6 +1925,9 @@ struct fl_batch {
     unsigned long long* d_sync = nullptr;   // [0] queue head, [1..] per-member done counts
     int* d_error = nullptr;
     int last_blocks = 0;
+    std::vector<int> member_xcd;    // XCD each member runs on (planning scratch, sized at create)
+    void* h_stage = nullptr;        // pinned host staging of the descriptors (fl_batch_run_noalloc)
+    size_t h_stage_bytes = 0;
     std::string err;
 };
 
@@ -1910,30 +1952,37 @@ fl_status batch_check_members(fl_batch* b) {
     return FL_OK;
 }
 
-template <typename T>
-fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
-    const int S = (int)b->members.size();
-    // Bin-pack the members onto the XCDs (largest first onto the least loaded).
+// Number of XCDs the batch's members are spread over.
+int batch_xccs(const fl_batch* b) {
     int nxcc = 1;
     if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, b->device) != hipSuccess || nxcc < 1)
         nxcc = 1;
-    nxcc = std::min(nxcc, kMaxXcc);
-    std::vector<std::vector<int>> bins(nxcc);
-    std::vector<long long> load(nxcc, 0);
+    return std::min(nxcc, kMaxXcc);
+}
+
+// The member descriptors of one launch into scen[S] (host memory) and the
+// per-XCD queues of `ba`: members are bin-packed onto the XCDs, largest
+// first onto the least loaded.  Allocates nothing.
+template <typename T>
+void batch_plan(fl_batch* b, int freeze, int nxcc, BatchScen<T>* scen, BatchArgs<T>& ba) {
+    const int S = (int)b->members.size();
+    long long load[kMaxXcc] = {};
     for (int k = 0; k < S; ++k) {    // b->order is by decreasing cell count
         const int m = b->order[k];
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        bins[x].push_back(m);
+        int x = 0;
+        for (int y = 1; y < nxcc; ++y)
+            if (load[y] < load[x]) x = y;
+        b->member_xcd[m] = x;
         load[x] += (long long)b->members[m]->nx * b->members[m]->ny;
     }
-    std::vector<BatchScen<T>> scen(S);
-    BatchArgs<T> ba{};
     ba.nxcc = nxcc;
     int idx = 0;
     for (int x = 0; x < nxcc; ++x) {
         ba.xbegin[x] = idx;
         int first = 0;
-        for (int m : bins[x]) {
+        for (int k = 0; k < S; ++k) {
+            const int m = b->order[k];
+            if (b->member_xcd[m] != x) continue;
             fl_ctx* c = b->members[m];
             const Tiling tl = tiling_of(c, b->cpt, b->rows);
             for (int r = 0; r < 6; ++r) {
@@ -1953,14 +2002,16 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         ba.per_step[x] = first;
     }
     ba.xbegin[nxcc] = idx;
-    const size_t bytes = sizeof(BatchScen<T>) * S;
-    if (bytes > b->scen_bytes) {
-        if (b->d_scen) (void)hipFree(b->d_scen);
-        b->d_scen = nullptr;
-        b->scen_bytes = 0;
-        BHIP_TRY(b, hipMalloc(&b->d_scen, bytes));
-        b->scen_bytes = bytes;
-    }
+}
+
+// One batch launch of nsteps steps with the descriptors scen_host (S entries)
+// copied to d_scen, the queue heads and completion counters at d_sync
+// (kMaxXcc + S words) and the error flag at d_error.  Allocates nothing.
+template <typename T>
+fl_status batch_execute(fl_batch* b, long long nsteps, int freeze, float* ms, BatchArgs<T>& ba,
+                        const BatchScen<T>* scen_host, BatchScen<T>* d_scen,
+                        unsigned long long* d_sync, int* d_error) {
+    const int S = (int)b->members.size();
     // Members' pending work is on their own streams; the batch runs on its own.
     for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
     // The partial-sum slots depend on the work decomposition: fold them
@@ -1978,14 +2029,17 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         if (!act_flags_hold(c, b->cpt, b->rows))
             BHIP_TRY(b, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, b->stream));
     }
-    BHIP_TRY(b, hipMemcpyAsync(b->d_scen, scen.data(), bytes, hipMemcpyHostToDevice, b->stream));
-    BHIP_TRY(b, hipMemsetAsync(b->d_sync, 0, sizeof(unsigned long long) * (S + kMaxXcc), b->stream));
-    BHIP_TRY(b, hipMemsetAsync(b->d_error, 0, sizeof(int), b->stream));
-    ba.scen = (const BatchScen<T>*)b->d_scen;
+    BHIP_TRY(b, hipMemcpyAsync(d_scen, scen_host, sizeof(BatchScen<T>) * S, hipMemcpyHostToDevice,
+                               b->stream));
+    // zeroed by a kernel (also fine inside a captured graph)
+    BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(d_sync),
+                                  (long long)(sizeof(unsigned long long) * (S + kMaxXcc)), 0, b->stream));
+    BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(d_error), sizeof(int), 0, b->stream));
+    ba.scen = d_scen;
     ba.nsteps = nsteps;
-    ba.next = b->d_sync;
-    ba.done = b->d_sync + kMaxXcc;
-    ba.error = b->d_error;
+    ba.next = d_sync;
+    ba.done = d_sync + kMaxXcc;
+    ba.error = d_error;
     ba.spin_limit = 1LL << 26;   // ~ seconds of s_sleep: a wait that long means a broken hand-over
     Event e0, e1;
     if (ms) {
@@ -1996,7 +2050,7 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     BHIP_TRY(b, launch_batch<T>(ba, b->cpt, b->device, b->stream, &b->last_blocks, any_active));
     if (ms) BHIP_TRY(b, hipEventRecord(e1.e, b->stream));
     int error = 0;
-    BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(&error, d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     if (ms) BHIP_TRY(b, hipEventElapsedTime(ms, e0.e, e1.e));
     for (fl_ctx* c : b->members) {
@@ -2015,6 +2069,59 @@ fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     }
     if (error) return bfail(b, FL_EHIP, "fl_batch_run: a wait for a member's previous step timed out");
     return FL_OK;
+}
+
+template <typename T>
+fl_status batch_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
+    const int S = (int)b->members.size();
+    std::vector<BatchScen<T>> scen(S);
+    BatchArgs<T> ba{};
+    batch_plan<T>(b, freeze, batch_xccs(b), scen.data(), ba);
+    const size_t bytes = sizeof(BatchScen<T>) * S;
+    if (bytes > b->scen_bytes) {
+        if (b->d_scen) (void)hipFree(b->d_scen);
+        b->d_scen = nullptr;
+        b->scen_bytes = 0;
+        BHIP_TRY(b, hipMalloc(&b->d_scen, bytes));
+        b->scen_bytes = bytes;
+    }
+    return batch_execute<T>(b, nsteps, freeze, ms, ba, scen.data(), (BatchScen<T>*)b->d_scen,
+                            b->d_sync, b->d_error);
+}
+
+constexpr size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Scratch layout of fl_batch_run_noalloc for S members: descriptors, then the
+// queue heads and completion counters, then the error flag.
+template <typename T>
+constexpr size_t noalloc_bytes(size_t S) {
+    return round256(sizeof(BatchScen<T>) * S) +
+           round256(sizeof(unsigned long long) * (kMaxXcc + S)) + 256;
+}
+static_assert(noalloc_bytes<float>(FL_NOALLOC_MAX_MEMBERS) <= kScratchBytes &&
+                  noalloc_bytes<double>(FL_NOALLOC_MAX_MEMBERS) <= kScratchBytes,
+              "the device scratch must hold the largest batch fl_batch_run_noalloc accepts");
+
+template <typename T>
+fl_status batch_launch_noalloc(fl_batch* b, long long nsteps) {
+    const int S = (int)b->members.size();
+    if (S > FL_NOALLOC_MAX_MEMBERS)
+        return bfail(b, FL_EINVAL, "fl_batch_run_noalloc: the batch has " + std::to_string(S) +
+                                       " members; at most " + std::to_string(FL_NOALLOC_MAX_MEMBERS) +
+                                       " fit the device scratch");
+    unsigned char* base = static_cast<unsigned char*>(scratch_ptr(b->device));
+    if (!base) return bfail(b, FL_EHIP, "fl_batch_run_noalloc: no device scratch address for this device");
+    if (!b->h_stage || b->h_stage_bytes < sizeof(BatchScen<T>) * S)
+        return bfail(b, FL_ESTATE, "fl_batch_run_noalloc: the batch has no host staging");
+    BatchScen<T>* hs = static_cast<BatchScen<T>*>(b->h_stage);
+    BatchArgs<T> ba{};
+    batch_plan<T>(b, 0, batch_xccs(b), hs, ba);
+    BatchScen<T>* d_scen = reinterpret_cast<BatchScen<T>*>(base);
+    unsigned long long* d_sync =
+        reinterpret_cast<unsigned long long*>(base + round256(sizeof(BatchScen<T>) * S));
+    int* d_error = reinterpret_cast<int*>(base + round256(sizeof(BatchScen<T>) * S) +
+                                          round256(sizeof(unsigned long long) * (kMaxXcc + S)));
+    return batch_execute<T>(b, nsteps, 0, nullptr, ba, hs, d_scen, d_sync, d_error);
 }
 
 fl_status batch_run(fl_batch* b, long long nsteps, int freeze, float* ms) {
@@ -2070,12 +2177,16 @@ fl_status fl_batch_create(fl_batch** out, int32_t nmembers, fl_ctx* const* membe
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_sync, sizeof(unsigned long long) * (nmembers + kMaxXcc));
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_error, sizeof(int));
+    // host staging of the descriptors for fl_batch_run_noalloc, sized for either precision
+    b->h_stage_bytes = std::max(sizeof(BatchScen<float>), sizeof(BatchScen<double>)) * nmembers;
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_stage, b->h_stage_bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
         g_create_error = std::string("fl_batch_create: ") + hipGetErrorString(e);
         fl_batch_destroy(b);
         return FL_EHIP;
     }
     b->order.resize(nmembers);
+    b->member_xcd.assign(nmembers, 0);
     for (int k = 0; k < nmembers; ++k) b->order[k] = k;
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         return (long long)members[x]->nx * members[x]->ny > (long long)members[y]->nx * members[y]->ny;
@@ -2100,6 +2211,17 @@ fl_status fl_batch_run(fl_batch* b, int64_t nsteps) {
     if (!b) return FL_EINVAL;
     if (nsteps < 0) return bfail(b, FL_EINVAL, "fl_batch_run: nsteps < 0");
     return batch_run(b, nsteps, 0, nullptr);
+}
+
+fl_status fl_batch_run_noalloc(fl_batch* b, int64_t nsteps) {
+    if (!b) return FL_EINVAL;
+    if (nsteps < 0) return bfail(b, FL_EINVAL, "fl_batch_run_noalloc: nsteps < 0");
+    fl_status st = batch_check_members(b);
+    if (st) return st;
+    if (nsteps == 0) return FL_OK;
+    BHIP_TRY(b, hipSetDevice(b->device));
+    return b->prec == FL_F64 ? batch_launch_noalloc<double>(b, nsteps)
+                             : batch_launch_noalloc<float>(b, nsteps);
 }
 
 fl_status fl_batch_time(fl_batch* b, int64_t nsteps, double* elapsed_ms) {
@@ -2161,6 +2283,7 @@ void fl_batch_destroy(fl_batch* b) {
     if (b->d_scen) (void)hipFree(b->d_scen);
     if (b->d_sync) (void)hipFree(b->d_sync);
     if (b->d_error) (void)hipFree(b->d_error);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
