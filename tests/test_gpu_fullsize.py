@@ -12,6 +12,9 @@ water, so the oracle runs the whole 268 M-cell grid, for 24 steps; and 1000
 steps against the oracle's stored values on a lattice of cells and dense
 blocks (tests/golden/make_d3wet_golden.py).
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
@@ -24,6 +27,7 @@ from synth import WEST, Scenario
 pytestmark = pytest.mark.gpu
 
 N = 16384
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.fixture(scope="module")
@@ -103,6 +107,43 @@ def test_valley16384_prewetted_24_steps_full_grid(d3_dry):
     assert eqx <= 1e-4 and eqy <= 1e-4
     assert r.steps == 24 and abs(r.t / o.clock.t - 1) <= 1e-6
     assert abs(r.v_in / o.clock.v_in - 1) <= 1e-5
+    assert r.budget_error() <= 1e-6
+
+
+def test_valley16384_prewetted_1000_steps_against_oracle_golden(d3_dry):
+    """The headline workload for its stated 1000 steps, in the benchmark's launch
+    configuration, against the oracle's stored depths and face discharges
+    (tests/golden/make_d3wet_golden.py) on a lattice of every 64th cell and four
+    dense 256 x 256 blocks (inflow, mid-valley channel, outflow edge, shoreline)."""
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    from make_d3wet_golden import input_hash
+    g = np.load(os.path.join(HERE, "golden", "d3wet_16384_1000.npz"))
+    wet = _prewetted(d3_dry)
+    assert input_hash(wet) == str(g["input_sha256"]), "the input generator changed"
+    print("CASE fullsize prewetted 1000 steps", flush=True)
+    f = fl.from_scenario(wet, "f32", fusion=2)
+    f.step(1000)
+    h = f.get_depth()
+    qx, qy = f.get_discharge()
+    r = f.get_report()
+    f.close()
+    st, off = (int(v) for v in g["lattice"])
+    B = int(g["block_size"])
+    qmax = float(g["qmax"])
+    lat = (slice(off, None, st), slice(off, None, st))
+    eh = max_abs(h[lat], g["h_lat"])
+    eq = max(max_abs(qx[lat], g["qx_lat"]), max_abs(qy[lat], g["qy_lat"])) / qmax
+    for b, (j, i) in enumerate(g["block_origin"]):
+        eh = max(eh, max_abs(h[j:j + B, i:i + B], g["h_blocks"][b]))
+        eq = max(eq, max_abs(qx[j:j + B, i:i + B + 1], g["qx_blocks"][b]) / qmax,
+                 max_abs(qy[j:j + B + 1, i:i + B], g["qy_blocks"][b]) / qmax)
+    print(f"max|dh| = {eh:.3e} m, max|dq|/max|q| = {eq:.3e}", flush=True)
+    assert (g["h_lat"] > 0.05).sum() > 10000
+    assert eh <= 1e-3
+    assert eq <= 1e-3
+    assert r.steps == int(g["steps"]) and abs(r.t / float(g["t"]) - 1) <= 1e-6
+    assert abs(r.v_in / float(g["v_in"]) - 1) <= 1e-5
+    assert abs(float(h.max()) - float(g["hmax"])) <= 1e-3
     assert r.budget_error() <= 1e-6
 
 
