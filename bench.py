@@ -139,8 +139,10 @@ def cpu_single_thread(sc):
 
 # (cells per lane, rows per work item) tried by the autotuner on small grids
 SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
-# ... and by the batch autotuner on the 64-member ensemble
+# ... and by the batch autotuner on the 64-member ensemble, one step per queue
+# entry and two (the two-step tiling)
 BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32)]
+BATCH2_TILINGS = [(2, 32), (2, 64), (2, 128), (1, 64)]
 
 
 def progress(msg: str):
@@ -180,7 +182,18 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
     b.close()
     for f in ctxs:
         f.close()
-    progress("ensemble: batch done; with active tiles")
+    progress("ensemble: batch done; two steps per queue entry")
+    # the same members from the same start, two steps per queue entry
+    ctx2 = [fl.from_scenario(sc, "f32", stream=stream, fusion=2) for sc in scs]
+    b2 = fl.Batch(ctx2)
+    b2.set_fusion(2)
+    best2, _ = b2.autotune(BATCH2_TILINGS, trial_steps)
+    batch2_ms = b2.time(steps)
+    rep2 = [f.get_report() for f in ctx2]
+    b2.close()
+    for f in ctx2:
+        f.close()
+    progress("ensemble: with active tiles")
     # the same members from the same start with active tiles (tilings autotuned
     # on skipping trial steps): batched, and one after another
     actx = [fl.from_scenario(sc, "f32", stream=stream, active_tiles=True) for sc in scs]
@@ -207,10 +220,19 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
                              "max_budget_error": max(r.budget_error() for r in rep_a)},
             "tiling_autotuned": list(best),
             "batch_gcell_s": round(cells * steps / (batch_ms / 1e3) / 1e9, 3),
+            "two_step_batch": {"tiling_autotuned": list(best2),
+                               "gcell_s": round(cells * steps / (batch2_ms / 1e3) / 1e9, 3),
+                               "vs_one_step_batch": round(batch_ms / batch2_ms, 3),
+                               "vs_sequential": round(seq_ms / batch2_ms, 3),
+                               "hbm_frac_one_pass_per_two_steps": round(
+                                   16 * cells * steps / (batch2_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "max_budget_error": max(r.budget_error() for r in rep2)},
             "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
             "batch_vs_sequential": round(seq_ms / batch_ms, 3),
             "sequential_two_step_gcell_s": round(cells * steps / (seq2_ms / 1e3) / 1e9, 3),
             "batch_vs_best_sequential": round(min(seq_ms, seq2_ms) / batch_ms, 3),
+            "best_batch_gcell_s": round(cells * steps / (min(batch_ms, batch2_ms) / 1e3) / 1e9, 3),
+            "best_batch_vs_best_sequential": round(min(seq_ms, seq2_ms) / min(batch_ms, batch2_ms), 3),
             "batch_hbm_frac": round(32 * cells * steps / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "max_budget_error": max(r.budget_error() for r in rep)}
 

@@ -415,9 +415,25 @@ fl_status fl_batch_create(fl_batch **batch, int32_t nmembers, fl_ctx *const *mem
  * FP64: 1, 2) and rows per work item (>= 1).  Default 4 (FP64 2) and 16. */
 fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t rows_per_item);
 
+/* Steps per queue entry of the batch launch: 1 (default) or 2.  With 2 every
+ * member makes the two-step launches of fl_set_fusion(ctx, 2, ...) (one read
+ * and one write of its state per two steps of Methods, eqs. 3-6; under the CFL
+ * clock the second step's dt is speculated, checked by the member's next
+ * launch and redone if wrong) inside the one persistent launch, so members
+ * wait for their own previous launch half as often; results stay bitwise those
+ * of stepping each member alone.  Every member must have been committed after
+ * fl_set_fusion(ctx, 2, ...) (ESTATE otherwise) and run without active tiles
+ * (EINVAL).  cells_per_lane (1 or 2; 0: 2 in FP32, 1 in FP64) and
+ * rows_per_item (>= 1; 0: 32) are the two-step tiling, which
+ * fl_batch_autotune then tunes.  fl_batch_run_noalloc always runs one step
+ * per entry.  EINVAL: other values. */
+fl_status fl_batch_set_fusion(fl_batch *batch, int32_t steps_per_entry, int32_t cells_per_lane,
+                              int32_t rows_per_item);
+
 /* Time each (cells_per_lane, rows_per_item) pair of candidates[2*ncand] over
  * trial_steps frozen steps (dt = 0: the state is streamed like a real step
- * but left unchanged) and keep the fastest.  Members with active tiles first
+ * but left unchanged) and keep the fastest (the two-step tiling when the batch
+ * runs two steps per entry, fl_batch_set_fusion).  Members with active tiles first
  * take two untimed frozen steps per candidate, so that the timed ones skip
  * as real steps would.  best[2] receives it, *best_ms its time per step.  The
  * members' states and clocks are unchanged. */
@@ -441,7 +457,8 @@ fl_status fl_batch_run(fl_batch *batch, int64_t nsteps);
  * overlap on one GPU (from several threads or streams) race and must not be
  * issued.  Synchronises like fl_batch_run.  EINVAL: nsteps < 0, or more than
  * FL_NOALLOC_MAX_MEMBERS members; ESTATE: a member not committed; EHIP as
- * fl_batch_run. */
+ * fl_batch_run.  Always one step per queue entry (fl_batch_set_fusion does not
+ * apply; the results are the same bits). */
 #define FL_NOALLOC_MAX_MEMBERS 256
 fl_status fl_batch_run_noalloc(fl_batch *batch, int64_t nsteps);
 

@@ -38,6 +38,7 @@ EXPORTS = [
     "fl_adj_setup", "fl_adj_forward", "fl_adj_backward", "fl_autotune", "fl_set_fusion",
     "fl_workspace_bytes", "fl_bind_workspace", "fl_get_state", "fl_autotune_fusion",
     "fl_set_active_tiles", "fl_active_items", "fl_set_variant", "fl_batch_run_noalloc",
+    "fl_batch_set_fusion",
 ]
 
 
@@ -133,6 +134,7 @@ def lib() -> C.CDLL:
                                             C.POINTER(dbl)]),
             "fl_batch_run": (C.c_int, [vp, i64]),
             "fl_batch_run_noalloc": (C.c_int, [vp, i64]),
+            "fl_batch_set_fusion": (C.c_int, [vp, i32, i32, i32]),
             "fl_batch_time": (C.c_int, [vp, i64, C.POINTER(dbl)]),
             "fl_batch_last_error": (C.c_char_p, [vp]),
             "fl_batch_destroy": (None, [vp]),
@@ -525,6 +527,12 @@ class Batch:
     def set_tiling(self, cells_per_lane: int, rows_per_item: int):
         self._live()
         self._check(lib().fl_batch_set_tiling(self.b, cells_per_lane, rows_per_item))
+
+    def set_fusion(self, steps_per_entry: int, cells_per_lane: int = 0, rows_per_item: int = 0):
+        """fl_batch_set_fusion: one or two steps per queue entry (two needs
+        members committed with fusion=2 and without active tiles)."""
+        self._live()
+        self._check(lib().fl_batch_set_fusion(self.b, steps_per_entry, cells_per_lane, rows_per_item))
 
     def autotune(self, candidates, trial_steps: int = 20):
         self._live()

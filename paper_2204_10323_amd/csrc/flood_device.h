@@ -119,41 +119,51 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Row accesses through pointers typed in the global address space.  Every
+// field of the library is device memory.  Pointers a kernel reads from memory
+// (a batch's member descriptors) rather than from its arguments would
+// otherwise compile to flat accesses, which cannot take a scalar base address
+// and are counted with the LDS and scalar-memory operations.
+template <typename T>
+struct Global { typedef __attribute__((address_space(1))) T type; };
+template <typename T>
+__device__ __forceinline__ typename Global<T>::type* as_global(T* p) {
+    return (typename Global<T>::type*)p;
+}
+
 // Element at byte offset boff (32-bit, per lane) from a row start that is the
 // same in every lane: the form the scalar-base + 32-bit-offset memory
 // instructions take, with no per-lane 64-bit address arithmetic.
-template <typename T>
-__device__ __forceinline__ T* at_byte(T* row, unsigned boff) {
-    return reinterpret_cast<T*>(reinterpret_cast<char*>(row) + boff);
-}
-template <typename T>
-__device__ __forceinline__ const T* at_byte(const T* row, unsigned boff) {
-    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
+template <typename P>
+__device__ __forceinline__ P* at_byte(P* row, unsigned boff) {
+    typedef typename Global<char>::type gchar;
+    gchar* b = const_cast<gchar*>(reinterpret_cast<const gchar*>(row));
+    return reinterpret_cast<P*>(b + boff);
 }
 
-template <typename T, int N>
-struct alignas(sizeof(T) * N) VecT { T v[N]; };
-
-template <typename T, int N>
-__device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
-    VecT<T, N> t = *reinterpret_cast<const VecT<T, N>*>(p);
-#pragma unroll
-    for (int m = 0; m < N; ++m) o[m] = t.v[m];
-}
-// Vector store of the new state.  NT = true marks it non-temporal: the new
-// state is not read again within the launch, so it should not displace the
-// halo rows and columns other waves still read.  Kernels that hand data to
-// other waves inside one launch (the persistent batch) store normally, so the
-// data is resident in L2 when the wave's memory counter drains.
+// Vector load of a row segment (N consecutive elements) and vector store of the
+// new state.  NT = true marks the store non-temporal: the new state is not
+// read again within the launch, so it should not displace the halo rows and
+// columns other waves still read.  Kernels that hand data to other waves
+// inside one launch (the persistent batch) store normally, so the data is
+// resident in L2 when the wave's memory counter drains.
 template <typename T, int N>
 struct NVec { typedef T type __attribute__((ext_vector_type(N))); };
+template <typename T, int N>
+__device__ __forceinline__ void ldv(const typename Global<T>::type* p, T (&o)[N]) {
+    typedef const typename Global<typename NVec<T, N>::type>::type V;
+    const typename NVec<T, N>::type t = *reinterpret_cast<V*>(p);
+#pragma unroll
+    for (int m = 0; m < N; ++m) o[m] = t[m];
+}
 template <typename T, int N, bool NT>
-__device__ __forceinline__ void stv(T* p, const T (&o)[N]) {
+__device__ __forceinline__ void stv(typename Global<T>::type* p, const T (&o)[N]) {
     typename NVec<T, N>::type t;
 #pragma unroll
     for (int m = 0; m < N; ++m) t[m] = o[m];
-    if (NT) __builtin_nontemporal_store(t, reinterpret_cast<typename NVec<T, N>::type*>(p));
-    else *reinterpret_cast<typename NVec<T, N>::type*>(p) = t;
+    typedef typename Global<typename NVec<T, N>::type>::type V;
+    if (NT) __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
+    else *reinterpret_cast<V*>(p) = t;
 }
 
 // ------------------------------------------------------------ the physics

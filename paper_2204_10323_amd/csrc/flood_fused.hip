@@ -251,11 +251,11 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     auto load_row = [&](int k) {
         if (loads && k >= -kHalo && k < ny + kHalo) {
             const long long o = (long long)(k + kHalo) * P;
-            ldv<T, CPT>(at_byte(h_in + o, boff), hN);
-            ldv<T, CPT>(at_byte(a.z + o, boff), zN);
-            ldv<T, CPT>(at_byte(a.n + o, boff), nN);
-            ldv<T, CPT>(at_byte(qx_in + o, boff), qxN);
-            ldv<T, CPT>(at_byte(qy_in + o, boff), qyN);
+            ldv<T, CPT>(at_byte(as_global(h_in) + o, boff), hN);
+            ldv<T, CPT>(at_byte(as_global(a.z) + o, boff), zN);
+            ldv<T, CPT>(at_byte(as_global(a.n) + o, boff), nN);
+            ldv<T, CPT>(at_byte(as_global(qx_in) + o, boff), qxN);
+            ldv<T, CPT>(at_byte(as_global(qy_in) + o, boff), qyN);
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
@@ -280,9 +280,9 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     };
     auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
         const long long o = (long long)(r + kHalo) * P;
-        T* const ho = h_out + o;
-        T* const qxr = qx_out + o;
-        T* const qyr = qy_out + o;
+        auto* const ho = as_global(h_out) + o;
+        auto* const qxr = as_global(qx_out) + o;
+        auto* const qyr = as_global(qy_out) + o;
         if (all_store) {
             stv<T, CPT, true>(at_byte(ho, boff), hv);
             stv<T, CPT, true>(at_byte(qxr, boff), qxv);
@@ -519,6 +519,73 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CPT == 2) ? 3 : 1) void k_s
     tile2_item<T, CPT, ACT>(A, P, wave);
 }
 
+// Persistent batch with two steps per queue entry: the two-step launches of
+// many members in one launch.  Per XCD the queue holds, launch after launch,
+// for each member its clock entry and its two-step work items; an entry of a
+// member's launch l waits only until that member's launch l - 1 is complete.
+// Every entry derives the launch's plan from the member's device clock, as the
+// waves of a two-step launch do, so each member makes exactly the launches
+// (steps, speculated second steps, redos) of its own two-step run, and its
+// state is bitwise that of stepping it alone.  Queue, hand-over between
+// launches and progress argument as in k_batch (flood_kernels.hip): an entry
+// waits only for entries of lower queue index, which running waves took
+// before it.
+// (FP32: two waves per SIMD; with three the queue's state spills the row
+// pointers of the marchers to scratch)
+template <typename T, int CPT>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_batch2(
+    Batch2Args<T> B, const BatchScen2<T>* __restrict__ scen) {
+    // scen is not written during the launch: its loads may be repeated instead of held
+    const int lane = threadIdx.x & 63;
+    const int x = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15);  // XCC_ID
+    if (x >= B.nxcc) return;
+    const int m_lo = B.xbegin[x], m_hi = B.xbegin[x + 1];
+    if (m_lo >= m_hi) return;
+    const int per = B.per_launch[x];
+    const unsigned long long total = (unsigned long long)per * (unsigned long long)B.nlaunch;
+    for (;;) {
+        unsigned long long q = 0;
+        if (lane == 0) q = atomicAdd(&B.next[x], 1ull);
+        q = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(q >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((unsigned)q);
+        if (q >= total) break;
+        const long long l = (long long)(q / (unsigned long long)per);
+        const int r = (int)(q - (unsigned long long)l * per);
+        int lo = m_lo, hi = m_hi - 1;      // member with first <= r, largest such
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (scen[mid].first <= r) lo = mid; else hi = mid - 1;
+        }
+        const int m = lo;
+        const BatchScen2<T>& S = scen[m];
+        const int e = r - S.first;
+        if (l > 0) {
+            const unsigned long long need = (unsigned long long)l * (unsigned long long)(S.items + 1);
+            int ok = 1;
+            if (lane == 0) {
+                long long spins = 0;
+                while (__hip_atomic_load(&B.done[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > B.spin_limit) { ok = 0; break; }
+                }
+            }
+            ok = __builtin_amdgcn_readfirstlane(ok);
+            if (!ok) {
+                if (lane == 0) atomicExch(B.error, 1);
+                break;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        const Step2Args<T>& A = S.a2[l == B.nlaunch - 1 ? 1 : 0][(int)((B.l0 + l) % 6)];
+        const Plan2 P = make_plan<T>(A);
+        if (e == 0) clock2_wave<T>(A, P);
+        else if (P.mode != 0) tile2_item<T, CPT, false>(A, P, e - 1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __asm__ volatile("" ::: "memory");
+        if (lane == 0) atomicAdd(&B.done[m], 1ull);
+    }
+}
+
 template <typename T>
 __global__ void k_enter2(StepArgs<T> a, int cur, long long target, int keep_gen) {
     if (threadIdx.x != 0) return;
@@ -612,6 +679,31 @@ hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long
     return hipGetLastError();
 }
 
+template <typename T, int CPT>
+static hipError_t launch_batch2_cpt(const Batch2Args<T>& b, int device, hipStream_t s, int* blocks_out) {
+    int per_cu = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch2<T, CPT>, 256, 0);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    const int blocks = std::max(1, per_cu) * ncu;
+    if (blocks_out) *blocks_out = blocks;
+    // an ordinary launch: the queue needs no co-residency (see k_batch2)
+    hipLaunchKernelGGL((k_batch2<T, CPT>), dim3(blocks), dim3(256), 0, s, b, b.scen);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int device, hipStream_t s, int* blocks_out) {
+    switch (cpt) {
+    case 1: return launch_batch2_cpt<T, 1>(b, device, s, blocks_out);
+    case 2: return launch_batch2_cpt<T, 2>(b, device, s, blocks_out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_batch2<float>(const Batch2Args<float>&, int, int, hipStream_t, int*);
+template hipError_t launch_batch2<double>(const Batch2Args<double>&, int, int, hipStream_t, int*);
 template hipError_t launch_step2<float>(const Step2Args<float>&, int, hipStream_t);
 template hipError_t launch_step2<double>(const Step2Args<double>&, int, hipStream_t);
 template hipError_t launch_enter2<float>(const StepArgs<float>&, long long, int, hipStream_t);

@@ -148,6 +148,32 @@ struct BatchArgs {
     long long spin_limit;
 };
 
+// A member of a batch run with two steps per queue entry: its two-step
+// launch arguments by settling flag and launch counter modulo 6, and its work.
+template <typename T>
+struct BatchScen2 {
+    Step2Args<T> a2[2][6];  // [resolve][launch counter % 6]
+    int items;              // two-step work items per launch
+    int first;              // offset of this member's (1 + items) entries within a launch
+};
+
+// A two-step batch run: every member makes `nlaunch` two-step launches with
+// counters l0 .. l0 + nlaunch - 1, the last of which only settles (checks, and
+// if needed redoes, the previous launch's speculated step).  Queue layout and
+// hand-over as in BatchArgs.
+template <typename T>
+struct Batch2Args {
+    const BatchScen2<T>* scen;
+    int nxcc;
+    int xbegin[kMaxXcc + 1];
+    int per_launch[kMaxXcc];      // per XCD: sum over its members of (1 + items)
+    long long l0, nlaunch;
+    unsigned long long* next;
+    unsigned long long* done;
+    int* error;
+    long long spin_limit;
+};
+
 // Reverse of one fixed-dt step (flood_adjoint.hip).
 template <typename T>
 struct AdjArgs {
@@ -234,6 +260,9 @@ hipError_t launch_enter2(const StepArgs<T>& single, long long target, int keep_g
 template <typename T>
 hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long long launches,
                          hipStream_t s);
+// A persistent batch launch with two steps per queue entry (flood_fused.hip).
+template <typename T>
+hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int device, hipStream_t s, int* blocks_out);
 
 int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
 int strip_width2(int cpt);  // the same for the two-step kernel

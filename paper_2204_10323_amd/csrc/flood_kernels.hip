@@ -99,11 +99,11 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
     auto load_row = [&](int k) {
         if (loads) {
             const long long o = (long long)(k + kHalo) * P;
-            ldv<T, CPT>(at_byte(a.h_in + o, boff), hN);
-            ldv<T, CPT>(at_byte(a.z + o, boff), zN);
-            ldv<T, CPT>(at_byte(a.n + o, boff), nN);
-            ldv<T, CPT>(at_byte(a.qx_in + o, boff), qxN);
-            ldv<T, CPT>(at_byte(a.qy_in + o, boff), qyN);
+            ldv<T, CPT>(at_byte(as_global(a.h_in) + o, boff), hN);
+            ldv<T, CPT>(at_byte(as_global(a.z) + o, boff), zN);
+            ldv<T, CPT>(at_byte(as_global(a.n) + o, boff), nN);
+            ldv<T, CPT>(at_byte(as_global(a.qx_in) + o, boff), qxN);
+            ldv<T, CPT>(at_byte(as_global(a.qy_in) + o, boff), qyN);
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
@@ -111,9 +111,9 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
     };
 
     auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
-        T* const ho = a.h_out + (long long)(r + kHalo) * P;
-        T* const qxr = a.qx_out + (long long)(r + kHalo) * P;
-        T* const qyr = a.qy_out + (long long)(r + kHalo) * P;
+        auto* const ho = as_global(a.h_out) + (long long)(r + kHalo) * P;
+        auto* const qxr = as_global(a.qx_out) + (long long)(r + kHalo) * P;
+        auto* const qyr = as_global(a.qy_out) + (long long)(r + kHalo) * P;
         if (all_store) {
             stv<T, CPT, NTS>(at_byte(ho, boff), hv);
             stv<T, CPT, NTS>(at_byte(qxr, boff), qxv);

@@ -407,6 +407,24 @@ Tiling tiling2_of(const fl_ctx* c, int cpt, int rows) {
     return t;
 }
 
+// Two-step launch arguments with two-step tiling tl (no active tiles).
+template <typename T>
+Step2Args<T> make_args2_tl(const fl_ctx* c, long long launch, int resolve, const Tiling& tl,
+                           int freeze) {
+    Step2Args<T> A{};
+    A.a = make_args<T>(c, 0, tl, freeze);
+    for (int p = 0; p < 2; ++p) {
+        A.h[p] = (T*)c->d_h[p];
+        A.qx[p] = (T*)c->d_qx[p];
+        A.qy[p] = (T*)c->d_qy[p];
+        A.part_a[p] = c->d_part2[p];
+        A.part_b[p] = c->d_part2[2 + p];
+    }
+    A.phase = (int)(launch % 6);
+    A.resolve = resolve;
+    return A;
+}
+
 template <typename T>
 Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve, int freeze = 0) {
     Step2Args<T> A{};
@@ -1925,6 +1943,9 @@ struct fl_batch {
     unsigned long long* d_sync = nullptr;   // [0] queue head, [1..] per-member done counts
     int* d_error = nullptr;
     int last_blocks = 0;
+    int fuse = 1, cpt2 = 0, rows2 = 0;   // steps per queue entry and the two-step tiling
+    void* d_scen2 = nullptr;
+    size_t scen2_bytes = 0;
     std::vector<int> member_xcd;    // XCD each member runs on (planning scratch, sized at create)
     void* h_stage = nullptr;        // pinned host staging of the descriptors (fl_batch_run_noalloc)
     size_t h_stage_bytes = 0;
@@ -2124,6 +2145,135 @@ fl_status batch_launch_noalloc(fl_batch* b, long long nsteps) {
     return batch_execute<T>(b, nsteps, 0, nullptr, ba, hs, d_scen, d_sync, d_error);
 }
 
+// Can the members run two steps per queue entry?  They need the two-step
+// buffers (committed after fl_set_fusion(ctx, 2, ...)) and no active tiles.
+fl_status batch_check_two_step(fl_batch* b) {
+    for (fl_ctx* c : b->members) {
+        if (!c->d_part2[0])
+            return bfail(b, FL_ESTATE, "two steps per queue entry: every member must be committed "
+                                       "after fl_set_fusion(ctx, 2, ...)");
+        if (c->active)
+            return bfail(b, FL_EINVAL, "two steps per queue entry: members with active tiles run "
+                                       "one step per entry");
+    }
+    return FL_OK;
+}
+
+// nsteps steps of every member with two steps per queue entry: the members'
+// single-step state (budget folded) becomes their two-step clock, as in
+// fused_steps_t; a round of batched two-step launches (about nsteps/2 plus one
+// that settles) follows, further rounds only if redos or one-step launches
+// left a member short; finally every member's state becomes its single-step
+// state again.
+template <typename T>
+fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
+    fl_status st = batch_check_two_step(b);
+    if (st) return st;
+    const int S = (int)b->members.size();
+    for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    for (fl_ctx* c : b->members) {
+        Tiling own{c->cpt, c->rows, c->nstrips, c->nchunks, c->npart};
+        if (fold_budget(c, own)) return bfail(b, FL_EHIP, c->err);
+    }
+    for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    for (fl_ctx* c : b->members)
+        BHIP_TRY(b, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, 0, b->stream));
+    // bin-pack onto the XCDs as the one-step batch does
+    const int nxcc = batch_xccs(b);
+    long long load[kMaxXcc] = {};
+    for (int k = 0; k < S; ++k) {
+        const int m = b->order[k];
+        int x = 0;
+        for (int y = 1; y < nxcc; ++y)
+            if (load[y] < load[x]) x = y;
+        b->member_xcd[m] = x;
+        load[x] += (long long)b->members[m]->nx * b->members[m]->ny;
+    }
+    std::vector<BatchScen2<T>> scen(S);
+    Batch2Args<T> ba{};
+    ba.nxcc = nxcc;
+    int idx = 0;
+    for (int x = 0; x < nxcc; ++x) {
+        ba.xbegin[x] = idx;
+        int first = 0;
+        for (int k = 0; k < S; ++k) {
+            const int m = b->order[k];
+            if (b->member_xcd[m] != x) continue;
+            fl_ctx* c = b->members[m];
+            const Tiling tl = tiling2_of(c, b->cpt2, b->rows2);
+            for (int res = 0; res < 2; ++res)
+                for (int ph = 0; ph < 6; ++ph) scen[idx].a2[res][ph] = make_args2_tl<T>(c, ph, res, tl, freeze);
+            scen[idx].items = tl.nstrips * tl.nchunks;
+            scen[idx].first = first;
+            first += 1 + scen[idx].items;
+            ++idx;
+        }
+        ba.per_launch[x] = first;
+    }
+    ba.xbegin[nxcc] = idx;
+    const size_t bytes = sizeof(BatchScen2<T>) * S;
+    if (bytes > b->scen2_bytes) {
+        if (b->d_scen2) (void)hipFree(b->d_scen2);
+        b->d_scen2 = nullptr;
+        b->scen2_bytes = 0;
+        BHIP_TRY(b, hipMalloc(&b->d_scen2, bytes));
+        b->scen2_bytes = bytes;
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->d_scen2, scen.data(), bytes, hipMemcpyHostToDevice, b->stream));
+    ba.scen = (const BatchScen2<T>*)b->d_scen2;
+    ba.next = b->d_sync;
+    ba.done = b->d_sync + kMaxXcc;
+    ba.error = b->d_error;
+    ba.spin_limit = 1LL << 26;
+    Event e0, e1;
+    if (ms) {
+        BHIP_TRY(b, hipEventCreate(&e0.e));
+        BHIP_TRY(b, hipEventCreate(&e1.e));
+        BHIP_TRY(b, hipEventRecord(e0.e, b->stream));
+    }
+    std::vector<Clock2> slot(S);
+    long long lc = 0, want = (nsteps + 1) / 2;
+    for (int round = 0;; ++round) {
+        BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(b->d_sync),
+                                      (long long)(sizeof(unsigned long long) * (S + kMaxXcc)), 0,
+                                      b->stream));
+        BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(b->d_error), sizeof(int), 0,
+                                      b->stream));
+        ba.l0 = lc;
+        ba.nlaunch = want + 1;   // the last launch only settles
+        BHIP_TRY(b, launch_batch2<T>(ba, b->cpt2, b->device, b->stream, &b->last_blocks));
+        lc += want + 1;
+        if (ms) BHIP_TRY(b, hipEventRecord(e1.e, b->stream));
+        int error = 0;
+        BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        for (int m = 0; m < S; ++m)
+            BHIP_TRY(b, hipMemcpyAsync(&slot[m], &b->members[m]->d_ctl->c2[lc & 1], sizeof(Clock2),
+                                       hipMemcpyDeviceToHost, b->stream));
+        BHIP_TRY(b, hipStreamSynchronize(b->stream));
+        if (error) return bfail(b, FL_EHIP, "fl_batch_run: a wait for a member's previous launch timed out");
+        long long short_by = 0;
+        for (int m = 0; m < S; ++m) {
+            if (slot[m].pending) return bfail(b, FL_EHIP, "two-step batch: unsettled member state");
+            short_by = std::max(short_by, nsteps - slot[m].vsteps);
+        }
+        if (short_by <= 0) break;
+        if (round >= 64) return bfail(b, FL_EHIP, "two-step batch: no progress");
+        want = short_by;   // enough even if every launch makes one step
+    }
+    if (ms) BHIP_TRY(b, hipEventElapsedTime(ms, e0.e, e1.e));
+    for (int m = 0; m < S; ++m) {
+        fl_ctx* c = b->members[m];
+        const Tiling tl = tiling2_of(c, b->cpt2, b->rows2);
+        long long n2 = c->nstep + nsteps;
+        n2 += (n2 ^ (long long)slot[m].cur) & 1;
+        BHIP_TRY(b, launch_leave2<T>(make_args<T>(c, n2), make_args2_tl<T>(c, 0, 0, tl, 0), lc,
+                                     b->stream));
+        c->nstep = n2;
+    }
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    return FL_OK;
+}
+
 fl_status batch_run(fl_batch* b, long long nsteps, int freeze, float* ms) {
     fl_status st = batch_check_members(b);
     if (st) return st;
@@ -2132,6 +2282,9 @@ fl_status batch_run(fl_batch* b, long long nsteps, int freeze, float* ms) {
         return FL_OK;
     }
     BHIP_TRY(b, hipSetDevice(b->device));
+    if (b->fuse == 2 && nsteps >= 2)
+        return b->prec == FL_F64 ? batch2_launch<double>(b, nsteps, freeze, ms)
+                                 : batch2_launch<float>(b, nsteps, freeze, ms);
     return b->prec == FL_F64 ? batch_launch<double>(b, nsteps, freeze, ms)
                              : batch_launch<float>(b, nsteps, freeze, ms);
 }
@@ -2207,6 +2360,24 @@ fl_status fl_batch_set_tiling(fl_batch* b, int32_t cells_per_lane, int32_t rows_
     return FL_OK;
 }
 
+fl_status fl_batch_set_fusion(fl_batch* b, int32_t steps_per_entry, int32_t cells_per_lane,
+                              int32_t rows_per_item) {
+    if (!b) return FL_EINVAL;
+    if (steps_per_entry != 1 && steps_per_entry != 2)
+        return bfail(b, FL_EINVAL, "fl_batch_set_fusion: steps_per_entry must be 1 or 2");
+    if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2)
+        return bfail(b, FL_EINVAL, "fl_batch_set_fusion: cells_per_lane must be 0, 1 or 2");
+    if (rows_per_item < 0) return bfail(b, FL_EINVAL, "fl_batch_set_fusion: rows_per_item < 0");
+    if (steps_per_entry == 2) {
+        fl_status st = batch_check_two_step(b);
+        if (st) return st;
+    }
+    b->fuse = steps_per_entry;
+    b->cpt2 = cells_per_lane ? cells_per_lane : (b->prec == FL_F64 ? 1 : 2);
+    b->rows2 = rows_per_item ? rows_per_item : 32;
+    return FL_OK;
+}
+
 fl_status fl_batch_run(fl_batch* b, int64_t nsteps) {
     if (!b) return FL_EINVAL;
     if (nsteps < 0) return bfail(b, FL_EINVAL, "fl_batch_run: nsteps < 0");
@@ -2236,14 +2407,20 @@ fl_status fl_batch_time(fl_batch* b, int64_t nsteps, double* elapsed_ms) {
 fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncand, int32_t trial_steps,
                             int32_t* best, double* best_ms) {
     if (!b || !candidates || ncand < 1 || trial_steps < 1) return FL_EINVAL;
-    const int cpt0 = b->cpt, rows0 = b->rows;
+    const bool two = b->fuse == 2;
+    int& cpt_ref = two ? b->cpt2 : b->cpt;
+    int& rows_ref = two ? b->rows2 : b->rows;
+    const int cpt0 = cpt_ref, rows0 = rows_ref;
     double best_t = 1e300;
     int bc = -1;
     for (int k = 0; k < ncand; ++k) {
-        fl_status st = fl_batch_set_tiling(b, candidates[2 * k], candidates[2 * k + 1]);
+        fl_status st = two ? fl_batch_set_fusion(b, 2, candidates[2 * k], candidates[2 * k + 1])
+                           : fl_batch_set_tiling(b, candidates[2 * k], candidates[2 * k + 1]);
+        if (!st && two && candidates[2 * k] == 0)
+            st = bfail(b, FL_EINVAL, "fl_batch_autotune: cells_per_lane must be 1 or 2");
         if (st) {
-            b->cpt = cpt0;
-            b->rows = rows0;
+            cpt_ref = cpt0;
+            rows_ref = rows0;
             return st;
         }
         float ms = 0.f;
@@ -2255,8 +2432,8 @@ fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncan
         if (any_active) st = batch_run(b, 2, 1, nullptr);
         if (!st) st = batch_run(b, trial_steps, 1, &ms);
         if (st) {
-            b->cpt = cpt0;
-            b->rows = rows0;
+            cpt_ref = cpt0;
+            rows_ref = rows0;
             return st;
         }
         if (ms < best_t) {
@@ -2264,11 +2441,11 @@ fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncan
             bc = k;
         }
     }
-    b->cpt = candidates[2 * bc];
-    b->rows = candidates[2 * bc + 1];
+    cpt_ref = candidates[2 * bc];
+    rows_ref = candidates[2 * bc + 1];
     if (best) {
-        best[0] = b->cpt;
-        best[1] = b->rows;
+        best[0] = cpt_ref;
+        best[1] = rows_ref;
     }
     if (best_ms) *best_ms = best_t / trial_steps;
     return FL_OK;
@@ -2281,6 +2458,7 @@ void fl_batch_destroy(fl_batch* b) {
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->d_scen) (void)hipFree(b->d_scen);
+    if (b->d_scen2) (void)hipFree(b->d_scen2);
     if (b->d_sync) (void)hipFree(b->d_sync);
     if (b->d_error) (void)hipFree(b->d_error);
     if (b->h_stage) (void)hipHostFree(b->h_stage);

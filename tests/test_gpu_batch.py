@@ -153,3 +153,99 @@ def test_batch_create_errors():
     b2.close()
     for x in (f, g, u):
         x.close()
+
+
+# ---------------------------------------------------------------- two steps per entry
+def _same2(a, b, what=""):
+    """State, clock and inflow volume bit for bit; the outflow volume is summed
+    over another work decomposition, so it agrees to FP64 rounding."""
+    for x, y, nm in zip(a[:3], b[:3], ("h", "qx", "qy")):
+        assert np.array_equal(x, y), f"{what}: {nm} differs"
+    ra, rb = a[3], b[3]
+    assert ra.steps == rb.steps and ra.t == rb.t and ra.last_dt == rb.last_dt, what
+    assert ra.v_in == rb.v_in, what
+    assert abs(ra.v_out - rb.v_out) <= 1e-13 * max(1.0, abs(rb.v_out)), what
+
+
+def _basin():
+    """A basin filled from the west whose CFL bound becomes active during the
+    run: speculated second steps are redone, then launches make one step."""
+    nx, ny = 96, 64
+    z = np.fromfunction(lambda j, i: 0.002 * (nx - i) + 0.01 * np.sin(j / 5.0),
+                        (ny, nx)).astype(np.float32)
+    n = np.full((ny, nx), 0.03, np.float32)
+    return Scenario("basin", nx, ny, 1.0, z, n, np.zeros_like(z),
+                    (WEST, 20, 8, 1e-3, np.array([0.0, 50.0, 100.0]), np.array([400.0, 400.0, 0.0])),
+                    (EAST, 0, ny, 1e-3), dt_max=1.0)
+
+
+@pytest.mark.parametrize("prec,tiling", [("f32", (2, 32)), ("f32", (1, 8)), ("f32", (2, 5)),
+                                         ("f64", (1, 16)), ("f64", (2, 7))])
+def test_two_step_batch_members_equal_single_runs(prec, tiling):
+    """Two steps per queue entry: each member ends as the same scenario stepped
+    alone one step per launch (odd step counts, a member whose CFL bound
+    becomes active, every side pair)."""
+    scs = _scenarios() + [_basin()]
+    chunks = [151, 150]
+    ref = []
+    for sc in scs:
+        f = fl.from_scenario(sc, prec)
+        for n in chunks:
+            f.step(n)
+        ref.append(_state(f))
+        f.close()
+    members = [fl.from_scenario(sc, prec, fusion=2) for sc in scs]
+    b = fl.Batch(members)
+    b.set_fusion(2, *tiling)
+    print("CASE two-step batch", prec, tiling, flush=True)
+    for n in chunks:
+        b.run(n)
+    b.close()
+    for sc, f, r0 in zip(scs, members, ref):
+        _same2(_state(f), r0, sc.name)
+        f.close()
+    assert ref[-1][3].last_dt < 1.0   # the basin's bound became active
+
+
+def test_two_step_batch_autotune_and_interleaving():
+    """The two-step batch autotuner leaves states untouched; batched two-step
+    runs, one-step batch runs and the members' own steps interleave."""
+    scs = _scenarios()
+    ref = [run_gpu(sc, 260, "f32") for sc in scs]
+    members = [fl.from_scenario(sc, "f32", fusion=2) for sc in scs]
+    b = fl.Batch(members)
+    b.set_fusion(2)
+    best, _ = b.autotune([(2, 32), (1, 16), (2, 8)], 6)
+    assert best in [(2, 32), (1, 16), (2, 8)]
+    b.run(100)
+    for f in members:
+        f.step(21)
+    b.set_fusion(1)
+    b.run(39)
+    b.set_fusion(2, *best)
+    b.run(100)
+    b.close()
+    for sc, f, (h0, qx0, qy0, r0) in zip(scs, members, ref):
+        h, qx, qy, r = _state(f)
+        _same2((h, qx, qy, r), (h0, qx0, qy0, r0), sc.name)
+        f.close()
+
+
+def test_two_step_batch_refusals():
+    scs = _scenarios()[:2]
+    plain = [fl.from_scenario(sc, "f32") for sc in scs]
+    b = fl.Batch(plain)
+    with pytest.raises(fl.FloodError) as e:
+        b.set_fusion(2)
+    assert e.value.status == fl.FL_ESTATE
+    with pytest.raises(fl.FloodError):
+        b.set_fusion(3)
+    b.close()
+    act = [fl.from_scenario(sc, "f32", fusion=2, active_tiles=True) for sc in scs]
+    b = fl.Batch(act)
+    with pytest.raises(fl.FloodError) as e:
+        b.set_fusion(2)
+    assert e.value.status == fl.FL_EINVAL
+    b.close()
+    for f in plain + act:
+        f.close()
