@@ -59,6 +59,43 @@ __device__ __forceinline__ FaceFwd<T> face_fwd(T hL, T hR, T zL, T zR, T nL, T n
     return f;
 }
 
+// FP32: the same derivatives from h_f^(-7/3) and 1/den as the forward face
+// update computes them (hardware log2/exp2/reciprocal, about one ulp each), so
+// q* has exactly the forward's bits and no cube root or division remains.
+template <>
+__device__ __forceinline__ FaceFwd<float> face_fwd<float>(float hL, float hR, float zL, float zR,
+                                                          float nL, float nR, float q, float gdt,
+                                                          float inv_dx, float h_eps) {
+    FaceFwd<float> f;
+    f.qs = f.Pq = f.PL = f.PR = f.Pn = 0.0f;
+    const float etaL = hL + zL, etaR = hR + zR;
+    const float hf = fmaxf(etaL, etaR) - fmaxf(zL, zR);
+    if (hf <= h_eps) return f;
+    // the forward value, operation for operation (face_q<float>)
+    const float nf = 0.5f * (nL + nR);
+    const float grad = (etaR - etaL) * inv_dx;
+    const float num = q - (gdt * hf) * grad;
+    const float m73 = fminf(__builtin_amdgcn_exp2f((-7.0f / 3.0f) * __builtin_amdgcn_logf(hf)), 3.0e38f);
+    const float fr = gdt * (nf * nf);
+    const float aq = fabsf(q);
+    const float den = 1.0f + (fr * aq) * m73;
+    const float rden = __builtin_amdgcn_rcpf(den);
+    f.qs = num * rden;
+    // its derivatives
+    const float sq = (float)((q > 0.0f) - (q < 0.0f));
+    const float dden_dq = (fr * sq) * m73;
+    const float dden_dhf = ((-(7.0f / 3.0f) * fr) * aq) * (m73 * __builtin_amdgcn_rcpf(hf));
+    const float dden_dnf = ((2.0f * gdt) * nf * aq) * m73;
+    const float dqs_dhf = (-gdt * grad - f.qs * dden_dhf) * rden;
+    const float dqs_dgrad = (-gdt * hf) * rden;
+    f.Pq = (1.0f - f.qs * dden_dq) * rden;
+    f.Pn = -(f.qs * dden_dnf) * rden;
+    const float tieL = (etaL >= etaR) ? 1.0f : 0.0f;
+    f.PL = dqs_dhf * tieL - dqs_dgrad * inv_dx;
+    f.PR = dqs_dhf * (1.0f - tieL) + dqs_dgrad * inv_dx;
+    return f;
+}
+
 enum { F_INT = 0, F_WALL = 1, F_IN = 2, F_OUT = 3 };
 
 // Kind of the border face of cell (i, j) on `side` (the cell is on that edge).

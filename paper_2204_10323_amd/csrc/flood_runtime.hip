@@ -143,6 +143,7 @@ struct fl_ctx {
     DevCtl* d_ck_ctl = nullptr;          // [nck]
     void* d_ck_qin = nullptr;            // [nck][side length]
     void* d_end = nullptr;               // the end-of-forward clock, inflow, partials, edges
+    void* d_bwd = nullptr;               // scratch of the backward sweep (stores, adjoints, gradients)
     long long adj_n0 = 0, adj_nsteps = 0, adj_C = 0, adj_nck = 0, adj_nobs = 0;
     double adj_t0 = 0.0;
 };
@@ -229,7 +230,7 @@ void free_adjoint(fl_ctx* c) {
     c->adj_allocs.clear();
     c->d_gauges = c->d_gcell = nullptr;
     c->ngcell = 0;
-    c->d_obs = c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
+    c->d_obs = c->d_series = c->d_ck = c->d_ck_qin = c->d_end = c->d_bwd = nullptr;
     c->d_ck_ctl = nullptr;
     c->adj_setup = false;
     c->adj_nsteps = 0;
@@ -1598,43 +1599,82 @@ fl_status snapshot_end(fl_ctx* c, bool restore) {
     return FL_OK;
 }
 
+// The backward sweep.  Segments are reversed from the last to the first.  A
+// segment's states are recomputed from its checkpoint into one of two state
+// stores by the step kernel on the context's stream, while the previous
+// segment (one store) is reversed on a second stream: the recompute touches
+// only the store, the clock, the inflow and partial-sum buffers and the edge
+// arrays, the reverse passes only the adjoint buffers and the Manning and
+// hydrograph gradients, so the two overlap.  Events order each store's
+// recompute after the reverse that last read it, and each reverse after its
+// recompute.
 template <typename T>
 fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_device,
                          double* grad_q) {
     const size_t fb = field_bytes(c), sb = side_bytes(c);
     const long long N = c->adj_nsteps, C = c->adj_C, n0 = c->adj_n0;
     const int nx = c->nx, ny = c->ny, ng = (int)c->gauges.size();
-    fl_status st;
-    // scratch of the sweep (freed at the end)
-    std::vector<void*> tmp;
-    auto talloc = [&](void** p, size_t bytes) -> fl_status {
-        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
-        if (e != hipSuccess) return fail(c, FL_ENOMEM, std::string("adjoint scratch: ") + hipGetErrorString(e));
-        tmp.push_back(*p);
-        return hipMemsetAsync(*p, 0, std::max<size_t>(bytes, 256), c->stream) == hipSuccess
-                   ? FL_OK : fail(c, FL_EHIP, "hipMemsetAsync");
-    };
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(c->stream);
-        for (void* p : tmp) (void)hipFree(p);
-    };
-    void *store = nullptr, *lam = nullptr, *aux = nullptr;
-    double *gn = nullptr, *ain = nullptr, *gq = nullptr;
-    void* d_dl = nullptr;
     const int nsamp = (int)c->ts.size();
-    if ((st = talloc(&store, fb * 3 * (C + 1))) || (st = talloc(&lam, fb * 6)) ||
-        (st = talloc(&aux, fb * 3)) || (st = talloc((void**)&gn, sizeof(double) * nx * ny)) ||
-        (st = talloc((void**)&ain, sizeof(double) * std::max(1, c->in_count))) ||
-        (st = talloc((void**)&gq, sizeof(double) * std::max(1, nsamp)))) {
-        cleanup();
-        return st;
+    fl_status st;
+    // scratch of the sweep, kept with the forward record for further sweeps
+    if (!c->d_bwd) {
+        const size_t bytes = fb * 3 * (C + 1) * 2 + fb * 6 + fb * 3 + sizeof(double) * nx * ny +
+                             sizeof(double) * std::max(1, c->in_count) + sizeof(double) * std::max(1, nsamp) +
+                             256 * 8;
+        hipError_t e = hipMalloc(&c->d_bwd, bytes);
+        if (e != hipSuccess) {
+            c->d_bwd = nullptr;
+            return fail(c, FL_ENOMEM, std::string("adjoint scratch: ") + hipGetErrorString(e));
+        }
+        c->adj_allocs.push_back(c->d_bwd);
     }
+    unsigned char* cur_b = static_cast<unsigned char*>(c->d_bwd);
+    auto carve = [&](size_t bytes) {
+        unsigned char* p = cur_b;
+        cur_b += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    void* store[2];
+    store[0] = carve(fb * 3 * (C + 1));
+    store[1] = carve(fb * 3 * (C + 1));
+    void* lam = carve(fb * 6);
+    void* aux = carve(fb * 3);
+    double* gn = (double*)carve(sizeof(double) * nx * ny);
+    double* ain = (double*)carve(sizeof(double) * std::max(1, c->in_count));
+    double* gq = (double*)carve(sizeof(double) * std::max(1, nsamp));
+    HIP_TRY(c, hipMemsetAsync(lam, 0, fb * 6, c->stream));
+    HIP_TRY(c, hipMemsetAsync(aux, 0, fb * 3, c->stream));
+    HIP_TRY(c, hipMemsetAsync(gn, 0, sizeof(double) * nx * ny, c->stream));
+    HIP_TRY(c, hipMemsetAsync(ain, 0, sizeof(double) * std::max(1, c->in_count), c->stream));
+    HIP_TRY(c, hipMemsetAsync(gq, 0, sizeof(double) * std::max(1, nsamp), c->stream));
+    void* d_dl = nullptr;
+    struct Owned {
+        void* dl = nullptr;
+        hipStream_t as = nullptr;
+        hipEvent_t ev[5] = {};
+        ~Owned() {
+            if (as) (void)hipStreamSynchronize(as);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (as) (void)hipStreamDestroy(as);
+            if (dl) (void)hipFree(dl);
+        }
+    } own;
     if (dl) {
         const size_t bytes = (size_t)c->adj_nobs * ng * sizeof(T);
-        if ((st = talloc(&d_dl, bytes))) { cleanup(); return st; }
-        hipError_t e = hipMemcpyAsync(d_dl, dl, bytes, hipMemcpyDefault, c->stream);
-        if (e != hipSuccess) { cleanup(); return hip_fail(c, e, "copy dL/dseries"); }
+        HIP_TRY(c, hipMalloc(&own.dl, std::max<size_t>(bytes, 256)));
+        d_dl = own.dl;
+        HIP_TRY(c, hipMemcpyAsync(d_dl, dl, bytes, hipMemcpyDefault, c->stream));
     }
+    // the reverse stream (default priority); events: recomputed[2], reversed[2], start
+    HIP_TRY(c, hipStreamCreateWithFlags(&own.as, hipStreamNonBlocking));
+    for (hipEvent_t& e : own.ev) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t* recomputed = own.ev;
+    hipEvent_t* reversed = own.ev + 2;
+    hipEvent_t start = own.ev[4];
+    bool reversed_set[2] = {false, false};
+    HIP_TRY(c, hipEventRecord(start, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(own.as, start, 0));
     auto F = [&](void* base, long long k) { return static_cast<unsigned char*>(base) + fb * k; };
     T* lamf[6];
     for (int k = 0; k < 6; ++k) lamf[k] = (T*)F(lam, k);
@@ -1648,46 +1688,60 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
     const T* obs = (const T*)c->d_obs;
     const T* dlT = (const T*)d_dl;
     hipError_t e = hipSuccess;
-    for (long long sgi = c->adj_nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+    // recompute segment sgi into store[sgi & 1] (context stream)
+    auto recompute = [&](long long sgi) -> hipError_t {
+        const int b = (int)(sgi & 1);
+        void* sto = store[b];
+        hipError_t r = hipSuccess;
+        if (reversed_set[b]) r = hipStreamWaitEvent(c->stream, reversed[b], 0);
         const long long ks = sgi * C, ke = std::min(ks + C, N);
         // restore the checkpoint: clock, the inflow that step reads, the state
         const long long nstart = n0 + ks;
-        e = hipMemcpyAsync(c->d_ctl, c->d_ck_ctl + sgi, sizeof(DevCtl), hipMemcpyDeviceToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->d_qin[nstart & 1], static_cast<unsigned char*>(c->d_ck_qin) + sb * sgi, sb,
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(c->d_ctl, c->d_ck_ctl + sgi, sizeof(DevCtl), hipMemcpyDeviceToDevice, c->stream);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(c->d_qin[nstart & 1], static_cast<unsigned char*>(c->d_ck_qin) + sb * sgi, sb,
                                hipMemcpyDeviceToDevice, c->stream);
-        for (int f = 0; f < 3 && e == hipSuccess; ++f)
-            e = hipMemcpyAsync(F(store, f), static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + f), fb,
+        for (int f = 0; f < 3 && r == hipSuccess; ++f)
+            r = hipMemcpyAsync(F(sto, f), static_cast<unsigned char*>(c->d_ck) + fb * (3 * sgi + f), fb,
                                hipMemcpyDeviceToDevice, c->stream);
         // recompute the segment, keeping every state
-        for (long long k = ks; k < ke && e == hipSuccess; ++k) {
+        for (long long k = ks; k < ke && r == hipSuccess; ++k) {
             StepArgs<T> a = make_args<T>(c, n0 + k);
             const long long si = k - ks;
-            a.h_in = (const T*)F(store, 3 * si + 0);
-            a.qx_in = (const T*)F(store, 3 * si + 1);
-            a.qy_in = (const T*)F(store, 3 * si + 2);
-            a.h_out = (T*)F(store, 3 * (si + 1) + 0);
-            a.qx_out = (T*)F(store, 3 * (si + 1) + 1);
-            a.qy_out = (T*)F(store, 3 * (si + 1) + 2);
-            e = launch_step<T>(a, c->cpt, c->stream);
+            a.h_in = (const T*)F(sto, 3 * si + 0);
+            a.qx_in = (const T*)F(sto, 3 * si + 1);
+            a.qy_in = (const T*)F(sto, 3 * si + 2);
+            a.h_out = (T*)F(sto, 3 * (si + 1) + 0);
+            a.qx_out = (T*)F(sto, 3 * (si + 1) + 1);
+            a.qy_out = (T*)F(sto, 3 * (si + 1) + 2);
+            r = launch_step<T>(a, c->cpt, c->stream);
         }
-        // reverse the segment's steps
-        for (long long k = ke - 1; k >= ks && e == hipSuccess; --k) {
+        if (r == hipSuccess) r = hipEventRecord(recomputed[b], c->stream);
+        return r;
+    };
+    // reverse segment sgi from store[sgi & 1] (reverse stream)
+    auto reverse = [&](long long sgi) -> hipError_t {
+        const int b = (int)(sgi & 1);
+        void* sto = store[b];
+        hipError_t r = hipStreamWaitEvent(own.as, recomputed[b], 0);
+        const long long ks = sgi * C, ke = std::min(ks + C, N);
+        for (long long k = ke - 1; k >= ks && r == hipSuccess; --k) {
             T* l1 = lamf[3 * cur];
             if ((k + 1) % c->obs_every == 0) {
                 const long long o = (k + 1) / c->obs_every - 1;
                 const int nu = c->ngcell;
-                e = launch_gauge_seed<T>(l1, c->pitch, nx, c->d_gcell, c->d_gcell + nu,
+                r = launch_gauge_seed<T>(l1, c->pitch, nx, c->d_gcell, c->d_gcell + nu,
                                          c->d_gcell + 2 * nu + 1, nu, series + o * ng,
                                          obs ? obs + o * ng : nullptr, dlT ? dlT + o * ng : nullptr,
-                                         c->stream);
-                if (e != hipSuccess) break;
+                                         own.as);
+                if (r != hipSuccess) break;
             }
             AdjArgs<T> a{};
             const long long si = k - ks;
-            a.h = (const T*)F(store, 3 * si + 0);
-            a.qx = (const T*)F(store, 3 * si + 1);
-            a.qy = (const T*)F(store, 3 * si + 2);
+            a.h = (const T*)F(sto, 3 * si + 0);
+            a.qx = (const T*)F(sto, 3 * si + 1);
+            a.qy = (const T*)F(sto, 3 * si + 2);
             a.z = (const T*)c->d_z;
             a.n = (const T*)c->d_n;
             a.lh1 = lamf[3 * cur];
@@ -1728,11 +1782,22 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
             // the inflow pass of step k+1 (reversed just before) runs inside pass A
             a.bc_prev = (k + 1 < N) ? 1 : 0;
             a.t_prev = (k + 1 < N) ? tseq[k + 1] : 0.0;
-            e = launch_adjoint_step<T>(a, c->stream);
+            r = launch_adjoint_step<T>(a, own.as);
             cur = 1 - cur;
-            if (k == 0 && e == hipSuccess) e = launch_adjoint_inflow<T>(a, c->stream);
+            if (k == 0 && r == hipSuccess) r = launch_adjoint_inflow<T>(a, own.as);
         }
+        if (r == hipSuccess) r = hipEventRecord(reversed[b], own.as);
+        reversed_set[b] = true;
+        return r;
+    };
+    if (c->adj_nck > 0) e = recompute(c->adj_nck - 1);
+    for (long long sgi = c->adj_nck - 1; sgi >= 0 && e == hipSuccess; --sgi) {
+        if (sgi >= 1) e = recompute(sgi - 1);   // overlaps the reverse of segment sgi
+        if (e == hipSuccess) e = reverse(sgi);
     }
+    // the context stream continues after the last reverse
+    if (e == hipSuccess) e = hipEventRecord(start, own.as);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, start, 0);
     if (e == hipSuccess) {
         e = hipMemcpyAsync(grad_n, gn, sizeof(double) * nx * ny,
                            grad_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
@@ -1743,8 +1808,8 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
     // back to the end of the forward run
     c->nstep = n0 + N;
     c->act_at = -1;
-    if (e == hipSuccess && (st = snapshot_end(c, true))) { cleanup(); return st; }
-    cleanup();
+    if (e == hipSuccess && (st = snapshot_end(c, true))) return st;
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint sweep");
     if (grad_q)
         for (int k = 0; k < nsamp; ++k) grad_q[k] = gqh[k];
@@ -1769,7 +1834,7 @@ fl_status adj_forward_t(fl_ctx* c, long long N, void* series_out, int on_device,
         if (p == c->d_gauges || p == c->d_gcell || p == c->d_obs) keep.push_back(p);
         else (void)hipFree(p);
     c->adj_allocs = keep;
-    c->d_series = c->d_ck = c->d_ck_qin = c->d_end = nullptr;
+    c->d_series = c->d_ck = c->d_ck_qin = c->d_end = c->d_bwd = nullptr;
     c->d_ck_ctl = nullptr;
     c->adj_nsteps = 0;
     const long long C = c->ckpt_req > 0 ? c->ckpt_req
