@@ -122,3 +122,16 @@ def test_variant_pins_catch_mutant(name, tmp_path):
 def test_adjoint_pins_catch_mutant(name, tmp_path):
     old, new = ADJ_MUTANTS[name]
     _build_and_run_pins(tmp_path, ADJ_SRC, old, new, "test_oracle_adjoint.py", name)
+
+
+# Forward mistakes a single face exposes: the hand-worked two-cell steps alone must catch them.
+FACE_MUTANTS = ["dt_dropped_from_gravity_term", "gravity_sign_flipped", "friction_exponent_4_3",
+                "hf_min_bed", "face_roughness_one_sided", "depth_update_sign",
+                "y_faces_use_x_neighbour", "donor_wrong_cell"]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", FACE_MUTANTS)
+def test_face_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    _build_and_run_pins(tmp_path, SRC, old, new, "test_oracle_face_pin.py", name)
