@@ -123,22 +123,45 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // field of the library is device memory.  Pointers a kernel reads from memory
 // (a batch's member descriptors) rather than from its arguments would
 // otherwise compile to flat accesses, which cannot take a scalar base address
-// and are counted with the LDS and scalar-memory operations.
+// and are counted with the LDS and scalar-memory operations.  Kernels whose
+// row pointers are launch arguments keep generic pointers (GA = false): the
+// compiler already proves them global there, and the generic form schedules
+// the two-step marcher's loads and stores better.
 template <typename T>
 struct Global { typedef __attribute__((address_space(1))) T type; };
 template <typename T>
 __device__ __forceinline__ typename Global<T>::type* as_global(T* p) {
     return (typename Global<T>::type*)p;
 }
+template <bool GA, typename T>
+struct Space { typedef T type; };
+template <typename T>
+struct Space<true, T> { typedef typename Global<T>::type type; };
+template <bool GA, typename T>
+__device__ __forceinline__ typename Space<GA, T>::type* in_space(T* p) {
+    return (typename Space<GA, T>::type*)p;
+}
+// V in the address space (and constness) of E
+template <typename E, typename V>
+struct Like { typedef V type; };
+template <typename E, typename V>
+struct Like<const E, V> { typedef const V type; };
+template <typename E, typename V>
+struct Like<__attribute__((address_space(1))) E, V> {
+    typedef __attribute__((address_space(1))) V type;
+};
+template <typename E, typename V>
+struct Like<const __attribute__((address_space(1))) E, V> {
+    typedef const __attribute__((address_space(1))) V type;
+};
 
 // Element at byte offset boff (32-bit, per lane) from a row start that is the
 // same in every lane: the form the scalar-base + 32-bit-offset memory
 // instructions take, with no per-lane 64-bit address arithmetic.
-template <typename P>
-__device__ __forceinline__ P* at_byte(P* row, unsigned boff) {
-    typedef typename Global<char>::type gchar;
-    gchar* b = const_cast<gchar*>(reinterpret_cast<const gchar*>(row));
-    return reinterpret_cast<P*>(b + boff);
+template <typename E>
+__device__ __forceinline__ E* at_byte(E* row, unsigned boff) {
+    typedef typename Like<E, char>::type B;
+    return reinterpret_cast<E*>(reinterpret_cast<B*>(row) + boff);
 }
 
 // Vector load of a row segment (N consecutive elements) and vector store of the
@@ -150,18 +173,28 @@ __device__ __forceinline__ P* at_byte(P* row, unsigned boff) {
 template <typename T, int N>
 struct NVec { typedef T type __attribute__((ext_vector_type(N))); };
 template <typename T, int N>
+struct alignas(sizeof(T) * N) VecT { T v[N]; };
+template <typename T, int N>
+__device__ __forceinline__ void ldv(const T* p, T (&o)[N]) {
+    const VecT<T, N> t = *reinterpret_cast<const VecT<T, N>*>(p);
+#pragma unroll
+    for (int m = 0; m < N; ++m) o[m] = t.v[m];
+}
+template <typename T, int N>
 __device__ __forceinline__ void ldv(const typename Global<T>::type* p, T (&o)[N]) {
     typedef const typename Global<typename NVec<T, N>::type>::type V;
     const typename NVec<T, N>::type t = *reinterpret_cast<V*>(p);
-#pragma unroll
-    for (int m = 0; m < N; ++m) o[m] = t[m];
+    // a byte copy out of the vector keeps the row registers out of private
+    // memory (copied element by element, the compiler spilled the prefetched
+    // row to scratch and waited for the loads at once)
+    __builtin_memcpy(o, &t, sizeof(t));
 }
-template <typename T, int N, bool NT>
-__device__ __forceinline__ void stv(typename Global<T>::type* p, const T (&o)[N]) {
+template <typename T, int N, bool NT, typename E>
+__device__ __forceinline__ void stv(E* p, const T (&o)[N]) {
     typename NVec<T, N>::type t;
 #pragma unroll
     for (int m = 0; m < N; ++m) t[m] = o[m];
-    typedef typename Global<typename NVec<T, N>::type>::type V;
+    typedef typename Like<E, typename NVec<T, N>::type>::type V;
     if (NT) __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
     else *reinterpret_cast<V*>(p) = t;
 }

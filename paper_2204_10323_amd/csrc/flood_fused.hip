@@ -217,7 +217,7 @@ __device__ __forceinline__ bool needs_inflow(const StepArgs<T>& a, int s, int j0
 // emits holds water (h > 0, or NaN), changed its depth in that step, or
 // carries a non-zero discharge on a face the item stores (border faces
 // included); A's rows beyond the item count too (conservative).
-template <typename T, int CPT, bool ACT = false>
+template <typename T, int CPT, bool ACT, bool GA>
 __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
                            const T* __restrict__ qx_in, const T* __restrict__ qy_in,
                            T* __restrict__ h_out, T* __restrict__ qx_out, T* __restrict__ qy_out,
@@ -251,11 +251,11 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     auto load_row = [&](int k) {
         if (loads && k >= -kHalo && k < ny + kHalo) {
             const long long o = (long long)(k + kHalo) * P;
-            ldv<T, CPT>(at_byte(as_global(h_in) + o, boff), hN);
-            ldv<T, CPT>(at_byte(as_global(a.z) + o, boff), zN);
-            ldv<T, CPT>(at_byte(as_global(a.n) + o, boff), nN);
-            ldv<T, CPT>(at_byte(as_global(qx_in) + o, boff), qxN);
-            ldv<T, CPT>(at_byte(as_global(qy_in) + o, boff), qyN);
+            ldv<T, CPT>(at_byte(in_space<GA>(h_in) + o, boff), hN);
+            ldv<T, CPT>(at_byte(in_space<GA>(a.z) + o, boff), zN);
+            ldv<T, CPT>(at_byte(in_space<GA>(a.n) + o, boff), nN);
+            ldv<T, CPT>(at_byte(in_space<GA>(qx_in) + o, boff), qxN);
+            ldv<T, CPT>(at_byte(in_space<GA>(qy_in) + o, boff), qyN);
         } else {
 #pragma unroll
             for (int m = 0; m < CPT; ++m) hN[m] = zN[m] = nN[m] = qxN[m] = qyN[m] = T(0);
@@ -280,9 +280,9 @@ __device__ void step2_item(const StepArgs<T>& a, const T* __restrict__ h_in,
     };
     auto store_row = [&](int r, const T (&hv)[CPT], const T (&qxv)[CPT], const T (&qyv)[CPT]) {
         const long long o = (long long)(r + kHalo) * P;
-        auto* const ho = as_global(h_out) + o;
-        auto* const qxr = as_global(qx_out) + o;
-        auto* const qyr = as_global(qy_out) + o;
+        auto* const ho = in_space<GA>(h_out) + o;
+        auto* const qxr = in_space<GA>(qx_out) + o;
+        auto* const qyr = in_space<GA>(qy_out) + o;
         if (all_store) {
             stv<T, CPT, true>(at_byte(ho, boff), hv);
             stv<T, CPT, true>(at_byte(qxr, boff), qxv);
@@ -435,7 +435,8 @@ __device__ __forceinline__ bool item_needed2(const StepArgs<T>& a, int s, int c,
     return __ballot(v != 0) != 0ull;
 }
 
-template <typename T, int CPT, bool ACT>
+// GA: row pointers typed global (they come from memory in the batch kernel)
+template <typename T, int CPT, bool ACT, bool GA>
 __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P, int item) {
     const StepArgs<T>& a = A.a;
     constexpr int WL = 64 * CPT, WO = WL - 8;
@@ -469,7 +470,7 @@ __device__ __forceinline__ void tile2_item(const Step2Args<T>& A, const Plan2& P
     typename Ord<T>::U hbA = 0, hbB = 0;
     double oA = 0.0, oB = 0.0;
     bool moved = false;
-    step2_item<T, CPT, ACT>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0],
+    step2_item<T, CPT, ACT, GA>(a, in1 ? A.h[1] : A.h[0], in1 ? A.qx[1] : A.qx[0],
                             in1 ? A.qy[1] : A.qy[0], in1 ? A.h[0] : A.h[1],
                             in1 ? A.qx[0] : A.qx[1], in1 ? A.qy[0] : A.qy[1], KA, KB, two, s, j0,
                             j1, hbA, hbB, oA, oB, moved);
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CPT == 2) ? 3 : 1) void k_s
     // derived from it: strip, rows, loop counter, border tests) scalar
     const int wave = lin * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= A.a.nstrips * A.a.nchunks) return;
-    tile2_item<T, CPT, ACT>(A, P, wave);
+    tile2_item<T, CPT, ACT, false>(A, P, wave);
 }
 
 // Persistent batch with two steps per queue entry: the two-step launches of
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_batch2(
         const Step2Args<T>& A = S.a2[l == B.nlaunch - 1 ? 1 : 0][(int)((B.l0 + l) % 6)];
         const Plan2 P = make_plan<T>(A);
         if (e == 0) clock2_wave<T>(A, P);
-        else if (P.mode != 0) tile2_item<T, CPT, false>(A, P, e - 1);
+        else if (P.mode != 0) tile2_item<T, CPT, false, true>(A, P, e - 1);
         __builtin_amdgcn_s_waitcnt(0);
         __asm__ volatile("" ::: "memory");
         if (lane == 0) atomicAdd(&B.done[m], 1ull);
