@@ -33,7 +33,8 @@ CSRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc")
 KERNEL_SRCS = ["flood_device.h", "flood_march.h", "flood_kernels.hip", "flood_fused.hip"]
 # committed PMC summaries of the dominant kernel, by steps per launch
 PMC_SUMMARY = {1: os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md"),
-               2: os.path.join(ROOT, "profiles", "k_step2_valley16384_prewetted_pmc.md")}
+               2: os.path.join(ROOT, "profiles", "k_fused2_valley16384_prewetted_pmc.md"),
+               3: os.path.join(ROOT, "profiles", "k_fused3_valley16384_prewetted_pmc.md")}
 PROBE_LIB = os.path.join(ROOT, "bench_probe.so")
 
 
@@ -174,6 +175,15 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
         seq2_ms += g.time_steps(steps)
         g.close()
     progress("ensemble: members one after another, two steps per launch, done")
+    # one after another with three steps per launch
+    seq3_ms = 0.0
+    for sc in scs:
+        g = fl.from_scenario(sc, "f32", stream=stream, fusion=3)
+        g.step(3)
+        seq3_ms += g.time_steps(steps)
+        g.close()
+    progress("ensemble: members one after another, three steps per launch, done")
+    seq_best = min(seq_ms, seq2_ms, seq3_ms)
     b = fl.Batch(ctxs)
     cands = BATCH_TILINGS
     best, _ = b.autotune(cands, trial_steps)
@@ -230,9 +240,11 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
             "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
             "batch_vs_sequential": round(seq_ms / batch_ms, 3),
             "sequential_two_step_gcell_s": round(cells * steps / (seq2_ms / 1e3) / 1e9, 3),
-            "batch_vs_best_sequential": round(min(seq_ms, seq2_ms) / batch_ms, 3),
+            "sequential_three_step_gcell_s": round(cells * steps / (seq3_ms / 1e3) / 1e9, 3),
+            "best_sequential_gcell_s": round(cells * steps / (seq_best / 1e3) / 1e9, 3),
+            "batch_vs_best_sequential": round(seq_best / batch_ms, 3),
             "best_batch_gcell_s": round(cells * steps / (min(batch_ms, batch2_ms) / 1e3) / 1e9, 3),
-            "best_batch_vs_best_sequential": round(min(seq_ms, seq2_ms) / min(batch_ms, batch2_ms), 3),
+            "best_batch_vs_best_sequential": round(seq_best / min(batch_ms, batch2_ms), 3),
             "batch_hbm_frac": round(32 * cells * steps / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "max_budget_error": max(r.budget_error() for r in rep)}
 
@@ -255,6 +267,10 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
     f = fl.from_scenario(sc, "f32", stream=stream, fusion=2)
     f.step(6)
     plain2_ms = f.time_steps(steps)
+    f.close()
+    f = fl.from_scenario(sc, "f32", stream=stream, fusion=3)
+    f.step(6)
+    plain3_ms = f.time_steps(steps)
     f.close()
     # truth run with n_true, gauges among its wet cells at the last step
     truth = synth.Scenario(sc.name, sc.nx, sc.ny, sc.dx, sc.z, sc.extra["n_true"], sc.h0,
@@ -288,7 +304,8 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
             "plain_gcell_s": round(cells * steps / (plain_ms / 1e3) / 1e9, 3),
             "adjoint_vs_plain": round((plain_ms / 1e3) / (t2 - t0), 4),
             "plain_two_step_gcell_s": round(cells * steps / (plain2_ms / 1e3) / 1e9, 3),
-            "adjoint_vs_best_plain": round((min(plain_ms, plain2_ms) / 1e3) / (t2 - t0), 4)}
+            "plain_three_step_gcell_s": round(cells * steps / (plain3_ms / 1e3) / 1e9, 3),
+            "adjoint_vs_best_plain": round((min(plain_ms, plain2_ms, plain3_ms) / 1e3) / (t2 - t0), 4)}
 
 
 # (cells per lane, rows per work item) the active-tile autotuner tries: small
@@ -425,8 +442,8 @@ def main():
     ap.add_argument("--workload", default="valley16384_wet", choices=sorted(WORKLOAD_NAMES),
                     help="valley16384_wet: pre-wetted start (default); valley16384: dry start")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--fusion", type=int, default=2, choices=[1, 2],
-                    help="time steps per launch (2: two-step kernel, the default)")
+    ap.add_argument("--fusion", type=int, default=3, choices=[1, 2, 3],
+                    help="time steps per launch (3: three chained steps per launch, the default)")
     ap.add_argument("--cells-per-lane", type=int, default=0,
                     help="tiling of the kernel in use (0: its default)")
     ap.add_argument("--rows-per-item", type=int, default=0)
@@ -472,8 +489,8 @@ def main():
 
     def run_timed(scn, fusion=args.fusion, keep_depth=False):
         tiling = dict(cells_per_lane=args.cells_per_lane, rows_per_item=args.rows_per_item)
-        if fusion == 2:
-            tiling = dict(fusion=(2, args.cells_per_lane, args.rows_per_item))
+        if fusion >= 2:
+            tiling = dict(fusion=(fusion, args.cells_per_lane, args.rows_per_item))
         f = fl.from_scenario(scn, args.precision, device=0, stream=stream,
                              steps_per_graph=args.steps_per_graph, **tiling)
         try:
@@ -549,11 +566,13 @@ def main():
     extras = {"wall_s_timed_region": round(wall, 4), "input_generation_s": round(t_gen, 1),
               "device_bytes": dev_bytes, "budget_error": rep.budget_error(),
               "sim_time_s": rep.t, "kernel_sha256_16": kernel_hash()}
-    other = 3 - args.fusion
+    others = [k for k in (1, 2, 3) if k != args.fusion]
     if not args.no_compare:
-        ev1, _, rep1, _, _ = run_timed(sc, other)
-        extras[f"steps_per_launch_{other}_gcell_s"] = gcell(ev1)
-        extras[f"steps_per_launch_{other}_same_clock"] = (rep1.t == rep.t and rep1.steps == rep.steps)
+        for other in others:
+            ev1, _, rep1, _, _ = run_timed(sc, other)
+            extras[f"steps_per_launch_{other}_gcell_s"] = gcell(ev1)
+            extras[f"steps_per_launch_{other}_same_clock"] = (rep1.t == rep.t and
+                                                               rep1.steps == rep.steps)
     if keep:
         progress("active tiles")
         extras["active_tiles"] = run_active(fl, torch, sc, args.warmup, args.steps, value, full_depth)
@@ -571,8 +590,9 @@ def main():
         d[f"steps_per_launch_{args.fusion}_gcell_s"] = gcell(ev2)
         d["budget_error"] = rep2.budget_error()
         if not args.no_compare:
-            ev3, _, _, _, _ = run_timed(sco, other)
-            d[f"steps_per_launch_{other}_gcell_s"] = gcell(ev3)
+            for other in others:
+                ev3, _, _, _, _ = run_timed(sco, other)
+                d[f"steps_per_launch_{other}_gcell_s"] = gcell(ev3)
         if keep_o:
             d["active_tiles"] = run_active(fl, torch, sco, args.warmup, args.steps,
                                            cells * args.steps / (ev2 / 1e3) / 1e9, depth_o)

@@ -171,7 +171,7 @@ fl_status fl_set_state(fl_ctx *ctx, const void *h, const void *qx, const void *q
 /* Device memory for the buffers fl_commit allocates, for a caller that owns
  * its memory (for example a PyTorch tensor):
  * fl_workspace_bytes gives the bytes a grid needs (0 for invalid arguments);
- * flags: FL_WS_TWO_STEP adds the buffers of fl_set_fusion(ctx, 2, ...),
+ * flags: FL_WS_TWO_STEP adds the buffers of fl_set_fusion(ctx, 2 or 3, ...),
  * FL_WS_ACTIVE_TILES those of fl_set_active_tiles(ctx, 1).
  * fl_bind_workspace makes the following commits carve their buffers from
  * dev_ptr (256-byte aligned, on the context's device) instead of allocating;
@@ -201,8 +201,8 @@ fl_status fl_commit(fl_ctx *ctx);
  * the explicit update of Methods, "Shallow Water Equations": boundary faces
  * (eqs. 5, 6), interior faces (eq. 3), donor scaling, depths (eq. 4), with dt
  * from the device clock (the paper's time step, Methods and Appendix,
- * "Inputs").  Asynchronous on the context's stream, except with two steps per
- * launch (fl_set_fusion), which synchronises before it returns.  ESTATE
+ * "Inputs").  Asynchronous on the context's stream, except with several steps
+ * per launch (fl_set_fusion), which synchronises before it returns.  ESTATE
  * before commit.  EINVAL: nsteps < 0. */
 fl_status fl_step(fl_ctx *ctx, int64_t nsteps);
 
@@ -255,18 +255,23 @@ fl_status fl_time_steps(fl_ctx *ctx, int64_t nsteps, double *elapsed_ms);
  * the default.  EINVAL: unsupported value. */
 fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_item);
 
-/* Steps per launch of fl_step and fl_time_steps: 1 (default) or 2, and the
- * tiling of the two-step kernel (0 = default: 2 cells per lane in FP32, 1 in
- * FP64; rows as fl_set_tiling).  With 2, one launch reads the state once and
- * makes two steps (Methods, eqs. 3-6, applied twice), halving the HBM traffic
- * per step.  Under the CFL clock the second step's dt is taken as if the
- * deepest cell of the intermediate state were shallow; the next launch checks
- * it against that state's actual maximum and, if it differs, redoes both steps
- * from the kept input.  Results are bitwise those of one step per launch.
- * fl_step then synchronises the context's stream before it returns; a count
- * of 1 still makes a single-step launch.  fl_advance, fl_autotune, reverse
- * mode and batches use single-step launches.  Takes effect at the next
- * fl_commit.  EINVAL: steps_per_launch not 1 or 2, an unsupported tiling. */
+/* Steps per launch of fl_step and fl_time_steps: 1 (default), 2 or 3, and
+ * the tiling of the multi-step kernel (0 = default: 2 cells per lane in FP32,
+ * 1 in FP64; rows as fl_set_tiling).  With k > 1, one launch reads the state
+ * once and makes up to k steps (Methods, eqs. 3-6, applied k times), dividing
+ * the HBM traffic per step by k.  The dt of every step after a launch's first
+ * is taken as if the deepest cell of the state before it were shallow (the
+ * paper's fixed dt is never shortened by depth); the next launch checks each
+ * against that state's actual maximum and, at the first that differs, redoes
+ * the launch up to that step from the kept input.  Under the CFL clock a
+ * launch makes fewer steps when the bound is close to active.  Results are
+ * bitwise those of one step per launch.  fl_step then synchronises the
+ * context's stream before it returns; a count of 1 still makes a
+ * single-step launch.  fl_advance, fl_autotune and reverse mode use
+ * single-step launches, batches one or two steps per queue entry
+ * (fl_batch_set_fusion).  Active tiles allow at most 2, 4 cells per lane only
+ * 2 (fl_commit: EINVAL otherwise).  Takes effect at the next fl_commit.
+ * EINVAL: steps_per_launch not 1, 2 or 3, an unsupported tiling. */
 fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per_lane,
                         int32_t rows_per_item);
 
@@ -286,7 +291,7 @@ fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per
  *     dx h^{2/3} sqrt(S)/n per unit width of its face; W of eq. (6) is then
  *     bisected 64 times in FP64.
  * Variants run one step per launch (fl_step, fl_advance, fl_time_steps,
- * fl_autotune); fl_commit fails with EINVAL with two steps per launch or
+ * fl_autotune); fl_commit fails with EINVAL with several steps per launch or
  * active tiles, fl_batch_create with a member that has a variant, and
  * fl_adj_setup on such a context.  Takes effect at the next fl_commit.
  * EINVAL: an unknown value. */
@@ -322,7 +327,8 @@ fl_status fl_set_variant(fl_ctx *ctx, int32_t friction, int32_t boundary);
  * water.  fl_autotune times both and keeps the faster with the tiling.  Two
  * steps per launch and batches always use the per-item test.  Takes effect
  * at the next fl_commit, which fails with EINVAL for two steps per launch
- * with 1-row work items.  EINVAL: on not 0, 1 or 2. */
+ * with 1-row work items and for three steps per launch.  EINVAL: on not 0, 1
+ * or 2. */
 fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
 
 /* Work items the next launch computes under active-tile skipping
@@ -344,16 +350,17 @@ fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items
 fl_status fl_autotune(fl_ctx *ctx, const int32_t *candidates, int32_t ncand, int32_t trial_steps,
                       int32_t *best, double *best_ms);
 
-/* Time one step per launch (the current tiling) against two steps per launch
- * (the current two-step tiling) over trial_steps frozen steps each (dt = 0:
+/* Time one step per launch (the current tiling) against the committed k
+ * steps per launch (fl_set_fusion; its tiling) over trial_steps frozen steps
+ * each (dt = 0:
  * the state is streamed but left as it is), and keep the faster for the
  * following fl_step calls; both give the same bits.  With active tiles the
  * trial steps skip as real steps would (after untimed steps that set the
  * flags).  Two steps per launch pay off on large grids that HBM bandwidth
  * bounds, and under active tiles when many items hold water; small,
- * cache-resident or nearly dry grids can be faster with one.  *steps_per_launch receives the choice (1 or 2),
+ * cache-resident or nearly dry grids can be faster with one.  *steps_per_launch receives the choice (1 or k),
  * *ms_per_step its time per step.  ESTATE: not committed, or committed
- * without fl_set_fusion(ctx, 2, ...) (the two-step buffers).  EINVAL:
+ * without fl_set_fusion(ctx, 2 or 3, ...) (the multi-step buffers).  EINVAL:
  * trial_steps < 2. */
 fl_status fl_autotune_fusion(fl_ctx *ctx, int32_t trial_steps, int32_t *steps_per_launch,
                              double *ms_per_step);
@@ -422,7 +429,7 @@ fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t r
  * launch and redone if wrong) inside the one persistent launch, so members
  * wait for their own previous launch half as often; results stay bitwise those
  * of stepping each member alone.  Every member must have been committed after
- * fl_set_fusion(ctx, 2, ...) (ESTATE otherwise) and run without active tiles
+ * fl_set_fusion(ctx, 2 or 3, ...) (ESTATE otherwise) and run without active tiles
  * (EINVAL).  cells_per_lane (1 or 2; 0: 2 in FP32, 1 in FP64) and
  * rows_per_item (>= 1; 0: 32) are the two-step tiling, which
  * fl_batch_autotune then tunes.  fl_batch_run_noalloc always runs one step

@@ -321,7 +321,7 @@ class Flood:
         self.set_outflow(side, first, count, slope)
 
     def set_fusion(self, steps_per_launch: int, cells_per_lane: int = 0, rows_per_item: int = 0):
-        """Steps per launch (1 or 2) and the two-step kernel's tiling (fl_set_fusion)."""
+        """Steps per launch (1, 2 or 3) and the multi-step kernel's tiling (fl_set_fusion)."""
         _check(self.ctx, lib().fl_set_fusion(self.ctx, steps_per_launch, cells_per_lane,
                                              rows_per_item))
 
@@ -362,7 +362,7 @@ class Flood:
 
     def autotune_fusion(self, trial_steps: int = 20):
         """Keep one or two steps per launch, whichever frozen trials find faster
-        (fl_autotune_fusion); needs a commit after set_fusion(2)."""
+        (fl_autotune_fusion); needs a commit after set_fusion(2 or 3)."""
         spl = C.c_int32()
         ms = C.c_double()
         _check(self.ctx, lib().fl_autotune_fusion(self.ctx, int(trial_steps), C.byref(spl),

@@ -3,6 +3,7 @@
 // and the inflow solve.  One definition each, so a quantity recomputed by
 // another kernel has the same bits.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -119,6 +120,35 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// f(std::integral_constant<int, I>) for I = B .. E - 1, in order: a loop whose
+// index is a compile-time constant in its body.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Wait until every vector memory operation of the wave has completed
+// (vmcnt = 0; the export and LDS/scalar counters are left alone).
+__device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// A value every lane of the wave holds: read it from the first lane, so that
+// it lives in scalar registers (VALU results are vector registers even when
+// uniform; a marcher chain's per-step constants would otherwise take ~7 VGPRs
+// per step).
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Row accesses through pointers typed in the global address space.  Every
 // field of the library is device memory.  Pointers a kernel reads from memory
 // (a batch's member descriptors) rather than from its arguments would
@@ -154,6 +184,21 @@ template <typename E, typename V>
 struct Like<const __attribute__((address_space(1))) E, V> {
     typedef const __attribute__((address_space(1))) V type;
 };
+
+// A pointer every lane holds (a row start): in scalar registers, so that a
+// row access takes the scalar-base + 32-bit lane offset form, and the compiler
+// does not keep a 64-bit per-lane address for every field across the row loop.
+// (Formed as p plus a zero the compiler cannot see through, so that the
+// pointer keeps its provenance and address space.)
+template <typename P>
+__device__ __forceinline__ P* wave_uniform_ptr(P* p) {
+    const unsigned long long b = (unsigned long long)(__UINTPTR_TYPE__)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    const long long d = (long long)((((unsigned long long)hi << 32) | lo) - b);
+    typedef typename Like<P, char>::type B;
+    return reinterpret_cast<P*>(const_cast<B*>(reinterpret_cast<const B*>(p)) + d);
+}
 
 // Element at byte offset boff (32-bit, per lane) from a row start that is the
 // same in every lane: the form the scalar-base + 32-bit-offset memory

@@ -25,23 +25,27 @@ struct ClockSlot {
     int nonfinite;     // a depth became NaN or infinite
 };
 
-// Clock of the two-step launches, one slot per launch parity.  A launch
-// claims the state it wrote.  When its second step ran with a speculated dt
-// (pending), the next launch compares that dt with the one the depth maximum
-// of the intermediate state gives; if they differ it redoes both steps from
-// the launch's input, which the ping-pong buffers still hold.
-struct Clock2 {
-    ClockSlot ck;       // clock of the claimed state; v_out without the last launch's outflow
-    ClockSlot back;     // clock at the start of the last launch (v_out complete)
-    ClockSlot mid;      // clock after the last launch's first step
-    double dt_a, dt_b;  // dt of its first and second step
-    long long vsteps;   // steps claimed since entering two-step mode (dt = 0 steps included)
-    int cur;            // buffer holding the claimed state
-    int pending;        // the second dt was speculated and is not checked yet
-    int nclose;         // steps of the last launch whose outflow is not in ck.v_out
-    int pad;
-    long long gen;      // launches that produced the claimed state (a redo keeps the count);
-                        // active-tile flags of a launch live in slot gen % 3
+// Most steps one launch makes (multi-step launches, flood_fused.hip).
+constexpr int kFuseMax = 3;
+
+// Clock of the multi-step launches, one slot per launch parity.  A launch
+// claims the state it wrote.  When it ran steps with speculated dts (pending:
+// steps spec .. nclose - 1), the next launch compares each with the dt the
+// depth maximum of the state before it gives; at the first that differs it
+// redoes the launch up to that step from the launch's input, which the
+// ping-pong buffers still hold.
+struct FusedClock {
+    ClockSlot ck;                 // clock of the claimed state; v_out without the last launch's outflow
+    ClockSlot back;               // clock at the start of the last launch (v_out complete)
+    ClockSlot mid[kFuseMax - 1];  // clock after each step of the last launch but its last
+    double dt[kFuseMax];          // dt of each step of the last launch
+    long long vsteps;             // steps claimed since entering multi-step mode (dt = 0 steps included)
+    int cur;                      // buffer holding the claimed state
+    int pending;                  // some of the last launch's dts were speculated and are not checked yet
+    int spec;                     // the last launch's first speculated step
+    int nclose;                   // steps of the last launch (their outflow is not in ck.v_out)
+    long long gen;                // launches that produced the claimed state (a redo keeps the count);
+                                  // active-tile flags of a launch live in slot gen % 3
 };
 
 // Device control block of one context.
@@ -50,13 +54,14 @@ struct DevCtl {
     unsigned long long hmax[3];  // deepest cell as ordered bits: read [n%3], max into [(n+1)%3]
     double t_end;                // effective end time (host may lower it between launches)
     double report[8];            // filled by the flush kernel
-    // two-step launches: launch p reads c2[p % 2] and writes c2[(p + 1) % 2]; its
-    // tiles put the deepest cell of the intermediate and the final state into
-    // hm2[2 (p % 3)] and hm2[2 (p % 3) + 1]
-    Clock2 c2[2];
-    unsigned long long hm2[6];
-    long long target2;           // steps to claim before launches become no-ops
-    long long gen2;              // generation of the last two-step run's claimed state
+    // multi-step launches: launch p reads cf[p % 2] and writes cf[(p + 1) % 2];
+    // its tiles put the deepest cell after its step s into
+    // hmf[kFuseMax (p % 3) + s] for every step but the last, and after its
+    // last step into hmf[kFuseMax (p % 3) + kFuseMax - 1]
+    FusedClock cf[2];
+    unsigned long long hmf[3 * kFuseMax];
+    long long targetf;           // steps to claim before launches become no-ops
+    long long genf;              // generation of the last multi-step run's claimed state
 };
 
 template <typename T>
@@ -105,17 +110,17 @@ struct StepArgs {
 
 enum { VAR_FRICTION_VECTOR = 1, VAR_BOUNDARY_CELL_AREA = 2 };
 
-// A two-step launch: the grid, boundary data and constants (with the
-// two-step tiling) in `a`; both ping-pong buffers, since the launch decides
-// on the device which one holds its input.
+// A multi-step launch: the grid, boundary data and constants (with the
+// tiling of K steps per launch) in `a`; both ping-pong buffers, since the
+// launch decides on the device which one holds its input.
 template <typename T>
-struct Step2Args {
+struct FusedArgs {
     StepArgs<T> a;
     T* h[2];
     T* qx[2];
     T* qy[2];
-    double* part_a[2];  // outflow partial sums of the first and second step, by launch parity
-    double* part_b[2];
+    double* part[kFuseMax][2];  // outflow partial sums of each step of a launch, by launch parity
+    int K;              // steps per launch (2 or 3): strips output 64 CPT - 4 K columns
     int phase;          // launch counter modulo 6
     int resolve;        // 1: only check (and if needed redo) the last launch
 };
@@ -149,10 +154,11 @@ struct BatchArgs {
 };
 
 // A member of a batch run with two steps per queue entry: its two-step
-// launch arguments by settling flag and launch counter modulo 6, and its work.
+// launch arguments (K = 2) by settling flag and launch counter modulo 6, and
+// its work.
 template <typename T>
 struct BatchScen2 {
-    Step2Args<T> a2[2][6];  // [resolve][launch counter % 6]
+    FusedArgs<T> a2[2][6];  // [resolve][launch counter % 6]
     int items;              // two-step work items per launch
     int first;              // offset of this member's (1 + items) entries within a launch
 };
@@ -247,25 +253,26 @@ hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
                              const int* list, int nu, const T* series, const T* obs, const T* dl,
                              hipStream_t s);
 
-// Two-step launches (flood_fused.hip).  enter: the single-step state at
-// step counter n (its budget folded) becomes slot 0 of the two-step clock,
+// Multi-step launches (flood_fused.hip).  enter: the single-step state at
+// step counter n (its budget folded) becomes slot 0 of the multi-step clock,
 // with `target` steps to claim; keep_gen: continue the launch generation of
-// the previous two-step run (its active-tile flags still hold).  leave: the state claimed after `launches`
-// launches becomes the single-step state at counter n2 (buffer n2 % 2 must
-// hold it).
+// the previous multi-step run (its active-tile flags still hold).  leave: the
+// state claimed after `launches` launches becomes the single-step state at
+// counter n2 (buffer n2 % 2 must hold it).
 template <typename T>
-hipError_t launch_step2(const Step2Args<T>& a, int cpt, hipStream_t s);
+hipError_t launch_fused(const FusedArgs<T>& a, int cpt, hipStream_t s);
 template <typename T>
-hipError_t launch_enter2(const StepArgs<T>& single, long long target, int keep_gen, hipStream_t s);
+hipError_t launch_enter_fused(const StepArgs<T>& single, long long target, int keep_gen,
+                              hipStream_t s);
 template <typename T>
-hipError_t launch_leave2(const StepArgs<T>& single, const Step2Args<T>& a2, long long launches,
-                         hipStream_t s);
+hipError_t launch_leave_fused(const StepArgs<T>& single, const FusedArgs<T>& af,
+                              long long launches, hipStream_t s);
 // A persistent batch launch with two steps per queue entry (flood_fused.hip).
 template <typename T>
 hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int device, hipStream_t s, int* blocks_out);
 
-int strip_width(int cpt);   // output columns per work item for cells-per-lane cpt
-int strip_width2(int cpt);  // the same for the two-step kernel
+int strip_width(int cpt);                 // output columns per work item for cells-per-lane cpt
+int strip_width_fused(int cpt, int k);    // the same for k steps per launch
 constexpr int kVolumeParts = 1024;
 
 }  // namespace flood

@@ -81,7 +81,11 @@ struct Marcher {
     }
 
     // Row k enters with its start-of-step h, z, n, qx, qy.  Out: hn, qxo, qyo
-    // of row k-2 (meaningful for rows inside the grid).
+    // of row k-2 (meaningful for rows inside the grid).  EDGE = false: the
+    // caller guarantees that the strip meets no border of the grid (every
+    // lane's cells inside it) and that rows k-2 .. k are inside the grid and
+    // not next to its south or north border, so the border code drops out.
+    template <bool EDGE = true>
     __device__ __forceinline__ void row(const StepArgs<T>& a, const StepK<T>& K,
                                         const StripGeo<CPT>& G, int k, const T (&h0)[CPT],
                                         const T (&z0)[CPT], const T (&n0)[CPT],
@@ -126,7 +130,7 @@ struct Marcher {
                 qsx0[m] = face_q<T>(eta0[m], eR, z0[m], zR, n0[m], nR, qx0[m], K.gdt, K.inv_dx, K.h_eps);
             }
         }
-        if (G.west_strip) {
+        if (EDGE && G.west_strip) {
             const T hRn = from_next(h0[0]);
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
@@ -135,7 +139,7 @@ struct Marcher {
                     qsx0[m] = row_real ? border_q<T, VAR>(a, K, SIDE_W, k, hR) : T(0);
                 }
         }
-        if (G.east_strip) {
+        if (EDGE && G.east_strip) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
                 if (G.east_face[m])
@@ -169,11 +173,11 @@ struct Marcher {
                 qsy1[m] = face_q<T>(eta1[m], eta0[m], z1[m], z0[m], n1[m], n0[m], qy1[m], K.gdt,
                                     K.inv_dx, K.h_eps);
         }
-        if (k - 1 == -1) {
+        if (EDGE && k - 1 == -1) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
                 qsy1[m] = G.outside[m] ? T(0) : border_q<T, VAR>(a, K, SIDE_S, G.i0 + m, h0[m]);
-        } else if (k - 1 == ny - 1) {
+        } else if (EDGE && k - 1 == ny - 1) {
 #pragma unroll
             for (int m = 0; m < CPT; ++m)
                 qsy1[m] = G.outside[m] ? T(0) : border_q<T, VAR>(a, K, SIDE_N, G.i0 + m, h1[m]);
@@ -193,7 +197,7 @@ struct Marcher {
             const T O = (K.dt * out) * K.inv_dx;
             const T hp = fmax(h1[m], T(0));
             const T rr = (O > hp) ? donor_ratio<T>(hp, O) : T(1);
-            r1[m] = (a.positivity && row1_real && !G.outside[m]) ? rr : T(1);
+            r1[m] = (a.positivity && (!EDGE || (row1_real && !G.outside[m]))) ? rr : T(1);
         }
 
         // D: applied discharges: x-faces of row k-1 and y-faces between rows k-2 and k-1.

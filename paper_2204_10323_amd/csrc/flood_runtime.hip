@@ -101,11 +101,13 @@ struct fl_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
 
-    // two-step launches (fl_set_fusion): requested and effective tiling,
-    // outflow partial sums of the first and second step by launch parity
-    int fuse = 1, cpt2_req = 0, rows2_req = 0;
+    // multi-step launches (fl_set_fusion): steps per launch (1, or fuse_k),
+    // the steps per launch of the committed multi-step tiling (0: none),
+    // requested and effective tiling, outflow partial sums of each step of a
+    // launch by launch parity
+    int fuse = 1, fuse_k = 0, cpt2_req = 0, rows2_req = 0;
     int cpt2 = 0, rows2 = 0, nstrips2 = 0, nchunks2 = 0, npart2 = 0;
-    double* d_part2[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* d_part2[2 * kFuseMax] = {};
     hipGraph_t graph2 = nullptr;
     hipGraphExec_t graph2_exec = nullptr;
     int graph2_k = 0;
@@ -396,74 +398,67 @@ hipError_t enqueue_one(fl_ctx* c, long long n, hipStream_t s) {
     return c->prec == FL_F64 ? enqueue_one_t<double>(c, n, s) : enqueue_one_t<float>(c, n, s);
 }
 
-// Work decomposition of the two-step kernel: strip 0 outputs columns
-// [0, W + 2), strip s > 0 columns [s W + 2, (s + 1) W + 2), W = strip_width2.
-Tiling tiling2_of(const fl_ctx* c, int cpt, int rows) {
+// Work decomposition of the k-step kernel: strip 0 outputs columns
+// [0, W + 2k - 2), strip s > 0 columns [s W + 2k - 2, (s + 1) W + 2k - 2),
+// W = strip_width_fused(cpt, k).
+Tiling tiling_fused_of(const fl_ctx* c, int cpt, int rows, int k) {
     Tiling t{cpt, rows, 0, 0, 0};
-    const int w = strip_width2(cpt);
-    t.nstrips = std::max(1, (c->nx - 2 + w - 1) / w);
+    const int w = strip_width_fused(cpt, k);
+    t.nstrips = std::max(1, (c->nx - (2 * k - 2) + w - 1) / w);
     t.nchunks = (c->ny + rows - 1) / rows;
     if (c->out_count > 0)
         t.npart = (c->out_side == FL_WEST || c->out_side == FL_EAST) ? t.nchunks : t.nstrips;
     return t;
 }
 
-// Two-step launch arguments with two-step tiling tl (no active tiles).
+// Launch arguments of k steps per launch with the k-step tiling tl (no
+// active tiles).
 template <typename T>
-Step2Args<T> make_args2_tl(const fl_ctx* c, long long launch, int resolve, const Tiling& tl,
-                           int freeze) {
-    Step2Args<T> A{};
+FusedArgs<T> make_args_fused_tl(const fl_ctx* c, long long launch, int resolve, const Tiling& tl,
+                                int k, int freeze) {
+    FusedArgs<T> A{};
     A.a = make_args<T>(c, 0, tl, freeze);
     for (int p = 0; p < 2; ++p) {
         A.h[p] = (T*)c->d_h[p];
         A.qx[p] = (T*)c->d_qx[p];
         A.qy[p] = (T*)c->d_qy[p];
-        A.part_a[p] = c->d_part2[p];
-        A.part_b[p] = c->d_part2[2 + p];
+        for (int q = 0; q < kFuseMax; ++q) A.part[q][p] = c->d_part2[2 * q + p];
     }
+    A.K = k;
     A.phase = (int)(launch % 6);
     A.resolve = resolve;
     return A;
 }
 
+// Launch arguments of the context's multi-step launches.
 template <typename T>
-Step2Args<T> make_args2(const fl_ctx* c, long long launch, int resolve, int freeze = 0) {
-    Step2Args<T> A{};
+FusedArgs<T> make_args_fused(const fl_ctx* c, long long launch, int resolve, int freeze = 0) {
     const Tiling tl{c->cpt2, c->rows2, c->nstrips2, c->nchunks2, c->npart2};
-    A.a = make_args<T>(c, 0, tl, freeze);
+    FusedArgs<T> A = make_args_fused_tl<T>(c, launch, resolve, tl, c->fuse_k, freeze);
     if (c->active) {
-        // active-tile skipping in the two-step launches (flags by generation)
+        // active-tile skipping in the multi-step launches (flags by generation)
         A.a.act = c->d_act;
         A.a.act_stride = c->act_stride;
     }
-    for (int p = 0; p < 2; ++p) {
-        A.h[p] = (T*)c->d_h[p];
-        A.qx[p] = (T*)c->d_qx[p];
-        A.qy[p] = (T*)c->d_qy[p];
-        A.part_a[p] = c->d_part2[p];
-        A.part_b[p] = c->d_part2[2 + p];
-    }
-    A.phase = (int)(launch % 6);
-    A.resolve = resolve;
     return A;
 }
 
-hipError_t enqueue_two(fl_ctx* c, long long launch, int resolve, hipStream_t s, int freeze = 0) {
+hipError_t enqueue_fused(fl_ctx* c, long long launch, int resolve, hipStream_t s, int freeze = 0) {
     if (c->prec == FL_F64)
-        return launch_step2<double>(make_args2<double>(c, launch, resolve, freeze), c->cpt2, s);
-    return launch_step2<float>(make_args2<float>(c, launch, resolve, freeze), c->cpt2, s);
+        return launch_fused<double>(make_args_fused<double>(c, launch, resolve, freeze), c->cpt2, s);
+    return launch_fused<float>(make_args_fused<float>(c, launch, resolve, freeze), c->cpt2, s);
 }
 
-// K two-step launches with launch counters 0 .. K-1 (K a multiple of 6, so
+// L multi-step launches with launch counters 0 .. L-1 (L a multiple of 6, so
 // the graph can be replayed whenever the counter is a multiple of 6).
 fl_status capture_graph2(fl_ctx* c) {
-    int K = c->params.steps_per_graph > 0 ? c->params.steps_per_graph / 2 : 30;
+    int K = c->params.steps_per_graph > 0 ? c->params.steps_per_graph / c->fuse_k : 60 / c->fuse_k;
     K = std::max(6, ((K + 5) / 6) * 6);
     hipStream_t cs;
     HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_two(c, k, 0, cs);
+        for (int k = 0; k < K && e == hipSuccess; ++k) e = enqueue_fused(c, k, 0, cs);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
@@ -475,7 +470,7 @@ fl_status capture_graph2(fl_ctx* c) {
         }
     }
     (void)hipStreamDestroy(cs);
-    if (e != hipSuccess) return hip_fail(c, e, "graph capture (two-step)");
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture (multi-step)");
     c->graph2_k = K;
     return FL_OK;
 }
@@ -529,12 +524,15 @@ int default_rows(int nx, int ny, int cpt) {
     return (int)std::max<long long>(8, std::min<long long>(32, r));
 }
 
-// Rows per work item of the two-step kernel: like the single-step kernel,
-// at least ~6000 waves on small grids.
-int default_rows2(int nx, int ny, int cpt) {
-    const long long strips = std::max(1, (nx - 2 + strip_width2(cpt) - 1) / strip_width2(cpt));
+// Rows per work item of the k-step kernel: like the single-step kernel, at
+// least ~6000 waves on small grids; on large grids 32 rows at two steps per
+// launch and 48 at three (the 4k + 2 extra rows an item loads weigh more;
+// both measured best on MI355X at 16384^2).
+int default_rows_fused(int nx, int ny, int cpt, int k) {
+    const int w = strip_width_fused(cpt, k);
+    const long long strips = std::max(1, (nx - (2 * k - 2) + w - 1) / w);
     const long long r = (long long)ny * strips / 6144;
-    return (int)std::max<long long>(8, std::min<long long>(32, r));
+    return (int)std::max<long long>(8, std::min<long long>(k >= 3 ? 48 : 32, r));
 }
 
 // Fold the last step's outflow partial sums into the clock (see k_fold).
@@ -553,7 +551,7 @@ fl_status fold_budget(fl_ctx* c, const Tiling& tl) {
 // Flag bytes per step slot of active-tile skipping: enough for the smallest
 // work items of either kernel (one cell per lane, one row).
 long long act_slot_bytes(int nx, int ny) {
-    const int w = std::min(strip_width(1), strip_width2(1));
+    const int w = std::min(strip_width(1), strip_width_fused(1, 2));
     return (long long)((nx + w - 1) / w) * ny;
 }
 
@@ -577,7 +575,7 @@ size_t workspace_bytes(int nx, int ny, fl_precision prec, bool two_step, bool ac
     b += 2 * ws_round(sizeof(double) * side);
     b += 2 * ws_round(sizeof(double) * 4096);
     b += ws_round(sizeof(double) * kVolumeParts) + ws_round(sizeof(double)) + ws_round(sizeof(DevCtl));
-    if (two_step) b += 4 * ws_round(sizeof(double) * side);
+    if (two_step) b += 2 * kFuseMax * ws_round(sizeof(double) * side);
     if (active)
         b += ws_round((size_t)(3 * act_slot_bytes(nx, ny))) +
              ws_round(sizeof(int) * (size_t)act_list_ints(nx, ny)) + ws_round(18 * sizeof(unsigned));
@@ -592,10 +590,12 @@ fl_status do_commit(fl_ctx* c) {
     free_device(c);
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
-    if (c->variant && (c->fuse == 2 || c->active))
+    if (c->variant && (c->fuse >= 2 || c->active))
         return fail(c, FL_EINVAL,
                     "fl_commit: method variants run one step per launch without active tiles");
-    if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse == 2, c->active != 0))
+    if (c->active && c->fuse >= 3)
+        return fail(c, FL_EINVAL, "fl_commit: active tiles run one or two steps per launch");
+    if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse >= 2, c->active != 0))
         return fail(c, FL_EINVAL, "fl_commit: the bound workspace is smaller than fl_workspace_bytes");
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
     c->rows = c->rows_req ? c->rows_req : default_rows(nx, ny, c->cpt);
@@ -722,13 +722,16 @@ fl_status do_commit(fl_ctx* c) {
         }
     }
     if ((st = capture_graph(c))) return st;
-    if (c->fuse == 2) {
+    c->fuse_k = c->fuse >= 2 ? c->fuse : 0;
+    if (c->fuse_k) {
         c->cpt2 = c->cpt2_req ? c->cpt2_req : (c->prec == FL_F64 ? 1 : 2);
-        c->rows2 = c->rows2_req ? c->rows2_req : default_rows2(nx, ny, c->cpt2);
+        if (c->cpt2 == 4 && c->fuse_k != 2)
+            return fail(c, FL_EINVAL, "fl_commit: 4 cells per lane run two steps per launch at most");
+        c->rows2 = c->rows2_req ? c->rows2_req : default_rows_fused(nx, ny, c->cpt2, c->fuse_k);
         if (c->active && c->rows2 < 2)
             return fail(c, FL_EINVAL,
                         "fl_commit: active tiles with two steps per launch need items of >= 2 rows");
-        const Tiling t2 = tiling2_of(c, c->cpt2, c->rows2);
+        const Tiling t2 = tiling_fused_of(c, c->cpt2, c->rows2, c->fuse_k);
         c->nstrips2 = t2.nstrips;
         c->nchunks2 = t2.nchunks;
         c->npart2 = t2.npart;
@@ -770,12 +773,13 @@ fl_status enqueue_steps(fl_ctx* c, long long nsteps) {
     return FL_OK;
 }
 
-// nsteps steps by two-step launches.  The single-step state (budget folded)
-// becomes the two-step clock; about nsteps/2 launches follow, then one that
-// only settles the last launch's speculated dt (redoing it if needed); the
-// claimed count is read back, and further rounds run if redone or one-step
-// launches left steps over.  Finally the state becomes the single-step state
-// again, at a step counter whose parity names the buffer that holds it.
+// nsteps steps by multi-step launches of k = fuse_k steps.  The single-step
+// state (budget folded) becomes the multi-step clock; about nsteps/k launches
+// follow, then one that only settles the last launch's speculated dts
+// (redoing it if needed); the claimed count is read back, and further rounds
+// run if redos or shorter launches left steps over.  Finally the state
+// becomes the single-step state again, at a step counter whose parity names
+// the buffer that holds it.
 template <typename T>
 fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
     fl_status st;
@@ -787,10 +791,10 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
     // the state since; otherwise compute every item in the first two launches
     const bool keep = c->active && c->act_mode == 2 && c->act_at == c->nstep;
     if (c->active && !keep) HIP_TRY(c, launch_fill_bytes(c->d_act, 3 * c->act_stride, 1, c->stream));
-    HIP_TRY(c, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, keep ? 1 : 0, c->stream));
+    HIP_TRY(c, launch_enter_fused<T>(make_args<T>(c, c->nstep), nsteps, keep ? 1 : 0, c->stream));
     long long lc = 0;
-    long long want = (nsteps + 1) / 2;
-    Clock2 slot{};
+    long long want = (nsteps + c->fuse_k - 1) / c->fuse_k;
+    FusedClock slot{};
     for (int round = 0;; ++round) {
         while (want > 0) {
             if (!freeze && c->graph2_exec && lc % 6 == 0 && want >= c->graph2_k) {
@@ -798,24 +802,24 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
                 lc += c->graph2_k;
                 want -= c->graph2_k;
             } else {
-                HIP_TRY(c, enqueue_two(c, lc, 0, c->stream, freeze));
+                HIP_TRY(c, enqueue_fused(c, lc, 0, c->stream, freeze));
                 lc += 1;
                 want -= 1;
             }
         }
-        HIP_TRY(c, enqueue_two(c, lc, 1, c->stream, freeze));
+        HIP_TRY(c, enqueue_fused(c, lc, 1, c->stream, freeze));
         lc += 1;
-        HIP_TRY(c, hipMemcpyAsync(&slot, &c->d_ctl->c2[lc & 1], sizeof(slot), hipMemcpyDeviceToHost,
+        HIP_TRY(c, hipMemcpyAsync(&slot, &c->d_ctl->cf[lc & 1], sizeof(slot), hipMemcpyDeviceToHost,
                                   c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (slot.pending) return fail(c, FL_EHIP, "two-step launches: unsettled state");
+        if (slot.pending) return fail(c, FL_EHIP, "multi-step launches: unsettled state");
         if (slot.vsteps >= nsteps) break;
-        if (round >= 64) return fail(c, FL_EHIP, "two-step launches: no progress");
+        if (round >= 64) return fail(c, FL_EHIP, "multi-step launches: no progress");
         want = nsteps - slot.vsteps;  // enough even if every launch makes one step
     }
     long long n2 = c->nstep + nsteps;
     n2 += (n2 ^ (long long)slot.cur) & 1;
-    HIP_TRY(c, launch_leave2<T>(make_args<T>(c, n2), make_args2<T>(c, 0, 0), lc, c->stream));
+    HIP_TRY(c, launch_leave_fused<T>(make_args<T>(c, n2), make_args_fused<T>(c, 0, 0), lc, c->stream));
     c->nstep = n2;
     if (c->active) {
         c->act_mode = 2;
@@ -825,7 +829,7 @@ fl_status fused_steps_t(fl_ctx* c, long long nsteps, int freeze = 0) {
 }
 
 fl_status run_steps(fl_ctx* c, long long nsteps) {
-    if (c->fuse == 2 && nsteps >= 2)
+    if (c->fuse >= 2 && c->fuse_k >= 2 && nsteps >= 2)
         return c->prec == FL_F64 ? fused_steps_t<double>(c, nsteps) : fused_steps_t<float>(c, nsteps);
     return enqueue_steps(c, nsteps);
 }
@@ -1156,8 +1160,8 @@ fl_status fl_set_tiling(fl_ctx* c, int32_t cells_per_lane, int32_t rows_per_item
 fl_status fl_set_fusion(fl_ctx* c, int32_t steps_per_launch, int32_t cells_per_lane,
                         int32_t rows_per_item) {
     if (!c) return FL_EINVAL;
-    if (steps_per_launch != 1 && steps_per_launch != 2)
-        return fail(c, FL_EINVAL, "fl_set_fusion: steps_per_launch must be 1 or 2");
+    if (steps_per_launch < 1 || steps_per_launch > kFuseMax)
+        return fail(c, FL_EINVAL, "fl_set_fusion: steps_per_launch must be 1, 2 or 3");
     if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
         return fail(c, FL_EINVAL, "fl_set_fusion: cells_per_lane must be 1, 2 or 4");
     if (c->prec == FL_F64 && cells_per_lane == 4)
@@ -1195,14 +1199,14 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
     if (!c->committed || !c->active)
         return fail(c, FL_ESTATE, "fl_active_items needs a context committed with active tiles on");
     HIP_TRY(c, hipSetDevice(c->device));
-    if (c->fuse == 2 && c->act_mode == 2 && c->act_at == c->nstep) {
+    if (c->fuse == 2 && c->fuse_k == 2 && c->act_mode == 2 && c->act_at == c->nstep) {
         // the next two-step launch: the rule of the two-step kernel's skip test
         const int ns = c->nstrips2, nc = c->nchunks2;
         const long long items = (long long)ns * nc;
         *total_items = items;
         long long gen = 0;
         std::vector<unsigned char> f1((size_t)items), f2((size_t)items);
-        HIP_TRY(c, hipMemcpyAsync(&gen, &c->d_ctl->gen2, sizeof(gen), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(&gen, &c->d_ctl->genf, sizeof(gen), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         const long long g = gen + 1;
         HIP_TRY(c, hipMemcpyAsync(f1.data(), c->d_act + ((g + 2) % 3) * c->act_stride, (size_t)items,
@@ -1210,7 +1214,7 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
         HIP_TRY(c, hipMemcpyAsync(f2.data(), c->d_act + ((g + 1) % 3) * c->act_stride, (size_t)items,
                                   hipMemcpyDeviceToHost, c->stream));  // generation g - 2
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        const int wl = 64 * c->cpt2, wo = strip_width2(c->cpt2);
+        const int wl = 64 * c->cpt2, wo = strip_width_fused(c->cpt2, 2);
         const int f0 = c->in_first, fe = c->in_first + c->in_count;
         long long need = 0;
         for (int cc = 0; cc < nc; ++cc)
@@ -1495,7 +1499,8 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     if (!c) return FL_EINVAL;
     if (!c->committed) return fail(c, FL_ESTATE, "fl_autotune_fusion before fl_commit");
     if (!c->d_part2[0] || !c->graph2_exec)
-        return fail(c, FL_ESTATE, "fl_autotune_fusion: commit with fl_set_fusion(ctx, 2, ...) first");
+        return fail(c, FL_ESTATE,
+                    "fl_autotune_fusion: commit with fl_set_fusion(ctx, 2 or 3, ...) first");
     if (trial_steps < 2) return fail(c, FL_EINVAL, "fl_autotune_fusion: trial_steps < 2");
     HIP_TRY(c, hipSetDevice(c->device));
     fl_status st;
@@ -1530,8 +1535,9 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     HIP_TRY(c, hipEventElapsedTime(&ms1, e0.e, e1.e));
     if ((st = fold_budget(c, tl))) return st;
     c->act_at = -1;
-    // two steps per launch, as fl_step runs them (entry, launches, settling,
-    // exit); with active tiles after an untimed run that sets the flags
+    // fuse_k steps per launch, as fl_step runs them (entry, launches,
+    // settling, exit); with active tiles after an untimed run that sets the
+    // flags
     if (c->active) {
         st = c->prec == FL_F64 ? fused_steps_t<double>(c, 4, 1) : fused_steps_t<float>(c, 4, 1);
         if (st) return st;
@@ -1543,9 +1549,9 @@ fl_status fl_autotune_fusion(fl_ctx* c, int32_t trial_steps, int32_t* steps_per_
     HIP_TRY(c, hipEventRecord(e1.e, c->stream));
     HIP_TRY(c, hipEventSynchronize(e1.e));
     HIP_TRY(c, hipEventElapsedTime(&ms2, e0.e, e1.e));
-    c->fuse = (ms2 < ms1) ? 2 : 1;
+    c->fuse = (ms2 < ms1) ? c->fuse_k : 1;
     if (steps_per_launch) *steps_per_launch = c->fuse;
-    if (ms_per_step) *ms_per_step = (c->fuse == 2 ? ms2 : ms1) / trial_steps;
+    if (ms_per_step) *ms_per_step = (c->fuse >= 2 ? ms2 : ms1) / trial_steps;
     return FL_OK;
 }
 
@@ -2210,13 +2216,13 @@ fl_status batch_launch_noalloc(fl_batch* b, long long nsteps) {
     return batch_execute<T>(b, nsteps, 0, nullptr, ba, hs, d_scen, d_sync, d_error);
 }
 
-// Can the members run two steps per queue entry?  They need the two-step
-// buffers (committed after fl_set_fusion(ctx, 2, ...)) and no active tiles.
+// Can the members run two steps per queue entry?  They need the multi-step
+// buffers (committed after fl_set_fusion(ctx, 2 or 3, ...)) and no active tiles.
 fl_status batch_check_two_step(fl_batch* b) {
     for (fl_ctx* c : b->members) {
         if (!c->d_part2[0])
             return bfail(b, FL_ESTATE, "two steps per queue entry: every member must be committed "
-                                       "after fl_set_fusion(ctx, 2, ...)");
+                                       "after fl_set_fusion(ctx, 2 or 3, ...)");
         if (c->active)
             return bfail(b, FL_EINVAL, "two steps per queue entry: members with active tiles run "
                                        "one step per entry");
@@ -2242,7 +2248,7 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     }
     for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
     for (fl_ctx* c : b->members)
-        BHIP_TRY(b, launch_enter2<T>(make_args<T>(c, c->nstep), nsteps, 0, b->stream));
+        BHIP_TRY(b, launch_enter_fused<T>(make_args<T>(c, c->nstep), nsteps, 0, b->stream));
     // bin-pack onto the XCDs as the one-step batch does
     const int nxcc = batch_xccs(b);
     long long load[kMaxXcc] = {};
@@ -2265,9 +2271,10 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
             const int m = b->order[k];
             if (b->member_xcd[m] != x) continue;
             fl_ctx* c = b->members[m];
-            const Tiling tl = tiling2_of(c, b->cpt2, b->rows2);
+            const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, 2);
             for (int res = 0; res < 2; ++res)
-                for (int ph = 0; ph < 6; ++ph) scen[idx].a2[res][ph] = make_args2_tl<T>(c, ph, res, tl, freeze);
+                for (int ph = 0; ph < 6; ++ph)
+                    scen[idx].a2[res][ph] = make_args_fused_tl<T>(c, ph, res, tl, 2, freeze);
             scen[idx].items = tl.nstrips * tl.nchunks;
             scen[idx].first = first;
             first += 1 + scen[idx].items;
@@ -2296,7 +2303,7 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         BHIP_TRY(b, hipEventCreate(&e1.e));
         BHIP_TRY(b, hipEventRecord(e0.e, b->stream));
     }
-    std::vector<Clock2> slot(S);
+    std::vector<FusedClock> slot(S);
     long long lc = 0, want = (nsteps + 1) / 2;
     for (int round = 0;; ++round) {
         BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(b->d_sync),
@@ -2312,7 +2319,7 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         int error = 0;
         BHIP_TRY(b, hipMemcpyAsync(&error, b->d_error, sizeof(int), hipMemcpyDeviceToHost, b->stream));
         for (int m = 0; m < S; ++m)
-            BHIP_TRY(b, hipMemcpyAsync(&slot[m], &b->members[m]->d_ctl->c2[lc & 1], sizeof(Clock2),
+            BHIP_TRY(b, hipMemcpyAsync(&slot[m], &b->members[m]->d_ctl->cf[lc & 1], sizeof(FusedClock),
                                        hipMemcpyDeviceToHost, b->stream));
         BHIP_TRY(b, hipStreamSynchronize(b->stream));
         if (error) return bfail(b, FL_EHIP, "fl_batch_run: a wait for a member's previous launch timed out");
@@ -2328,11 +2335,11 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     if (ms) BHIP_TRY(b, hipEventElapsedTime(ms, e0.e, e1.e));
     for (int m = 0; m < S; ++m) {
         fl_ctx* c = b->members[m];
-        const Tiling tl = tiling2_of(c, b->cpt2, b->rows2);
+        const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, 2);
         long long n2 = c->nstep + nsteps;
         n2 += (n2 ^ (long long)slot[m].cur) & 1;
-        BHIP_TRY(b, launch_leave2<T>(make_args<T>(c, n2), make_args2_tl<T>(c, 0, 0, tl, 0), lc,
-                                     b->stream));
+        BHIP_TRY(b, launch_leave_fused<T>(make_args<T>(c, n2), make_args_fused_tl<T>(c, 0, 0, tl, 2, 0),
+                                          lc, b->stream));
         c->nstep = n2;
     }
     BHIP_TRY(b, hipStreamSynchronize(b->stream));

@@ -20,7 +20,8 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-@pytest.mark.parametrize("name", ["k_step2_valley16384_prewetted_pmc.md", "k_step_valley16384_pmc.md"])
+@pytest.mark.parametrize("name", sorted(os.path.basename(p) for p in __import__("glob").glob(
+    os.path.join(ROOT, "profiles", "k_*_pmc.md"))))
 def test_pmc_summaries_parse(name):
     """The machine-readable block bench.py takes roofline.traffic from."""
     txt = open(os.path.join(ROOT, "profiles", name)).read()

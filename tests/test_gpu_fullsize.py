@@ -36,10 +36,10 @@ def d3_dry():
     return synth.config_d3(N, wet=False)
 
 
-@pytest.mark.parametrize("spl", [2, 1])
+@pytest.mark.parametrize("spl", [3, 2, 1])
 def test_valley16384_dry_1000_steps_full_grid(d3_dry, spl):
-    """spl = 2 is the benchmark's launch configuration (two steps per launch,
-    default tiling); spl = 1 the single-step kernel."""
+    """spl = 3 is the benchmark's launch configuration (three steps per launch,
+    default tiling); spl = 2 two steps per launch, 1 the single-step kernel."""
     sc = d3_dry
     print(f"CASE fullsize dry 1000 steps, {spl} step(s) per launch", flush=True)
     f = fl.from_scenario(sc, "f32", fusion=spl)
@@ -86,18 +86,26 @@ def _prewetted(sc):
 
 
 def test_valley16384_prewetted_24_steps_full_grid(d3_dry):
-    """The benchmark's headline workload and launch configuration (two steps per
-    launch, default tiling, speculated second dt): 12 launches, every cell and
-    face against the oracle run on the whole grid."""
+    """The benchmark's headline workload and launch configuration (three steps
+    per launch, default tiling, speculated later dts): 8 launches, every cell
+    and face against the oracle run on the whole grid; two steps per launch
+    give the same bits."""
     wet = _prewetted(d3_dry)
-    print("CASE fullsize prewetted 24 steps", flush=True)
-    f = fl.from_scenario(wet, "f32", fusion=2)
-    f.step(24)
-    h = f.get_depth()
-    qx, qy = f.get_discharge()
-    r = f.get_report()
-    f.close()
-    del f
+    got = {}
+    for spl in (3, 2):
+        print(f"CASE fullsize prewetted 24 steps, {spl} steps per launch", flush=True)
+        f = fl.from_scenario(wet, "f32", fusion=spl)
+        f.step(24)
+        h = f.get_depth()
+        qx, qy = f.get_discharge()
+        r = f.get_report()
+        f.close()
+        del f
+        got[spl] = (h, qx, qy, r)
+    for a, b in zip(got[3][:3], got[2][:3]):
+        assert np.array_equal(a, b)
+    assert got[3][3].t == got[2][3].t and got[3][3].v_in == got[2][3].v_in
+    h, qx, qy, r = got[3]
     o = oracle.Run(wet)
     o.step(24)
     assert (o.h > 0).mean() > 0.2
@@ -110,9 +118,10 @@ def test_valley16384_prewetted_24_steps_full_grid(d3_dry):
     assert r.budget_error() <= 1e-6
 
 
-def test_valley16384_prewetted_1000_steps_against_oracle_golden(d3_dry):
+@pytest.mark.parametrize("spl", [3, 2])
+def test_valley16384_prewetted_1000_steps_against_oracle_golden(d3_dry, spl):
     """The headline workload for its stated 1000 steps, in the benchmark's launch
-    configuration, against the oracle's stored depths and face discharges
+    configuration (spl = 3; also 2), against the oracle's stored depths and face discharges
     (tests/golden/make_d3wet_golden.py) on a lattice of every 64th cell and four
     dense 256 x 256 blocks (inflow, mid-valley channel, outflow edge, shoreline)."""
     sys.path.insert(0, os.path.join(HERE, "golden"))
@@ -120,8 +129,8 @@ def test_valley16384_prewetted_1000_steps_against_oracle_golden(d3_dry):
     g = np.load(os.path.join(HERE, "golden", "d3wet_16384_1000.npz"))
     wet = _prewetted(d3_dry)
     assert input_hash(wet) == str(g["input_sha256"]), "the input generator changed"
-    print("CASE fullsize prewetted 1000 steps", flush=True)
-    f = fl.from_scenario(wet, "f32", fusion=2)
+    print(f"CASE fullsize prewetted 1000 steps, {spl} steps per launch", flush=True)
+    f = fl.from_scenario(wet, "f32", fusion=spl)
     f.step(1000)
     h = f.get_depth()
     qx, qy = f.get_discharge()
