@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 BYTES_PER_CELL = {"f32": 32, "f64": 64}   # read h z n qx qy, write h qx qy
 CSRC = os.path.join(ROOT, "paper_2204_10323_amd", "csrc")
 # the sources that make the step kernels' code
-KERNEL_SRCS = ["flood_device.h", "flood_march.h", "flood_kernels.hip", "flood_fused.hip"]
+KERNEL_SRCS = ["flood_internal.h", "flood_device.h", "flood_march.h", "flood_kernels.hip",
+               "flood_fused.hip"]
 # committed PMC summaries of the dominant kernel, by steps per launch
 PMC_SUMMARY = {1: os.path.join(ROOT, "profiles", "k_step_valley16384_pmc.md"),
                2: os.path.join(ROOT, "profiles", "k_fused2_valley16384_prewetted_pmc.md"),
@@ -43,6 +44,24 @@ def kernel_hash() -> str:
     for name in KERNEL_SRCS:
         h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
+
+
+# SQ counters of the dominant kernel (VALU busy): what bounds it
+SQ_SUMMARY = {3: os.path.join(ROOT, "profiles", "k_fused3_valley16384_prewetted_sq_counters.md")}
+
+
+def measured_valu_busy(fusion: int):
+    """VALU busy of the dominant kernel from the committed SQ-counter summary,
+    if it was taken on the current kernel sources; else None."""
+    try:
+        txt = open(SQ_SUMMARY[fusion]).read()
+    except (OSError, KeyError):
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", txt, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    return d.get("valu_busy") if d.get("kernel_sha256_16") == kernel_hash() else None
 
 
 def measured_traffic(cells: int, fusion: int, workload: str):
@@ -561,7 +580,10 @@ def main():
                                       if traffic else None),
                      # what a kernel making one pass per step would have to move
                      # for the same rate: a cell-update equivalent, not HBM bytes
-                     "one_pass_per_step_equivalent_gbs": round(achieved * args.fusion, 1)},
+                     "one_pass_per_step_equivalent_gbs": round(achieved * args.fusion, 1),
+                     # SQ counters of the same kernel (committed profile, current sources
+                     # only): the fraction of cycles its SIMDs issue VALU instructions
+                     "valu_busy": measured_valu_busy(args.fusion) if f32 else None},
     }
     extras = {"wall_s_timed_region": round(wall, 4), "input_generation_s": round(t_gen, 1),
               "device_bytes": dev_bytes, "budget_error": rep.budget_error(),
