@@ -304,11 +304,7 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
     t.adj_setup(gauges, obs_every)
     obs, _ = t.adj_forward(steps)
     t.close()
-    # the forward runs between checkpoints and observations with the fastest
-    # plain launch mode (the same states whatever the mode); the recompute and
-    # the reverse sweep use single steps of the autotuned tiling
-    fwd_spl = min((plain_ms, 1), (plain2_ms, 2), (plain3_ms, 3))[1]
-    m = fl.from_scenario(sc, "f32", stream=stream, fusion=fwd_spl)
+    m = fl.from_scenario(sc, "f32", stream=stream)
     m.autotune(SMALL_GRID_TILINGS, 10)
     m.adj_setup(gauges, obs_every, obs)
     torch.cuda.synchronize()
@@ -322,7 +318,6 @@ def run_adjoint(fl, torch, steps: int = 5000, nx: int = 1024, ngauges: int = 500
             "observations": steps // obs_every, "checkpoints": int(np.ceil(steps / np.ceil(np.sqrt(steps)))),
             "loss": loss, "grad_n_nonzero": int((gn != 0).sum()), "grad_q_norm": float(np.linalg.norm(gq)),
             "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
-            "forward_steps_per_launch": fwd_spl,
             "adjoint_gcell_s": round(cells * steps / (t2 - t0) / 1e9, 3),
             "plain_tiling_autotuned": list(best),
             "plain_gcell_s": round(cells * steps / (plain_ms / 1e3) / 1e9, 3),

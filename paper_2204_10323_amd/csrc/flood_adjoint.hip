@@ -69,7 +69,7 @@ __device__ __forceinline__ FaceFwd<float> face_fwd<float>(float hL, float hR, fl
     FaceFwd<float> f;
     f.qs = f.Pq = f.PL = f.PR = f.Pn = 0.0f;
     const float etaL = hL + zL, etaR = hR + zR;
-    const float hf = fmaxf(etaL, etaR) - fmaxf(zL, zR);
+    const float hf = maxv(etaL, etaR) - maxv(zL, zR);
     if (hf <= h_eps) return f;
     // the forward value, operation for operation (face_q<float>)
     const float nf = 0.5f * (nL + nR);

@@ -261,6 +261,39 @@ __device__ __forceinline__ T face_q(T etaL, T etaR, T zL, T zR, T nL, T nR, T q,
     return num / den;
 }
 
+// Maxima on the hot path.  For fmax the compiler first "canonicalises" every
+// operand it cannot prove canonical (a value straight from memory, a lane
+// move, a loop-carried register) with v_max_f32 x, x, x, which only quiets a
+// signalling NaN: about 16 instructions per marcher row.  v_max_f32 itself
+// already returns the other operand for a quiet NaN and a quiet NaN for a
+// signalling one, which is what fmax returns, so FP32 takes it directly (the
+// same instruction the compiler emits for fmax, minus the canonicalisation).
+template <typename T>
+__device__ __forceinline__ T maxv(T a, T b) { return fmax(a, b); }
+template <>
+__device__ __forceinline__ float maxv<float>(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// max(0, a) and max(0, -a)
+template <typename T>
+__device__ __forceinline__ T max0(T a) { return fmax(T(0), a); }
+template <>
+__device__ __forceinline__ float max0<float>(float a) {
+    float r;
+    asm("v_max_f32 %0, 0, %1" : "=v"(r) : "v"(a));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T max0_neg(T a) { return fmax(T(0), -a); }
+template <>
+__device__ __forceinline__ float max0_neg<float>(float a) {
+    float r;
+    asm("v_max_f32_e64 %0, 0, -%1" : "=v"(r) : "v"(a));
+    return r;
+}
+
 // FP32 face update: the same formula with h_f^(-7/3) = 2^(-(7/3) log2 h_f)
 // and the quotient by the hardware reciprocal (v_log_f32, v_exp_f32,
 // v_rcp_f32, about one ulp each) instead of cbrt and two correctly rounded
@@ -270,7 +303,7 @@ template <>
 __device__ __forceinline__ float face_q<float>(float etaL, float etaR, float zL, float zR,
                                                float nL, float nR, float q, float gdt,
                                                float inv_dx, float h_eps) {
-    float hf = fmaxf(etaL, etaR) - fmaxf(zL, zR);
+    float hf = maxv(etaL, etaR) - maxv(zL, zR);
     if (hf <= h_eps) return 0.0f;
     float nf = 0.5f * (nL + nR);
     float grad = (etaR - etaL) * inv_dx;

@@ -190,12 +190,12 @@ struct Marcher {
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
             const T qW = (m > 0) ? qsx1[(m + CPT - 1) % CPT] : qWn;
-            T out = fmax(T(0), -qW);
-            out += fmax(T(0), qsx1[m]);
-            out += fmax(T(0), -qsy2[m]);
-            out += fmax(T(0), qsy1[m]);
+            T out = max0_neg(qW);
+            out += max0(qsx1[m]);
+            out += max0_neg(qsy2[m]);
+            out += max0(qsy1[m]);
             const T O = (K.dt * out) * K.inv_dx;
-            const T hp = fmax(h1[m], T(0));
+            const T hp = max0(h1[m]);
             const T rr = (O > hp) ? donor_ratio<T>(hp, O) : T(1);
             r1[m] = (a.positivity && (!EDGE || (row1_real && !G.outside[m]))) ? rr : T(1);
         }

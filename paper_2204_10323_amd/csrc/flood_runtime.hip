@@ -1872,9 +1872,9 @@ fl_status adj_forward_t(fl_ctx* c, long long N, void* series_out, int on_device,
         const long long next_ck = (k / C + 1) * C;
         const long long next_obs = (k / c->obs_every + 1) * c->obs_every;
         const long long next = std::min(std::min(next_ck, next_obs), N);
-        // between checkpoints and observations the context's own launches
-        // (several steps per launch if committed so: the same states)
-        if ((st = run_steps(c, next - k))) return st;
+        // single-step launches: the step counter (buffer parity and clock
+        // slots) must advance by exactly one per step for the recompute
+        if ((st = enqueue_steps(c, next - k))) return st;
         k = next;
         if (k % c->obs_every == 0 && k / c->obs_every <= nobs) {
             const long long o = k / c->obs_every - 1;

@@ -162,30 +162,26 @@ def test_fp64_gpu_adjoint_matches_finite_differences():
     assert max(abs(a - fd) for a, fd in pairs) <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_forward_with_multi_step_launches_gives_the_same_gradients(prec):
-    """A context committed with two or three steps per launch runs the forward
-    between checkpoints and observations with those launches: the same states,
-    so the same gauge series, loss and gradients, bit for bit."""
-    sc = _valley_scen(nx=130, ny=90)
-    if prec == "f32":
-        sc = _cast(sc, np.float32)
+def test_forward_of_a_multi_step_context_gives_the_same_gradients():
+    """A context committed with three steps per launch still makes the reverse
+    mode's forward with single steps (the recompute relies on the step
+    counter): the same series, loss and gradients, bit for bit."""
+    sc = _cast(_valley_scen(nx=130, ny=90), np.float32)
     rng = np.random.default_rng(9)
     gauges = rng.choice(sc.nx * sc.ny, NG, replace=False)
     obs = rng.uniform(0.0, 0.5, (N // OBS_EVERY, NG))
     out = {}
-    for k in (1, 2, 3):
-        print(f"CASE adjoint forward {prec} k={k}", flush=True)
-        f = fl.from_scenario(sc, prec, fusion=k)
+    for k in (1, 3):
+        print(f"CASE adjoint forward k={k}", flush=True)
+        f = fl.from_scenario(sc, "f32", fusion=k)
         f.adj_setup(gauges, OBS_EVERY, obs.astype(f.dtype), 7)
         series, loss = f.adj_forward(N)
         gn, gq = f.adj_backward(None, len(sc.inflow[5]))
         h = f.get_depth()
         f.close()
         out[k] = (series, loss, gn, gq, h)
-    for k in (2, 3):
-        for a, b in zip(out[k], out[1]):
-            assert np.array_equal(np.asarray(a), np.asarray(b)), k
+    for a, b in zip(out[3], out[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
 def test_context_continues_after_the_backward_sweep():
