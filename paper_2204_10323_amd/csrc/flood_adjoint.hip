@@ -1,8 +1,7 @@
-// Reverse of one fixed-dt flood step on the GPU (gather form: every thread
-// owns one cell and collects what it needs from its four faces and
-// neighbours; no atomics).  Used by the checkpointed adjoint of the runtime to
-// obtain gradients of a gauge misfit with respect to the per-cell Manning n
-// and the inflow hydrograph samples.
+// Reverse of one fixed-dt flood step on the GPU (every cell's adjoints are
+// written by the one lane that owns it; no atomics).  Used by the checkpointed
+// adjoint of the runtime to obtain gradients of a gauge misfit with respect to
+// the per-cell Manning n and the inflow hydrograph samples.
 //
 // For the adjoints lh', lq' of the new state (the step computes the boundary
 // faces (eq. 5, 6), then eq. (3) on the interior faces, then donor-cell
@@ -12,9 +11,13 @@
 //   mu*_f = mu_f r_d + nu_d sign(q*_f),  nu_d = rho_d dr_d/dO_d * dt/dx
 //   lh_c  = lh'_c + rho_c dr_c/dh_c + sum_f mu*_f dq*_f/dh_c
 //   lq_f  = mu*_f dq*_f/dq_f,     dL/dn_c += sum_f mu*_f dq*_f/dn_c
-// Pass A computes r, nu and rho dr/dh per cell; pass B the adjoints and the
-// Manning gradient; a one-wave pass carries the inflow section through the
-// water level W of eq. (6) to Q(t) and to the section's roughness.
+// One row-marching pass per reversed step computes both: each wave marches
+// up a strip, evaluates every face once (the forward value and its
+// derivatives), gets r, nu and rho dr/dh of a row as soon as the faces around
+// it exist, and the adjoints and the Manning gradient of the row below that,
+// keeping all of it in registers (no round trip through memory between the
+// two).  A one-wave pass carries the inflow section through the water level W
+// of eq. (6) to Q(t) and to the section's roughness.
 // The forward quantities are recomputed with the step's own device
 // functions, so the branches (dry face, limiter, donor) match the forward.
 #include <math.h>
@@ -123,138 +126,252 @@ __device__ __forceinline__ T outflow_fwd(const AdjArgs<T>& a, int side, int pos,
     return ws ? v : -v;
 }
 
-// The four faces of cell (i, j): 0 W, 1 E, 2 S, 3 N.  Neighbour offset, the
-// face's discharge offset, whether the cell is the face's left cell, side.
-struct FaceGeo {
-    long long nb, fq;
-    bool cell_is_L;
-    int side, pos;
-    bool border;
+// A face of the reversed step: its forward value q*, the derivatives of q*
+// (eq. 3: dq*/dq, dq*/dh_L, dq*/dh_R, dq*/dn_f; an outflow border face: its
+// derivatives in the edge cell's depth in PL or PR and in the cell's n in Pn)
+// and mu = lq'_f + dt/dx (lh'_R - lh'_L).
+template <typename T>
+struct AFace {
+    T qs, Pq, PL, PR, Pn, mu;
 };
 
-__device__ __forceinline__ FaceGeo face_geo(int f, long long o, long long P, int i, int j, int nx,
-                                            int ny, const long long* qoff) {
-    FaceGeo g;
-    switch (f) {
-    case 0: g = {o - 1, o - 1, false, SIDE_W, j, i == 0}; break;
-    case 1: g = {o + 1, o, true, SIDE_E, j, i == nx - 1}; break;
-    case 2: g = {o - P, o - P, false, SIDE_S, i, j == 0}; break;
-    default: g = {o + P, o, true, SIDE_N, i, j == ny - 1}; break;
-    }
-    (void)qoff;
-    return g;
+template <typename T>
+__device__ __forceinline__ AFace<T> aface_prev(const AFace<T>& e) {
+    AFace<T> f;
+    f.qs = from_prev(e.qs);
+    f.Pq = from_prev(e.Pq);
+    f.PL = from_prev(e.PL);
+    f.PR = from_prev(e.PR);
+    f.Pn = from_prev(e.Pn);
+    f.mu = from_prev(e.mu);
+    return f;
 }
 
-// Pass A: per cell, the donor factor r of the forward step, and the
-// limiter's adjoint terms nu = rho dr/dO dt/dx and kappa = rho dr/dh.
-// An extra block column runs the inflow pass of the step reversed just
-// before (its pass B is complete; pass A reads nothing that pass touches), so
-// it overlaps this pass instead of following the previous one.
+// The face between cells L and R (R on the +axis side).  lq: the adjoint of
+// the face's new value; real_L/real_R: whether L and R lie in the grid; for a
+// border face the edge cell's side and position along it.
 template <typename T>
-__device__ void adj_inflow(const AdjArgs<T>& a, double t);
+__device__ __forceinline__ AFace<T> aface(const AdjArgs<T>& a, T hL, T hR, T zL, T zR, T nL, T nR,
+                                          T q, T lq, T lhL, T lhR, bool real_L, bool real_R,
+                                          int side, int pos, T gdt, T inv_dx, T h_eps, T dtdx) {
+    AFace<T> f;
+    f.qs = f.Pq = f.PL = f.PR = f.Pn = T(0);
+    f.mu = lq + dtdx * (lhR - lhL);
+    if (real_L && real_R) {
+        const FaceFwd<T> F = face_fwd<T>(hL, hR, zL, zR, nL, nR, q, gdt, inv_dx, h_eps);
+        f.qs = F.qs;
+        f.Pq = F.Pq;
+        f.PL = F.PL;
+        f.PR = F.PR;
+        f.Pn = F.Pn;
+    } else if (real_L != real_R) {
+        if (border_kind(a, side, pos) == F_OUT) {
+            T d_dh, d_dn;
+            if (real_L) {
+                f.qs = outflow_fwd(a, side, pos, hL, nL, d_dh, d_dn);
+                f.PL = d_dh;
+            } else {
+                f.qs = outflow_fwd(a, side, pos, hR, nR, d_dh, d_dn);
+                f.PR = d_dh;
+            }
+            f.Pn = d_dn;
+        }
+    }
+    return f;
+}
+
+// Donor terms of the face for the cell on its right (cell_is_L = false) or
+// left: mu* = mu r_d + nu_d sign(q*), the donor being the cell the face drains.
+template <typename T>
+__device__ __forceinline__ T face_mus(const AFace<T>& f, bool cell_is_L, T r_c, T nu_c, T r_nb,
+                                      T nu_nb) {
+    const bool donor_is_c = (f.qs > T(0)) == cell_is_L;
+    const T r_d = donor_is_c ? r_c : r_nb;
+    const T nu_d = donor_is_c ? nu_c : nu_nb;
+    return f.mu * r_d + nu_d * T((f.qs > T(0)) - (f.qs < T(0)));
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_a(AdjArgs<T> a) {
-    if (blockIdx.x == gridDim.x - 1) {
-        if (a.bc_prev && blockIdx.y == 0 && threadIdx.x < 64) adj_inflow<T>(a, a.t_prev);
+__device__ void adj_inflow(const AdjArgs<T>& a, double t, const double* ain);
+
+// The reverse of one step on strips of 60 output columns (one cell per lane,
+// two halo columns on each side) and chunks of `rows` output rows: row k
+// enters; the faces east of its cells and the faces between rows k-1 and k
+// are evaluated; r, nu, kappa of row k-1 follow (its four faces exist); then
+// the adjoints and the Manning gradient of row k-2 (r and nu of its four
+// neighbours exist).  Block 0 runs the inflow pass of the step reversed just
+// before (that step's kernel has completed; the two use different ain
+// buffers and the inflow pass accumulates its roughness terms apart).
+constexpr int kAdjWO = 60;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_march(AdjArgs<T> a) {
+    if (blockIdx.x == 0) {
+        if (a.bc_prev && threadIdx.x < 64) adj_inflow<T>(a, a.t_prev, a.ain_prev);
         return;
     }
-    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
-    if (i >= a.nx) return;
-    const long long P = a.pitch, o = (long long)(j + kHalo) * P + i + kHalo;
+    const int wave = (blockIdx.x - 1) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nstrips = (a.nx + kAdjWO - 1) / kAdjWO;
+    const int nchunks = (a.ny + a.rows - 1) / a.rows;
+    if (wave >= nstrips * nchunks) return;
+    const int s = wave % nstrips, c = wave / nstrips;
+    const int j0 = c * a.rows, j1 = min(j0 + a.rows, a.ny);
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx, ny = a.ny;
+    const int i = s * kAdjWO - kHalo + lane;       // this lane's column
+    const bool col_real = (i >= 0 && i < nx);
+    const bool out_col = (lane >= 2 && lane < 62 && col_real);
+    const bool loads = (i >= -kHalo && i < nx + kHalo);
+    const long long P = a.pitch;
     const T dt = (T)a.dt, inv_dx = T(1) / T(a.dx), gdt = T(a.g) * dt, h_eps = T(a.h_eps);
     const T dtdx = dt * inv_dx;
-    const T h = a.h[o], z = a.z[o], nn = a.n[o], eta = h + z;
-    const T lh_c = a.lh1[o];
-    T qs[4], mu[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const FaceGeo g = face_geo(f, o, P, i, j, a.nx, a.ny, nullptr);
-        const T lq = (f == 0 || f == 1) ? a.lqx1[g.fq] : a.lqy1[g.fq];
-        const T lnb = a.lh1[g.nb];
-        mu[f] = lq + dtdx * (g.cell_is_L ? (lnb - lh_c) : (lh_c - lnb));
-        if (g.border) {
-            const int kind = border_kind(a, g.side, g.pos);
-            T d1, d2;
-            qs[f] = (kind == F_OUT) ? outflow_fwd(a, g.side, g.pos, h, nn, d1, d2) : T(0);
-        } else {
-            const T hb = a.h[g.nb], zb = a.z[g.nb], nb = a.n[g.nb], eb = hb + zb;
-            const T q = (f == 0 || f == 1) ? a.qx[g.fq] : a.qy[g.fq];
-            qs[f] = g.cell_is_L ? face_q<T>(eta, eb, z, zb, nn, nb, q, gdt, inv_dx, h_eps)
-                                : face_q<T>(eb, eta, zb, z, nb, nn, q, gdt, inv_dx, h_eps);
-        }
-    }
-    T out = fmax(T(0), -qs[0]);
-    out += fmax(T(0), qs[1]);
-    out += fmax(T(0), -qs[2]);
-    out += fmax(T(0), qs[3]);
-    const T O = (dt * out) * inv_dx;
-    const T hp = fmax(h, T(0));
-    const bool lim = a.positivity && (O > hp);
-    T rho = T(0);
-    if (qs[0] < T(0)) rho += mu[0] * qs[0];
-    if (qs[1] > T(0)) rho += mu[1] * qs[1];
-    if (qs[2] < T(0)) rho += mu[2] * qs[2];
-    if (qs[3] > T(0)) rho += mu[3] * qs[3];
-    a.rr[o] = lim ? donor_ratio<T>(hp, O) : T(1);
-    a.nu[o] = lim ? rho * (-hp / (O * O)) * dtdx : T(0);
-    a.kap[o] = (lim && h > T(0)) ? rho / O : T(0);
-}
 
-// Pass B: adjoints of the state and the Manning gradient of one cell.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_b(AdjArgs<T> a) {
-    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
-    if (i >= a.nx) return;
-    const long long P = a.pitch, o = (long long)(j + kHalo) * P + i + kHalo;
-    const T dt = (T)a.dt, inv_dx = T(1) / T(a.dx), gdt = T(a.g) * dt, h_eps = T(a.h_eps);
-    const T dtdx = dt * inv_dx;
-    const T h = a.h[o], z = a.z[o], nn = a.n[o], eta = h + z;
-    const T lh_c = a.lh1[o];
-    const T r_c = a.rr[o], nu_c = a.nu[o];
-    T lh = lh_c + a.kap[o];
-    T gn = T(0), lqx = T(0), lqy = T(0);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const FaceGeo g = face_geo(f, o, P, i, j, a.nx, a.ny, nullptr);
-        const T lq = (f == 0 || f == 1) ? a.lqx1[g.fq] : a.lqy1[g.fq];
-        const T lnb = a.lh1[g.nb];
-        const T mu = lq + dtdx * (g.cell_is_L ? (lnb - lh_c) : (lh_c - lnb));
-        if (g.border) {
-            const int kind = border_kind(a, g.side, g.pos);
-            if (kind == F_OUT) {
-                T d_dh, d_dn;
-                const T qs = outflow_fwd(a, g.side, g.pos, h, nn, d_dh, d_dn);
-                // the edge cell drains this face (outward discharge)
-                const T mus = mu * r_c + nu_c * T((qs > T(0)) - (qs < T(0)));
-                lh += mus * d_dh;
-                gn += mus * d_dn;
-            } else if (kind == F_IN) {
-                // no donor inside the grid: the inflow is applied unscaled
-                const T sgn_in = (g.side == SIDE_W || g.side == SIDE_S) ? T(1) : T(-1);
-                a.ain[g.pos - a.in_first] = (double)(mu * sgn_in);
-            }
-        } else {
-            const T hb = a.h[g.nb], zb = a.z[g.nb], nb = a.n[g.nb], eb = hb + zb;
-            const T q = (f == 0 || f == 1) ? a.qx[g.fq] : a.qy[g.fq];
-            const FaceFwd<T> F = g.cell_is_L
-                                     ? face_fwd<T>(h, hb, z, zb, nn, nb, q, gdt, inv_dx, h_eps)
-                                     : face_fwd<T>(hb, h, zb, z, nb, nn, q, gdt, inv_dx, h_eps);
-            // donor: the left cell if the face flows toward +axis, else the right one
-            const bool donor_is_c = (F.qs > T(0)) == g.cell_is_L;
-            const T r_d = donor_is_c ? r_c : a.rr[g.nb];
-            const T nu_d = donor_is_c ? nu_c : a.nu[g.nb];
-            const T mus = mu * r_d + nu_d * T((F.qs > T(0)) - (F.qs < T(0)));
-            lh += mus * (g.cell_is_L ? F.PL : F.PR);
-            gn += T(0.5) * mus * F.Pn;
-            if (f == 1) lqx = mus * F.Pq;
-            if (f == 3) lqy = mus * F.Pq;
+    // row k (entering), row k-1, row k-2
+    T h0 = 0, z0 = 0, n0 = 0, qx0 = 0, qy0 = 0, l0 = 0, lx0 = 0, ly0 = 0;
+    T h1 = 0, z1 = 0, n1 = 0, qy1 = 0, l1 = 0, ly1 = 0;
+    T l2 = 0;
+    AFace<T> E1{}, E2{};        // faces east of the cells of rows k-1, k-2
+    AFace<T> Y1{}, Y2{};        // faces between rows k-2|k-1 and k-3|k-2
+    // r, nu (and kappa) of rows k-2 (r1 ...) and k-3 (r2 ...), before this
+    // iteration computes those of row k-1 (r0 ...)
+    T r1 = 1, nu1 = 0, kap1 = 0, r2 = 1, nu2 = 0;
+    // the next row's values are loaded one iteration ahead
+    T fh, fz, fn, fqx, fqy, fl, flx, fly;
+    auto fetch = [&](int k) {
+        fh = fz = fn = fqx = fqy = fl = flx = fly = T(0);
+        if (loads && k >= -kHalo && k < ny + kHalo) {
+            const long long o = (long long)(k + kHalo) * P + i + kHalo;
+            fh = a.h[o];
+            fz = a.z[o];
+            fn = a.n[o];
+            fqx = a.qx[o];
+            fqy = a.qy[o];
+            fl = a.lh1[o];
+            flx = a.lqx1[o];
+            fly = a.lqy1[o];
         }
+    };
+    fetch(j0 - 2);
+    for (int k = j0 - 2; k <= j1 + 1; ++k) {
+        h0 = fh; z0 = fz; n0 = fn; qx0 = fqx; qy0 = fqy; l0 = fl; lx0 = flx; ly0 = fly;
+        if (k < j1 + 1) fetch(k + 1);
+        const bool row_real = (k >= 0 && k < ny);
+        // faces east of the cells of row k (the lane at column -1 holds the
+        // west border face of column 0)
+        const T hn = from_next(h0), zn = from_next(z0), nn = from_next(n0), ln = from_next(l0);
+        const bool nxt_real = (i + 1 >= 0 && i + 1 < nx);
+        const AFace<T> E0 = aface<T>(a, h0, hn, z0, zn, n0, nn, qx0, lx0, l0, ln,
+                                     row_real && col_real, row_real && nxt_real,
+                                     col_real ? SIDE_E : SIDE_W, k, gdt, inv_dx, h_eps, dtdx);
+        // faces between rows k-1 and k
+        const bool prev_row_real = (k - 1 >= 0 && k - 1 < ny);
+        const AFace<T> Y0 = aface<T>(a, h1, h0, z1, z0, n1, n0, qy1, ly1, l1, l0,
+                                     col_real && prev_row_real, col_real && row_real,
+                                     prev_row_real ? SIDE_N : SIDE_S, i, gdt, inv_dx, h_eps, dtdx);
+        // r, nu, kappa of row k-1: faces W (east face of the lane before), E, S, N
+        T r0 = 1, nu0 = 0, kap0 = 0;
+        {
+            const T qW = from_prev(E1.qs), muW = from_prev(E1.mu);
+            T out = max0_neg(qW);
+            out += max0(E1.qs);
+            out += max0_neg(Y1.qs);
+            out += max0(Y0.qs);
+            const T O = (dt * out) * inv_dx;
+            const T hp = max0(h1);
+            const bool lim = a.positivity && (O > hp);
+            T rho = T(0);
+            if (qW < T(0)) rho += muW * qW;
+            if (E1.qs > T(0)) rho += E1.mu * E1.qs;
+            if (Y1.qs < T(0)) rho += Y1.mu * Y1.qs;
+            if (Y0.qs > T(0)) rho += Y0.mu * Y0.qs;
+            r0 = lim ? donor_ratio<T>(hp, O) : T(1);
+            nu0 = lim ? rho * (-hp / (O * O)) * dtdx : T(0);
+            kap0 = (lim && h1 > T(0)) ? rho / O : T(0);
+        }
+        // adjoints of row k-2
+        const int rb = k - 2;
+        // lane moves with every lane active (a disabled source lane gives no value)
+        const AFace<T> W = aface_prev(E2);
+        const T rW = from_prev(r1), nuW = from_prev(nu1), rE = from_next(r1), nuE = from_next(nu1);
+        if (rb >= j0 && rb < j1 && out_col) {
+            T lh = l2 + kap1;
+            T gnc = T(0), lqx = T(0), lqy = T(0);
+            // west face (the cell on its right)
+            if (i == 0) {
+                const int kind = border_kind(a, SIDE_W, rb);
+                if (kind == F_OUT) {
+                    const T mus = face_mus(W, false, r1, nu1, r1, nu1);
+                    lh += mus * W.PR;
+                    gnc += mus * W.Pn;
+                } else if (kind == F_IN) {
+                    a.ain[rb - a.in_first] = (double)W.mu;
+                }
+            } else {
+                const T mus = face_mus(W, false, r1, nu1, rW, nuW);
+                lh += mus * W.PR;
+                gnc += T(0.5) * mus * W.Pn;
+            }
+            // east face (the cell on its left)
+            if (i == nx - 1) {
+                const int kind = border_kind(a, SIDE_E, rb);
+                if (kind == F_OUT) {
+                    const T mus = face_mus(E2, true, r1, nu1, r1, nu1);
+                    lh += mus * E2.PL;
+                    gnc += mus * E2.Pn;
+                } else if (kind == F_IN) {
+                    a.ain[rb - a.in_first] = (double)(-E2.mu);
+                }
+            } else {
+                const T mus = face_mus(E2, true, r1, nu1, rE, nuE);
+                lh += mus * E2.PL;
+                gnc += T(0.5) * mus * E2.Pn;
+                lqx = mus * E2.Pq;
+            }
+            // south face
+            if (rb == 0) {
+                const int kind = border_kind(a, SIDE_S, i);
+                if (kind == F_OUT) {
+                    const T mus = face_mus(Y2, false, r1, nu1, r1, nu1);
+                    lh += mus * Y2.PR;
+                    gnc += mus * Y2.Pn;
+                } else if (kind == F_IN) {
+                    a.ain[i - a.in_first] = (double)Y2.mu;
+                }
+            } else {
+                const T mus = face_mus(Y2, false, r1, nu1, r2, nu2);
+                lh += mus * Y2.PR;
+                gnc += T(0.5) * mus * Y2.Pn;
+            }
+            // north face
+            if (rb == ny - 1) {
+                const int kind = border_kind(a, SIDE_N, i);
+                if (kind == F_OUT) {
+                    const T mus = face_mus(Y1, true, r1, nu1, r1, nu1);
+                    lh += mus * Y1.PL;
+                    gnc += mus * Y1.Pn;
+                } else if (kind == F_IN) {
+                    a.ain[i - a.in_first] = (double)(-Y1.mu);
+                }
+            } else {
+                const T mus = face_mus(Y1, true, r1, nu1, r0, nu0);
+                lh += mus * Y1.PL;
+                gnc += T(0.5) * mus * Y1.Pn;
+                lqy = mus * Y1.Pq;
+            }
+            const long long o = (long long)(rb + kHalo) * P + i + kHalo;
+            a.lh[o] = lh;
+            a.lqx[o] = lqx;
+            a.lqy[o] = lqy;
+            a.gn[(long long)rb * nx + i] += (double)gnc;
+        }
+        // shift the window
+        l2 = l1;
+        h1 = h0; z1 = z0; n1 = n0; qy1 = qy0; l1 = l0; ly1 = ly0;
+        E2 = E1; E1 = E0;
+        Y2 = Y1; Y1 = Y0;
+        r2 = r1; nu2 = nu1;
+        r1 = r0; nu1 = nu0; kap1 = kap0;
     }
-    a.lh[o] = lh;
-    a.lqx[o] = lqx;
-    a.lqy[o] = lqy;
-    a.gn[(long long)j * a.nx + i] += (double)gn;
 }
 
 // Q(t) and its interpolation weights on the samples (k0, 1-w) and (k0+1, w).
@@ -273,10 +390,10 @@ __device__ __forceinline__ double hydro_weights(const double* ts, const double* 
 }
 
 // Inflow section of the step that started at time t (one wave; needs that
-// step's pass B complete): with G(W) = sum_c dx k_c (W - z_c)_+^{5/3} - Q = 0,
+// step's reverse kernel complete, which wrote ain): with G(W) = sum_c dx k_c (W - z_c)_+^{5/3} - Q = 0,
 // dW/dQ = 1/D and dW/dk_j = -dx (W - z_j)^{5/3} / D, D = sum_c dx k_c (5/3)(W - z_c)^{2/3}.
 template <typename T>
-__device__ void adj_inflow(const AdjArgs<T>& a, double t) {
+__device__ void adj_inflow(const AdjArgs<T>& a, double t, const double* ain) {
     const int lane = threadIdx.x & 63;
     const int nc = a.in_count;
     if (nc <= 0 || a.nsamp <= 0) return;
@@ -291,7 +408,7 @@ __device__ void adj_inflow(const AdjArgs<T>& a, double t) {
         const double c = d > 0.0 ? cbrt(d) : 0.0;
         const double e = a.in_k[p] * (5.0 / 3.0) * (c * c);
         D += a.dx * e;
-        A += a.ain[p] * e;
+        A += ain[p] * e;
     }
     D = wave_sum(D);
     A = wave_sum(A);
@@ -300,20 +417,33 @@ __device__ void adj_inflow(const AdjArgs<T>& a, double t) {
         a.gq[k0] += (k0 + 1 < a.nsamp && w > 0.0) ? (1.0 - w) * dLdQ : dLdQ;
         if (k0 + 1 < a.nsamp && w > 0.0) a.gq[k0 + 1] += w * dLdQ;
     }
+    // the section's roughness terms go to gn_in (by section position): the
+    // step kernel this pass runs in adds to gn at the same cells
     for (int p = lane; p < nc; p += 64) {
         const int pos = a.in_first + p;
         const int ci = (a.in_side == SIDE_W) ? 0 : (a.in_side == SIDE_E) ? a.nx - 1 : pos;
         const int cj = (a.in_side == SIDE_S) ? 0 : (a.in_side == SIDE_N) ? a.ny - 1 : pos;
         const double nc_ = (double)a.n[(long long)(cj + kHalo) * a.pitch + ci + kHalo];
-        const double dLdk = pow53(W - a.in_z[p]) * (a.ain[p] - a.dx * A / D);
-        a.gn[(long long)cj * a.nx + ci] += dLdk * (-sqrt(a.in_slope) / (nc_ * nc_));
+        const double dLdk = pow53(W - a.in_z[p]) * (ain[p] - a.dx * A / D);
+        a.gn_in[p] += dLdk * (-sqrt(a.in_slope) / (nc_ * nc_));
+    }
+}
+
+// gn at the inflow cells += the inflow pass's roughness terms (after a sweep).
+template <typename T>
+__global__ void k_adj_fold_inflow(AdjArgs<T> a) {
+    for (int p = threadIdx.x; p < a.in_count; p += blockDim.x) {
+        const int pos = a.in_first + p;
+        const int ci = (a.in_side == SIDE_W) ? 0 : (a.in_side == SIDE_E) ? a.nx - 1 : pos;
+        const int cj = (a.in_side == SIDE_S) ? 0 : (a.in_side == SIDE_N) ? a.ny - 1 : pos;
+        a.gn[(long long)cj * a.nx + ci] += a.gn_in[p];
     }
 }
 
 // The inflow pass on its own (the last step of a sweep).
 template <typename T>
 __global__ void k_adj_bc(AdjArgs<T> a) {
-    adj_inflow<T>(a, a.t);
+    adj_inflow<T>(a, a.t, a.ain);
 }
 
 // Depth at the gauge cells (flat j*nx + i) into dst[0 .. ng).
@@ -344,11 +474,26 @@ __global__ void k_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
     lh[(long long)(j + kHalo) * pitch + i + kHalo] += s;
 }
 
+int adjoint_rows(int nx, int ny) {
+    // about 4096 work items (four waves per SIMD): a chunk of r rows costs r + 3
+    // row iterations, so chunks stay as tall as the grid allows, between 4 and 32
+    const long long strips = (nx + kAdjWO - 1) / kAdjWO;
+    int r = 32;
+    while (r > 4 && strips * ((ny + r - 1) / r) < 4096) r >>= 1;
+    return r;
+}
+
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s) {
-    const dim3 grid((a.nx + 255) / 256, a.ny);
-    hipLaunchKernelGGL((k_adj_a<T>), dim3(grid.x + 1, grid.y), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_adj_b<T>), grid, dim3(256), 0, s, a);
+    if (a.rows < 1) return hipErrorInvalidValue;
+    const long long items = (long long)((a.nx + kAdjWO - 1) / kAdjWO) * ((a.ny + a.rows - 1) / a.rows);
+    hipLaunchKernelGGL((k_adj_march<T>), dim3((unsigned)(1 + (items + 3) / 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_fold_inflow(const AdjArgs<T>& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_fold_inflow<T>), dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -377,6 +522,8 @@ hipError_t launch_gauge_seed(T* lh, long long pitch, int nx, const int* cells, c
 
 template hipError_t launch_adjoint_step<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_step<double>(const AdjArgs<double>&, hipStream_t);
+template hipError_t launch_adjoint_fold_inflow<float>(const AdjArgs<float>&, hipStream_t);
+template hipError_t launch_adjoint_fold_inflow<double>(const AdjArgs<double>&, hipStream_t);
 template hipError_t launch_adjoint_inflow<float>(const AdjArgs<float>&, hipStream_t);
 template hipError_t launch_adjoint_inflow<double>(const AdjArgs<double>&, hipStream_t);
 template hipError_t launch_gauge_gather<float>(const float*, long long, int, const int*, int, float*,

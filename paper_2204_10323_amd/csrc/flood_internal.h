@@ -194,12 +194,12 @@ struct AdjArgs {
     T* lh;                 // adjoint of x^n
     T* lqx;
     T* lqy;
-    T* rr;                 // per cell: donor factor r, and the limiter terms nu, kappa
-    T* nu;
-    T* kap;
     double* gn;            // dL/dn per cell, dense [ny][nx], accumulated
-    double* ain;           // adjoint of the inflow magnitudes [in_count]
+    double* ain;           // adjoint of the inflow magnitudes [in_count], written by this step
+    const double* ain_prev;  // ... written by the step reversed just before (its inflow pass)
+    double* gn_in;         // the inflow pass's dL/dn terms by section position [in_count], accumulated
     double* gq;            // dL/dQ_k [nsamp], accumulated
+    int rows;              // output rows per work item of the reverse pass
     const T* kout;
     const double* in_z;
     const double* in_k;
@@ -241,10 +241,14 @@ hipError_t launch_volume(const T* h, long long pitch, int nx, int ny, double* pa
 // Sets n bytes at p to v (a kernel, so that it can sit in a captured graph).
 hipError_t launch_fill_bytes(unsigned char* p, long long n, unsigned char v, hipStream_t s);
 
+// Output rows per work item of the reverse pass on an nx x ny grid.
+int adjoint_rows(int nx, int ny);
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint_inflow(const AdjArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_fold_inflow(const AdjArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_gauge_gather(const T* h, long long pitch, int nx, const int* gauges, int ng,
                                T* dst, hipStream_t s);

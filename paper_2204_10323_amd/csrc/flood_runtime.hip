@@ -1624,9 +1624,9 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
     fl_status st;
     // scratch of the sweep, kept with the forward record for further sweeps
     if (!c->d_bwd) {
-        const size_t bytes = fb * 3 * (C + 1) * 2 + fb * 6 + fb * 3 + sizeof(double) * nx * ny +
-                             sizeof(double) * std::max(1, c->in_count) + sizeof(double) * std::max(1, nsamp) +
-                             256 * 8;
+        const size_t bytes = fb * 3 * (C + 1) * 2 + fb * 6 + sizeof(double) * nx * ny +
+                             3 * sizeof(double) * std::max(1, c->in_count) +
+                             sizeof(double) * std::max(1, nsamp) + 256 * 8;
         hipError_t e = hipMalloc(&c->d_bwd, bytes);
         if (e != hipSuccess) {
             c->d_bwd = nullptr;
@@ -1644,14 +1644,18 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
     store[0] = carve(fb * 3 * (C + 1));
     store[1] = carve(fb * 3 * (C + 1));
     void* lam = carve(fb * 6);
-    void* aux = carve(fb * 3);
     double* gn = (double*)carve(sizeof(double) * nx * ny);
-    double* ain = (double*)carve(sizeof(double) * std::max(1, c->in_count));
+    // inflow adjoints by step parity (a step's kernel writes one while it runs
+    // the inflow pass of the step reversed before from the other), and the
+    // inflow pass's own roughness terms
+    const size_t inb = sizeof(double) * std::max(1, c->in_count);
+    double* ain = (double*)carve(3 * inb);
+    double* ainb[2] = {ain, (double*)((unsigned char*)ain + inb)};
+    double* gn_in = (double*)((unsigned char*)ain + 2 * inb);
     double* gq = (double*)carve(sizeof(double) * std::max(1, nsamp));
     HIP_TRY(c, hipMemsetAsync(lam, 0, fb * 6, c->stream));
-    HIP_TRY(c, hipMemsetAsync(aux, 0, fb * 3, c->stream));
     HIP_TRY(c, hipMemsetAsync(gn, 0, sizeof(double) * nx * ny, c->stream));
-    HIP_TRY(c, hipMemsetAsync(ain, 0, sizeof(double) * std::max(1, c->in_count), c->stream));
+    HIP_TRY(c, hipMemsetAsync(ain, 0, 3 * inb, c->stream));
     HIP_TRY(c, hipMemsetAsync(gq, 0, sizeof(double) * std::max(1, nsamp), c->stream));
     void* d_dl = nullptr;
     struct Owned {
@@ -1756,12 +1760,12 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
             a.lh = lamf[3 * (1 - cur)];
             a.lqx = lamf[3 * (1 - cur) + 1];
             a.lqy = lamf[3 * (1 - cur) + 2];
-            a.rr = (T*)F(aux, 0);
-            a.nu = (T*)F(aux, 1);
-            a.kap = (T*)F(aux, 2);
             a.gn = gn;
-            a.ain = ain;
+            a.ain = ainb[k & 1];
+            a.ain_prev = ainb[(k + 1) & 1];
+            a.gn_in = gn_in;
             a.gq = gq;
+            a.rows = adjoint_rows(nx, ny);
             a.kout = (const T*)c->d_kout;
             a.in_z = c->d_in_z;
             a.in_k = c->d_in_k;
@@ -1785,12 +1789,14 @@ fl_status adj_backward_t(fl_ctx* c, const void* dl, double* grad_n, int grad_on_
             a.in_slope = c->in_slope;
             a.out_slope = c->out_slope;
             a.t = tseq[k];
-            // the inflow pass of step k+1 (reversed just before) runs inside pass A
+            // the inflow pass of step k+1 (reversed just before) runs in this
+            // step's kernel
             a.bc_prev = (k + 1 < N) ? 1 : 0;
             a.t_prev = (k + 1 < N) ? tseq[k + 1] : 0.0;
             r = launch_adjoint_step<T>(a, own.as);
             cur = 1 - cur;
             if (k == 0 && r == hipSuccess) r = launch_adjoint_inflow<T>(a, own.as);
+            if (k == 0 && r == hipSuccess) r = launch_adjoint_fold_inflow<T>(a, own.as);
         }
         if (r == hipSuccess) r = hipEventRecord(reversed[b], own.as);
         reversed_set[b] = true;
