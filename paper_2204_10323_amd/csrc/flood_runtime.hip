@@ -206,6 +206,33 @@ fl_status need_device(fl_ctx* c, const void* p, const char* what) {
     return FL_OK;
 }
 
+// Copies `rows` rows of row_bytes bytes from device memory (row pitch spitch)
+// to host memory (row pitch dpitch) on stream s and waits for them.  Pitched
+// rows go as 1D copies of whole row blocks through a host staging buffer of
+// at most 64 MiB: pitched device-to-host copies into pageable memory have
+// been seen to leave the destination untouched under rocprofv3, while 1D
+// copies arrive.
+fl_status rows_to_host(fl_ctx* c, unsigned char* dst, size_t dpitch, const unsigned char* src,
+                       size_t spitch, size_t row_bytes, int rows, hipStream_t s) {
+    if (rows <= 0 || row_bytes == 0) return FL_OK;
+    if (dpitch == row_bytes && spitch == row_bytes) {
+        HIP_TRY(c, hipMemcpyAsync(dst, src, row_bytes * rows, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        return FL_OK;
+    }
+    const int block = (int)std::max<size_t>(1, std::min<size_t>((size_t)rows, (size_t(64) << 20) / spitch));
+    std::vector<unsigned char> stage((size_t)(block - 1) * spitch + row_bytes);
+    for (int r0 = 0; r0 < rows; r0 += block) {
+        const int n = std::min(block, rows - r0);
+        HIP_TRY(c, hipMemcpyAsync(stage.data(), src + (size_t)r0 * spitch, (size_t)(n - 1) * spitch + row_bytes,
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        for (int j = 0; j < n; ++j)
+            std::memcpy(dst + (size_t)(r0 + j) * dpitch, stage.data() + (size_t)j * spitch, row_bytes);
+    }
+    return FL_OK;
+}
+
 // Copy ny rows of `cols` elements with stride `stride` from host or device
 // memory into a dense host vector.
 fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int cols, int on_device,
@@ -215,8 +242,9 @@ fl_status fetch_rows(fl_ctx* c, const void* src, int64_t stride, int rows_, int 
     if (on_device) {
         HIP_TRY(c, hipSetDevice(c->device));
         if (fl_status st = need_device(c, src, "input array")) return st;
-        HIP_TRY(c, hipMemcpy2D(out.data(), cols * es, src, (size_t)stride * es, cols * es, rows_,
-                               hipMemcpyDeviceToHost));
+        if (fl_status st = rows_to_host(c, out.data(), cols * es, static_cast<const unsigned char*>(src),
+                                        (size_t)stride * es, cols * es, rows_, nullptr))
+            return st;
     } else {
         for (int j = 0; j < rows_; ++j)
             std::memcpy(out.data() + (size_t)j * cols * es,
@@ -644,13 +672,18 @@ fl_status do_commit(fl_ctx* c) {
         if ((st = dalloc(c, (void**)&c->d_act_count, 18 * sizeof(unsigned)))) return st;
     }
 
+    // Host sources of the asynchronous uploads below stay alive until the
+    // stream is synchronized at the end of this function (a copy from pageable
+    // memory may still read its source after the call returns).
+    std::vector<unsigned char> east, west, north, kb;
     // cell fields
     if ((st = upload_field(c, c->d_z, c->z, ny, nx, kHalo, kHalo))) return st;
     if ((st = upload_field(c, c->d_n, c->n, ny, nx, kHalo, kHalo))) return st;
     if (c->have_state) {
         if ((st = upload_field(c, c->d_h[0], c->h0, ny, nx, kHalo, kHalo))) return st;
         // qx (ny x (nx+1)): column 0 is the west border, columns 1..nx the east faces.
-        std::vector<unsigned char> east((size_t)ny * nx * es), west((size_t)ny * es);
+        east.resize((size_t)ny * nx * es);
+        west.resize((size_t)ny * es);
         for (int j = 0; j < ny; ++j) {
             std::memcpy(east.data() + (size_t)j * nx * es, c->qx0.data() + ((size_t)j * (nx + 1) + 1) * es,
                         nx * es);
@@ -660,7 +693,7 @@ fl_status do_commit(fl_ctx* c) {
         HIP_TRY(c, hipMemcpyAsync(c->d_edge_w, west.data(), west.size(), hipMemcpyHostToDevice,
                                   c->stream));
         // qy ((ny+1) x nx): row 0 is the south border, rows 1..ny the north faces.
-        std::vector<unsigned char> north(c->qy0.begin() + (size_t)nx * es, c->qy0.end());
+        north.assign(c->qy0.begin() + (size_t)nx * es, c->qy0.end());
         if ((st = upload_field(c, c->d_qy[0], north, ny, nx, kHalo, kHalo))) return st;
         HIP_TRY(c, hipMemcpyAsync(c->d_edge_s, c->qy0.data(), (size_t)nx * es, hipMemcpyHostToDevice,
                                   c->stream));
@@ -673,7 +706,6 @@ fl_status do_commit(fl_ctx* c) {
             side_cell(c, c->out_side, c->out_first + p, &i, &j);
             k[c->out_first + p] = std::sqrt(c->out_slope) / get_elem(c, c->n.data(), (size_t)j * nx + i);
         }
-        std::vector<unsigned char> kb;
         if (c->prec == FL_F64) fill_host<double>(kb, k.size(), k); else fill_host<float>(kb, k.size(), k);
         HIP_TRY(c, hipMemcpyAsync(c->d_kout, kb.data(), kb.size(), hipMemcpyHostToDevice, c->stream));
     }
@@ -1442,8 +1474,11 @@ fl_status fl_get_depth(fl_ctx* c, void* dst, int64_t row_stride, int on_device) 
     const size_t es = esz(c);
     const unsigned char* src = static_cast<const unsigned char*>(c->d_h[c->nstep & 1]) +
                                ((size_t)kHalo * c->pitch + kHalo) * es;
+    if (!on_device)
+        return rows_to_host(c, static_cast<unsigned char*>(dst), row_stride * es, src, c->pitch * es,
+                            c->nx * es, c->ny, c->stream);
     HIP_TRY(c, hipMemcpy2DAsync(dst, row_stride * es, src, c->pitch * es, c->nx * es, c->ny,
-                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+                                hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return FL_OK;
 }
@@ -1459,11 +1494,24 @@ fl_status fl_get_discharge(fl_ctx* c, void* qx, void* qy, int on_device) {
     }
     const size_t es = esz(c);
     const int nx = c->nx, ny = c->ny;
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const int p = c->nstep & 1;
     const size_t off = ((size_t)kHalo * c->pitch + kHalo) * es;
     unsigned char* dqx = static_cast<unsigned char*>(qx);
     unsigned char* dqy = static_cast<unsigned char*>(qy);
+    if (!on_device) {
+        fl_status st;
+        if ((st = rows_to_host(c, dqx + es, (nx + 1) * es, static_cast<unsigned char*>(c->d_qx[p]) + off,
+                               c->pitch * es, nx * es, ny, c->stream)) ||
+            (st = rows_to_host(c, dqx, (nx + 1) * es, static_cast<unsigned char*>(c->d_edge_w), es, es, ny,
+                               c->stream)) ||
+            (st = rows_to_host(c, dqy, nx * es, static_cast<unsigned char*>(c->d_edge_s), nx * es, nx * es, 1,
+                               c->stream)) ||
+            (st = rows_to_host(c, dqy + nx * es, nx * es, static_cast<unsigned char*>(c->d_qy[p]) + off,
+                               c->pitch * es, nx * es, ny, c->stream)))
+            return st;
+        return FL_OK;
+    }
+    const hipMemcpyKind kind = hipMemcpyDeviceToDevice;
     HIP_TRY(c, hipMemcpy2DAsync(dqx + es, (nx + 1) * es, static_cast<unsigned char*>(c->d_qx[p]) + off,
                                 c->pitch * es, nx * es, ny, kind, c->stream));
     HIP_TRY(c, hipMemcpy2DAsync(dqx, (nx + 1) * es, c->d_edge_w, es, es, ny, kind, c->stream));
@@ -1945,6 +1993,7 @@ fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, i
     fl_status st;
     if ((st = adalloc(c, (void**)&c->d_gauges, sizeof(int) * ngauges))) return st;
     HIP_TRY(c, hipMemcpyAsync(c->d_gauges, gauge_cells, sizeof(int) * ngauges, hipMemcpyHostToDevice, c->stream));
+    std::vector<int> packed;   // read by an asynchronous upload until the synchronization below
     {   // gauges grouped by cell, each group in gauge order
         std::vector<int> idx(ngauges);
         for (int k = 0; k < ngauges; ++k) idx[k] = k;
@@ -1959,7 +2008,7 @@ fl_status fl_adj_setup(fl_ctx* c, const int32_t* gauge_cells, int32_t ngauges, i
         }
         ptr.push_back(ngauges);
         c->ngcell = (int)cells.size();
-        std::vector<int> packed(cells);
+        packed = cells;
         packed.insert(packed.end(), ptr.begin(), ptr.end());
         packed.insert(packed.end(), list.begin(), list.end());
         if ((st = adalloc(c, (void**)&c->d_gcell, sizeof(int) * packed.size()))) return st;
