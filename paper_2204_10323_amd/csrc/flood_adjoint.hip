@@ -101,20 +101,20 @@ __device__ __forceinline__ FaceFwd<float> face_fwd<float>(float hL, float hR, fl
 
 enum { F_INT = 0, F_WALL = 1, F_IN = 2, F_OUT = 3 };
 
-// Kind of the border face of cell (i, j) on `side` (the cell is on that edge).
+// Kind of the border face of cell (i, j) on `side` (the cell is on that edge);
+// kb: the outflow coefficient kout[pos] (zero off the outflow side).
 template <typename T>
-__device__ __forceinline__ int border_kind(const AdjArgs<T>& a, int side, int pos) {
+__device__ __forceinline__ int border_kind(const AdjArgs<T>& a, int side, int pos, T kb) {
     if (a.in_side == side && pos >= a.in_first && pos < a.in_first + a.in_count) return F_IN;
-    if (a.out_side == side && a.kout[pos] > T(0)) return F_OUT;
+    if (a.out_side == side && kb > T(0)) return F_OUT;
     return F_WALL;
 }
 
 // Outflow border value as the step computes it (border_q without inflow),
 // with its derivatives in the edge cell's depth and roughness.
 template <typename T>
-__device__ __forceinline__ T outflow_fwd(const AdjArgs<T>& a, int side, int pos, T h, T n, T& d_dh,
+__device__ __forceinline__ T outflow_fwd(const AdjArgs<T>& a, int side, T k, T h, T n, T& d_dh,
                                          T& d_dn) {
-    const T k = a.kout[pos];
     const T hp = fmax(h, T(0));
     const T v = -k * pow53(hp);
     const T c = cbrt_t(hp);
@@ -149,11 +149,13 @@ __device__ __forceinline__ AFace<T> aface_prev(const AFace<T>& e) {
 
 // The face between cells L and R (R on the +axis side).  lq: the adjoint of
 // the face's new value; real_L/real_R: whether L and R lie in the grid; for a
-// border face the edge cell's side and position along it.
+// border face the edge cell's side, its position along it and the outflow
+// coefficient there.
 template <typename T>
 __device__ __forceinline__ AFace<T> aface(const AdjArgs<T>& a, T hL, T hR, T zL, T zR, T nL, T nR,
                                           T q, T lq, T lhL, T lhR, bool real_L, bool real_R,
-                                          int side, int pos, T gdt, T inv_dx, T h_eps, T dtdx) {
+                                          int side, int pos, T kb, T gdt, T inv_dx, T h_eps,
+                                          T dtdx) {
     AFace<T> f;
     f.qs = f.Pq = f.PL = f.PR = f.Pn = T(0);
     f.mu = lq + dtdx * (lhR - lhL);
@@ -165,13 +167,13 @@ __device__ __forceinline__ AFace<T> aface(const AdjArgs<T>& a, T hL, T hR, T zL,
         f.PR = F.PR;
         f.Pn = F.Pn;
     } else if (real_L != real_R) {
-        if (border_kind(a, side, pos) == F_OUT) {
+        if (border_kind(a, side, pos, kb) == F_OUT) {
             T d_dh, d_dn;
             if (real_L) {
-                f.qs = outflow_fwd(a, side, pos, hL, nL, d_dh, d_dn);
+                f.qs = outflow_fwd(a, side, kb, hL, nL, d_dh, d_dn);
                 f.PL = d_dh;
             } else {
-                f.qs = outflow_fwd(a, side, pos, hR, nR, d_dh, d_dn);
+                f.qs = outflow_fwd(a, side, kb, hR, nR, d_dh, d_dn);
                 f.PR = d_dh;
             }
             f.Pn = d_dn;
@@ -205,7 +207,7 @@ __device__ void adj_inflow(const AdjArgs<T>& a, double t, const double* ain);
 constexpr int kAdjWO = 60;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_march(AdjArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 1) void k_adj_march(AdjArgs<T> a) {
     if (blockIdx.x == 0) {
         if (a.bc_prev && threadIdx.x < 64) adj_inflow<T>(a, a.t_prev, a.ain_prev);
         return;
@@ -235,10 +237,20 @@ __global__ __launch_bounds__(256) void k_adj_march(AdjArgs<T> a) {
     // r, nu (and kappa) of rows k-2 (r1 ...) and k-3 (r2 ...), before this
     // iteration computes those of row k-1 (r0 ...)
     T r1 = 1, nu1 = 0, kap1 = 0, r2 = 1, nu2 = 0;
-    // the next row's values are loaded one iteration ahead
+    // the next row's values are loaded one iteration ahead, and with them the
+    // Manning gradient of the row that iteration finishes (two rows behind)
     T fh, fz, fn, fqx, fqy, fl, flx, fly;
+    double fgn = 0.0, gn_row = 0.0;
+    // outflow coefficients at the borders: by row on a west or east outflow
+    // side (fetched with the rows: kr0, kr1, kr2 for rows k, k-1, k-2), by
+    // column on a south or north one (kc)
+    const bool out_we = (a.out_side == SIDE_W || a.out_side == SIDE_E);
+    const T kc = (!out_we && col_real) ? a.kout[i] : T(0);
+    T fkr = T(0), kr0 = T(0), kr1 = T(0), kr2 = T(0);
     auto fetch = [&](int k) {
         fh = fz = fn = fqx = fqy = fl = flx = fly = T(0);
+        fkr = (out_we && k >= 0 && k < ny) ? a.kout[k] : T(0);
+        if (out_col && k - 2 >= j0 && k - 2 < j1) fgn = a.gn[(long long)(k - 2) * nx + i];
         if (loads && k >= -kHalo && k < ny + kHalo) {
             const long long o = (long long)(k + kHalo) * P + i + kHalo;
             fh = a.h[o];
@@ -254,23 +266,34 @@ __global__ __launch_bounds__(256) void k_adj_march(AdjArgs<T> a) {
     fetch(j0 - 2);
     for (int k = j0 - 2; k <= j1 + 1; ++k) {
         h0 = fh; z0 = fz; n0 = fn; qx0 = fqx; qy0 = fqy; l0 = fl; lx0 = flx; ly0 = fly;
+        gn_row = fgn;   // row k-2's
+        kr2 = kr1; kr1 = kr0; kr0 = fkr;
         if (k < j1 + 1) fetch(k + 1);
         const bool row_real = (k >= 0 && k < ny);
+        // Only what the output rows j0 .. j1-1 use is evaluated (the conditions
+        // are uniform over the wave): r and nu of rows j0-1 .. j1, so the faces
+        // east of rows j0-1 .. j1 and those between rows j0-2|j0-1 .. j1|j1+1.
         // faces east of the cells of row k (the lane at column -1 holds the
         // west border face of column 0)
-        const T hn = from_next(h0), zn = from_next(z0), nn = from_next(n0), ln = from_next(l0);
-        const bool nxt_real = (i + 1 >= 0 && i + 1 < nx);
-        const AFace<T> E0 = aface<T>(a, h0, hn, z0, zn, n0, nn, qx0, lx0, l0, ln,
-                                     row_real && col_real, row_real && nxt_real,
-                                     col_real ? SIDE_E : SIDE_W, k, gdt, inv_dx, h_eps, dtdx);
+        AFace<T> E0{};
+        if (k >= j0 - 1 && k <= j1) {
+            const T hn = from_next(h0), zn = from_next(z0), nn = from_next(n0), ln = from_next(l0);
+            const bool nxt_real = (i + 1 >= 0 && i + 1 < nx);
+            E0 = aface<T>(a, h0, hn, z0, zn, n0, nn, qx0, lx0, l0, ln, row_real && col_real,
+                          row_real && nxt_real, col_real ? SIDE_E : SIDE_W, k, kr0, gdt, inv_dx,
+                          h_eps, dtdx);
+        }
         // faces between rows k-1 and k
-        const bool prev_row_real = (k - 1 >= 0 && k - 1 < ny);
-        const AFace<T> Y0 = aface<T>(a, h1, h0, z1, z0, n1, n0, qy1, ly1, l1, l0,
-                                     col_real && prev_row_real, col_real && row_real,
-                                     prev_row_real ? SIDE_N : SIDE_S, i, gdt, inv_dx, h_eps, dtdx);
+        AFace<T> Y0{};
+        if (k >= j0 - 1) {
+            const bool prev_row_real = (k - 1 >= 0 && k - 1 < ny);
+            Y0 = aface<T>(a, h1, h0, z1, z0, n1, n0, qy1, ly1, l1, l0, col_real && prev_row_real,
+                          col_real && row_real, prev_row_real ? SIDE_N : SIDE_S, i, kc, gdt,
+                          inv_dx, h_eps, dtdx);
+        }
         // r, nu, kappa of row k-1: faces W (east face of the lane before), E, S, N
         T r0 = 1, nu0 = 0, kap0 = 0;
-        {
+        if (k >= j0) {
             const T qW = from_prev(E1.qs), muW = from_prev(E1.mu);
             T out = max0_neg(qW);
             out += max0(E1.qs);
@@ -290,79 +313,81 @@ __global__ __launch_bounds__(256) void k_adj_march(AdjArgs<T> a) {
         }
         // adjoints of row k-2
         const int rb = k - 2;
-        // lane moves with every lane active (a disabled source lane gives no value)
-        const AFace<T> W = aface_prev(E2);
-        const T rW = from_prev(r1), nuW = from_prev(nu1), rE = from_next(r1), nuE = from_next(nu1);
-        if (rb >= j0 && rb < j1 && out_col) {
-            T lh = l2 + kap1;
-            T gnc = T(0), lqx = T(0), lqy = T(0);
-            // west face (the cell on its right)
-            if (i == 0) {
-                const int kind = border_kind(a, SIDE_W, rb);
-                if (kind == F_OUT) {
-                    const T mus = face_mus(W, false, r1, nu1, r1, nu1);
+        if (rb >= j0 && rb < j1) {
+            // lane moves with every lane active (a disabled source lane gives no value)
+            const AFace<T> W = aface_prev(E2);
+            const T rW = from_prev(r1), nuW = from_prev(nu1), rE = from_next(r1), nuE = from_next(nu1);
+            if (out_col) {
+                T lh = l2 + kap1;
+                T gnc = T(0), lqx = T(0), lqy = T(0);
+                // west face (the cell on its right)
+                if (i == 0) {
+                    const int kind = border_kind(a, SIDE_W, rb, kr2);
+                    if (kind == F_OUT) {
+                        const T mus = face_mus(W, false, r1, nu1, r1, nu1);
+                        lh += mus * W.PR;
+                        gnc += mus * W.Pn;
+                    } else if (kind == F_IN) {
+                        a.ain[rb - a.in_first] = (double)W.mu;
+                    }
+                } else {
+                    const T mus = face_mus(W, false, r1, nu1, rW, nuW);
                     lh += mus * W.PR;
-                    gnc += mus * W.Pn;
-                } else if (kind == F_IN) {
-                    a.ain[rb - a.in_first] = (double)W.mu;
+                    gnc += T(0.5) * mus * W.Pn;
                 }
-            } else {
-                const T mus = face_mus(W, false, r1, nu1, rW, nuW);
-                lh += mus * W.PR;
-                gnc += T(0.5) * mus * W.Pn;
-            }
-            // east face (the cell on its left)
-            if (i == nx - 1) {
-                const int kind = border_kind(a, SIDE_E, rb);
-                if (kind == F_OUT) {
-                    const T mus = face_mus(E2, true, r1, nu1, r1, nu1);
+                // east face (the cell on its left)
+                if (i == nx - 1) {
+                    const int kind = border_kind(a, SIDE_E, rb, kr2);
+                    if (kind == F_OUT) {
+                        const T mus = face_mus(E2, true, r1, nu1, r1, nu1);
+                        lh += mus * E2.PL;
+                        gnc += mus * E2.Pn;
+                    } else if (kind == F_IN) {
+                        a.ain[rb - a.in_first] = (double)(-E2.mu);
+                    }
+                } else {
+                    const T mus = face_mus(E2, true, r1, nu1, rE, nuE);
                     lh += mus * E2.PL;
-                    gnc += mus * E2.Pn;
-                } else if (kind == F_IN) {
-                    a.ain[rb - a.in_first] = (double)(-E2.mu);
+                    gnc += T(0.5) * mus * E2.Pn;
+                    lqx = mus * E2.Pq;
                 }
-            } else {
-                const T mus = face_mus(E2, true, r1, nu1, rE, nuE);
-                lh += mus * E2.PL;
-                gnc += T(0.5) * mus * E2.Pn;
-                lqx = mus * E2.Pq;
-            }
-            // south face
-            if (rb == 0) {
-                const int kind = border_kind(a, SIDE_S, i);
-                if (kind == F_OUT) {
-                    const T mus = face_mus(Y2, false, r1, nu1, r1, nu1);
+                // south face
+                if (rb == 0) {
+                    const int kind = border_kind(a, SIDE_S, i, kc);
+                    if (kind == F_OUT) {
+                        const T mus = face_mus(Y2, false, r1, nu1, r1, nu1);
+                        lh += mus * Y2.PR;
+                        gnc += mus * Y2.Pn;
+                    } else if (kind == F_IN) {
+                        a.ain[i - a.in_first] = (double)Y2.mu;
+                    }
+                } else {
+                    const T mus = face_mus(Y2, false, r1, nu1, r2, nu2);
                     lh += mus * Y2.PR;
-                    gnc += mus * Y2.Pn;
-                } else if (kind == F_IN) {
-                    a.ain[i - a.in_first] = (double)Y2.mu;
+                    gnc += T(0.5) * mus * Y2.Pn;
                 }
-            } else {
-                const T mus = face_mus(Y2, false, r1, nu1, r2, nu2);
-                lh += mus * Y2.PR;
-                gnc += T(0.5) * mus * Y2.Pn;
-            }
-            // north face
-            if (rb == ny - 1) {
-                const int kind = border_kind(a, SIDE_N, i);
-                if (kind == F_OUT) {
-                    const T mus = face_mus(Y1, true, r1, nu1, r1, nu1);
+                // north face
+                if (rb == ny - 1) {
+                    const int kind = border_kind(a, SIDE_N, i, kc);
+                    if (kind == F_OUT) {
+                        const T mus = face_mus(Y1, true, r1, nu1, r1, nu1);
+                        lh += mus * Y1.PL;
+                        gnc += mus * Y1.Pn;
+                    } else if (kind == F_IN) {
+                        a.ain[i - a.in_first] = (double)(-Y1.mu);
+                    }
+                } else {
+                    const T mus = face_mus(Y1, true, r1, nu1, r0, nu0);
                     lh += mus * Y1.PL;
-                    gnc += mus * Y1.Pn;
-                } else if (kind == F_IN) {
-                    a.ain[i - a.in_first] = (double)(-Y1.mu);
+                    gnc += T(0.5) * mus * Y1.Pn;
+                    lqy = mus * Y1.Pq;
                 }
-            } else {
-                const T mus = face_mus(Y1, true, r1, nu1, r0, nu0);
-                lh += mus * Y1.PL;
-                gnc += T(0.5) * mus * Y1.Pn;
-                lqy = mus * Y1.Pq;
+                const long long o = (long long)(rb + kHalo) * P + i + kHalo;
+                a.lh[o] = lh;
+                a.lqx[o] = lqx;
+                a.lqy[o] = lqy;
+                a.gn[(long long)rb * nx + i] = gn_row + (double)gnc;
             }
-            const long long o = (long long)(rb + kHalo) * P + i + kHalo;
-            a.lh[o] = lh;
-            a.lqx[o] = lqx;
-            a.lqy[o] = lqy;
-            a.gn[(long long)rb * nx + i] += (double)gnc;
         }
         // shift the window
         l2 = l1;
