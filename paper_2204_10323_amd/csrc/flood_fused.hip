@@ -494,6 +494,8 @@ __device__ __forceinline__ void step_consts(const StepArgs<T>& a, double dt, Ste
     K.qin = nullptr;
     K.W = 0.0;
     K.inflow_on = 0;
+    K.pre = false;
+    K.b_in = K.b_out = T(0);
 }
 
 template <typename T>

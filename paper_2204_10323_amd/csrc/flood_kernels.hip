@@ -84,6 +84,8 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
     K.qin = a.qin;
     K.W = 0.0;
     K.inflow_on = 0;
+    K.pre = true;
+    K.b_in = K.b_out = T(0);
 
     bool store_col[CPT];
     bool all_store = true, any_store = false;
@@ -96,7 +98,18 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
     }
 
     T hN[CPT], zN[CPT], nN[CPT], qxN[CPT], qyN[CPT];
+    // the inflow and outflow coefficient of a row on a west or east section,
+    // loaded with the row by the strips at those borders
+    const bool edge_we = G.west_strip || G.east_strip;
+    const bool in_we = (a.in_side == SIDE_W || a.in_side == SIDE_E);
+    const bool out_we = (a.out_side == SIDE_W || a.out_side == SIDE_E);
+    T bN_in = T(0), bN_out = T(0);
     auto load_row = [&](int k) {
+        if (edge_we) {
+            const bool rr = (k >= 0 && k < ny);
+            bN_in = (rr && in_we && a.qin) ? a.qin[k] : T(0);
+            bN_out = (rr && out_we) ? a.kout[k] : T(0);
+        }
         if (loads) {
             const long long o = (long long)(k + kHalo) * P;
             ldv<T, CPT>(at_byte(as_global(a.h_in) + o, boff), hN);
@@ -146,6 +159,8 @@ __device__ void step_item(const StepArgs<T>& a, int s, int c, T dt, typename Ord
         for (int m = 0; m < CPT; ++m) {
             h0[m] = hN[m]; z0[m] = zN[m]; n0[m] = nN[m]; qx0[m] = qxN[m]; qy0[m] = qyN[m];
         }
+        K.b_in = bN_in;
+        K.b_out = bN_out;
         if (kDefer && spend) {
             store_row(srow, sh, sqx, sqy);
             spend = false;

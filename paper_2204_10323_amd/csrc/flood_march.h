@@ -24,6 +24,11 @@ struct StepK {
     const T* qin;
     double W;
     int inflow_on;
+    // pre: the west and east border faces of the row take its inflow b_in and
+    // outflow coefficient b_out from here (loaded with the row) instead of
+    // loading them when the face is evaluated
+    bool pre;
+    T b_in, b_out;
 };
 
 // Inflow magnitude at position p along the inflow side: the same expression
@@ -44,13 +49,15 @@ __device__ __forceinline__ T inflow_at(const StepArgs<T>& a, const StepK<T>& K, 
 template <typename T, int VAR = 0>
 __device__ __forceinline__ T border_q(const StepArgs<T>& a, const StepK<T>& K, int side, int p,
                                       T h_edge) {
+    const bool given = K.pre && (side == SIDE_W || side == SIDE_E);
     T v = T(0);
-    if (a.in_side == side) v = inflow_at<T>(a, K, p);
+    if (a.in_side == side) v = given ? K.b_in : inflow_at<T>(a, K, p);
     if (a.out_side == side) {
+        const T ko = given ? K.b_out : a.kout[p];
         if constexpr ((VAR & VAR_BOUNDARY_CELL_AREA) != 0)
-            v -= a.kout[p] * (T(a.dx) * pow23(fmax(h_edge, T(0))));
+            v -= ko * (T(a.dx) * pow23(fmax(h_edge, T(0))));
         else
-            v -= a.kout[p] * pow53(fmax(h_edge, T(0)));
+            v -= ko * pow53(fmax(h_edge, T(0)));
     }
     return (side == SIDE_W || side == SIDE_S) ? v : -v;
 }
