@@ -89,6 +89,41 @@ def test_fp64_gpu_adjoint_matches_cpu_adjoint(wet):
             assert np.array_equal(gn, ref[0]) and np.array_equal(gq, ref[1])
 
 
+@pytest.mark.parametrize("sides", [(EAST, WEST), (SOUTH, NORTH), (NORTH, SOUTH), (WEST, SOUTH)],
+                         ids=["east_in_west_out", "south_in_north_out", "north_in_south_out",
+                              "west_in_south_out"])
+def test_fp64_gpu_adjoint_sections_on_every_side(sides):
+    """Inflow and outflow sections on every side of a 71 x 23 grid (two strips of
+    the reverse pass, chunks of a few rows): the reverse pass takes a west or
+    east border by row and a south or north one by column, and writes the
+    inflow adjoints from the row or column on the section."""
+    in_side, out_side = sides
+    nx, ny, dx, S = 71, 23, 5.0, 1e-3
+    rng = np.random.default_rng(17)
+    z = rng.uniform(0.0, 0.05, (ny, nx))
+    n = rng.uniform(0.03, 0.05, (ny, nx))
+    h0 = rng.uniform(0.2, 0.6, (ny, nx))
+    l_in = ny if in_side in (WEST, EAST) else nx
+    l_out = ny if out_side in (WEST, EAST) else nx
+    ts = np.linspace(0, 100, 6)
+    qs = np.array([5.0, 8.0, 12.0, 9.0, 6.0, 5.0])
+    sc = _cast(Scenario("adj_sides", nx, ny, dx, z, n, h0, (in_side, l_in // 3, l_in // 3, S, ts, qs),
+                        (out_side, 0, l_out, S), dt_max=0.5, dt_fixed=0.5), np.float64)
+    gauges = rng.choice(nx * ny, NG, replace=False)
+    truth, _, _, _ = oracle.adjoint(sc, N, gauges, OBS_EVERY, obs=np.zeros((N // OBS_EVERY, NG)),
+                                    n=sc.n * 1.1)
+    s_cpu, l_cpu, gn_cpu, gq_cpu = oracle.adjoint(sc, N, gauges, OBS_EVERY, obs=truth)
+    print("CASE adjoint fp64 sides in=%d out=%d" % sides, flush=True)
+    f, s, l, gn, gq = _gpu_adjoint(sc, "f64", gauges, truth)
+    f.close()
+    assert np.abs(s - s_cpu).max() <= 1e-11 * max(1.0, np.abs(s_cpu).max())
+    assert abs(l / l_cpu - 1) <= 1e-8
+    assert _rel_l2(gn, gn_cpu) <= 1e-8, _rel_l2(gn, gn_cpu)
+    assert _rel_l2(gq, gq_cpu) <= 1e-8, _rel_l2(gq, gq_cpu)
+    # the gradients reach the section's cells and the hydrograph
+    assert np.abs(gq_cpu).max() > 0 and np.count_nonzero(gn_cpu) > nx * ny // 2
+
+
 def test_fp32_gpu_adjoint_close_to_fp64():
     sc64 = _cast(_pin_scen(True), np.float64)
     sc32 = _cast(sc64, np.float32)
