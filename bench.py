@@ -211,17 +211,23 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
     b.close()
     for f in ctxs:
         f.close()
+    def multi_step_batch(k):
+        """The same members from the same start, k steps per queue entry."""
+        ctxk = [fl.from_scenario(sc, "f32", stream=stream, fusion=k) for sc in scs]
+        bk = fl.Batch(ctxk)
+        bk.set_fusion(k)
+        bestk, _ = bk.autotune(BATCH2_TILINGS, trial_steps)
+        ms = bk.time(steps)
+        repk = [f.get_report() for f in ctxk]
+        bk.close()
+        for f in ctxk:
+            f.close()
+        return bestk, ms, repk
+
     progress("ensemble: batch done; two steps per queue entry")
-    # the same members from the same start, two steps per queue entry
-    ctx2 = [fl.from_scenario(sc, "f32", stream=stream, fusion=2) for sc in scs]
-    b2 = fl.Batch(ctx2)
-    b2.set_fusion(2)
-    best2, _ = b2.autotune(BATCH2_TILINGS, trial_steps)
-    batch2_ms = b2.time(steps)
-    rep2 = [f.get_report() for f in ctx2]
-    b2.close()
-    for f in ctx2:
-        f.close()
+    best2, batch2_ms, rep2 = multi_step_batch(2)
+    progress("ensemble: three steps per queue entry")
+    best3, batch3_ms, rep3 = multi_step_batch(3)
     progress("ensemble: with active tiles")
     # the same members from the same start with active tiles (tilings autotuned
     # on skipping trial steps): batched, and one after another
@@ -256,14 +262,22 @@ def run_ensemble(fl, torch, steps: int, members: int = 64, trial_steps: int = 20
                                "hbm_frac_one_pass_per_two_steps": round(
                                    16 * cells * steps / (batch2_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                "max_budget_error": max(r.budget_error() for r in rep2)},
+            "three_step_batch": {"tiling_autotuned": list(best3),
+                                 "gcell_s": round(cells * steps / (batch3_ms / 1e3) / 1e9, 3),
+                                 "vs_one_step_batch": round(batch_ms / batch3_ms, 3),
+                                 "vs_two_step_batch": round(batch2_ms / batch3_ms, 3),
+                                 "vs_sequential": round(seq_ms / batch3_ms, 3),
+                                 "hbm_frac_one_pass_per_three_steps": round(
+                                     32 / 3 * cells * steps / (batch3_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "max_budget_error": max(r.budget_error() for r in rep3)},
             "sequential_gcell_s": round(cells * steps / (seq_ms / 1e3) / 1e9, 3),
             "batch_vs_sequential": round(seq_ms / batch_ms, 3),
             "sequential_two_step_gcell_s": round(cells * steps / (seq2_ms / 1e3) / 1e9, 3),
             "sequential_three_step_gcell_s": round(cells * steps / (seq3_ms / 1e3) / 1e9, 3),
             "best_sequential_gcell_s": round(cells * steps / (seq_best / 1e3) / 1e9, 3),
             "batch_vs_best_sequential": round(seq_best / batch_ms, 3),
-            "best_batch_gcell_s": round(cells * steps / (min(batch_ms, batch2_ms) / 1e3) / 1e9, 3),
-            "best_batch_vs_best_sequential": round(seq_best / min(batch_ms, batch2_ms), 3),
+            "best_batch_gcell_s": round(cells * steps / (min(batch_ms, batch2_ms, batch3_ms) / 1e3) / 1e9, 3),
+            "best_batch_vs_best_sequential": round(seq_best / min(batch_ms, batch2_ms, batch3_ms), 3),
             "batch_hbm_frac": round(32 * cells * steps / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "max_budget_error": max(r.budget_error() for r in rep)}
 

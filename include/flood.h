@@ -268,7 +268,7 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
  * bitwise those of one step per launch.  fl_step then synchronises the
  * context's stream before it returns; a count of 1 still makes a
  * single-step launch.  fl_advance, fl_autotune and reverse mode use
- * single-step launches, batches one or two steps per queue entry
+ * single-step launches, batches one, two or three steps per queue entry
  * (fl_batch_set_fusion).  Active tiles allow at most 2, 4 cells per lane only
  * 2 (fl_commit: EINVAL otherwise).  Takes effect at the next fl_commit.
  * EINVAL: steps_per_launch not 1, 2 or 3, an unsupported tiling. */
@@ -422,16 +422,16 @@ fl_status fl_batch_create(fl_batch **batch, int32_t nmembers, fl_ctx *const *mem
  * FP64: 1, 2) and rows per work item (>= 1).  Default 4 (FP64 2) and 16. */
 fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t rows_per_item);
 
-/* Steps per queue entry of the batch launch: 1 (default) or 2.  With 2 every
- * member makes the two-step launches of fl_set_fusion(ctx, 2, ...) (one read
- * and one write of its state per two steps of Methods, eqs. 3-6; under the CFL
- * clock the second step's dt is speculated, checked by the member's next
+/* Steps per queue entry of the batch launch: 1 (default), 2 or 3.  With k > 1
+ * every member makes the k-step launches of fl_set_fusion(ctx, k, ...) (one
+ * read and one write of its state per k steps of Methods, eqs. 3-6; under the
+ * CFL clock the later steps' dts are speculated, checked by the member's next
  * launch and redone if wrong) inside the one persistent launch, so members
- * wait for their own previous launch half as often; results stay bitwise those
- * of stepping each member alone.  Every member must have been committed after
- * fl_set_fusion(ctx, 2 or 3, ...) (ESTATE otherwise) and run without active tiles
- * (EINVAL).  cells_per_lane (1 or 2; 0: 2 in FP32, 1 in FP64) and
- * rows_per_item (>= 1; 0: 32) are the two-step tiling, which
+ * wait for their own previous launch k times less often; results stay bitwise
+ * those of stepping each member alone.  Every member must have been committed
+ * after fl_set_fusion(ctx, 2 or 3, ...) (ESTATE otherwise) and run without
+ * active tiles (EINVAL).  cells_per_lane (1 or 2; 0: 2 in FP32, 1 in FP64)
+ * and rows_per_item (>= 1; 0: 32) are the multi-step tiling, which
  * fl_batch_autotune then tunes.  fl_batch_run_noalloc always runs one step
  * per entry.  EINVAL: other values. */
 fl_status fl_batch_set_fusion(fl_batch *batch, int32_t steps_per_entry, int32_t cells_per_lane,

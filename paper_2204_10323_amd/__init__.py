@@ -529,8 +529,9 @@ class Batch:
         self._check(lib().fl_batch_set_tiling(self.b, cells_per_lane, rows_per_item))
 
     def set_fusion(self, steps_per_entry: int, cells_per_lane: int = 0, rows_per_item: int = 0):
-        """fl_batch_set_fusion: one or two steps per queue entry (two needs
-        members committed with fusion=2 and without active tiles)."""
+        """fl_batch_set_fusion: one, two or three steps per queue entry (more
+        than one needs members committed with fusion 2 or 3 and without active
+        tiles)."""
         self._live()
         self._check(lib().fl_batch_set_fusion(self.b, steps_per_entry, cells_per_lane, rows_per_item))
 

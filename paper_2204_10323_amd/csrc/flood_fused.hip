@@ -646,20 +646,20 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && CPT == 2) ? 3 : 1) void k_f
     fused_tile<T, CPT, K, ACT, false>(A, P, wave);
 }
 
-// Persistent batch with two steps per queue entry: the two-step launches of
-// many members in one launch.  Per XCD the queue holds, launch after launch,
-// for each member its clock entry and its two-step work items; an entry of a
-// member's launch l waits only until that member's launch l - 1 is complete.
-// Every entry derives the launch's plan from the member's device clock, as the
-// waves of a two-step launch do, so each member makes exactly the launches
-// (steps, speculated second steps, redos) of its own two-step run, and its
-// state is bitwise that of stepping it alone.  Queue, hand-over between
+// Persistent batch with K = 2 or 3 steps per queue entry: the K-step launches
+// of many members in one launch.  Per XCD the queue holds, launch after
+// launch, for each member its clock entry and its K-step work items; an entry
+// of a member's launch l waits only until that member's launch l - 1 is
+// complete.  Every entry derives the launch's plan from the member's device
+// clock, as the waves of a K-step launch do, so each member makes exactly the
+// launches (steps, speculated later steps, redos) of its own K-step run, and
+// its state is bitwise that of stepping it alone.  Queue, hand-over between
 // launches and progress argument as in k_batch (flood_kernels.hip): an entry
 // waits only for entries of lower queue index, which running waves took
 // before it.
 // (FP32: two waves per SIMD; with three the queue's state spills the row
 // pointers of the marchers to scratch)
-template <typename T, int CPT>
+template <typename T, int CPT, int K>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_batch2(
     Batch2Args<T> B, const BatchScen2<T>* __restrict__ scen) {
     // scen is not written during the launch: its loads may be repeated instead of held
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_batch2(
         const FusedArgs<T>& A = S.a2[l == B.nlaunch - 1 ? 1 : 0][(int)((B.l0 + l) % 6)];
         const FusedPlan P = make_plan<T>(A);
         if (e == 0) clock_wave_fused<T>(A, P);
-        else if (P.ns != 0) fused_tile<T, CPT, 2, false, true>(A, P, e - 1);
+        else if (P.ns != 0) fused_tile<T, CPT, K, false, true>(A, P, e - 1);
         __builtin_amdgcn_s_waitcnt(0);
         __asm__ volatile("" ::: "memory");
         if (lane == 0) atomicAdd(&B.done[m], 1ull);
@@ -817,31 +817,42 @@ hipError_t launch_leave_fused(const StepArgs<T>& single, const FusedArgs<T>& af,
     return hipGetLastError();
 }
 
-template <typename T, int CPT>
-static hipError_t launch_batch2_cpt(const Batch2Args<T>& b, int device, hipStream_t s, int* blocks_out) {
+template <typename T, int CPT, int K>
+static hipError_t launch_batch2_k(const Batch2Args<T>& b, int device, hipStream_t s, int* blocks_out) {
     int per_cu = 0, ncu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch2<T, CPT>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch2<T, CPT, K>, 256, 0);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
     const int blocks = std::max(1, per_cu) * ncu;
     if (blocks_out) *blocks_out = blocks;
     // an ordinary launch: the queue needs no co-residency (see k_batch2)
-    hipLaunchKernelGGL((k_batch2<T, CPT>), dim3(blocks), dim3(256), 0, s, b, b.scen);
+    hipLaunchKernelGGL((k_batch2<T, CPT, K>), dim3(blocks), dim3(256), 0, s, b, b.scen);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int device, hipStream_t s, int* blocks_out) {
-    switch (cpt) {
-    case 1: return launch_batch2_cpt<T, 1>(b, device, s, blocks_out);
-    case 2: return launch_batch2_cpt<T, 2>(b, device, s, blocks_out);
-    default: return hipErrorInvalidValue;
+hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int k, int device, hipStream_t s,
+                         int* blocks_out) {
+    if (k == 2) {
+        switch (cpt) {
+        case 1: return launch_batch2_k<T, 1, 2>(b, device, s, blocks_out);
+        case 2: return launch_batch2_k<T, 2, 2>(b, device, s, blocks_out);
+        default: return hipErrorInvalidValue;
+        }
     }
+    if (k == 3) {
+        switch (cpt) {
+        case 1: return launch_batch2_k<T, 1, 3>(b, device, s, blocks_out);
+        case 2: return launch_batch2_k<T, 2, 3>(b, device, s, blocks_out);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
-template hipError_t launch_batch2<float>(const Batch2Args<float>&, int, int, hipStream_t, int*);
-template hipError_t launch_batch2<double>(const Batch2Args<double>&, int, int, hipStream_t, int*);
+template hipError_t launch_batch2<float>(const Batch2Args<float>&, int, int, int, hipStream_t, int*);
+template hipError_t launch_batch2<double>(const Batch2Args<double>&, int, int, int, hipStream_t, int*);
 template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t);
 template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t);
 template hipError_t launch_enter_fused<float>(const StepArgs<float>&, long long, int, hipStream_t);

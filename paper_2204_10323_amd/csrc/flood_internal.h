@@ -153,19 +153,18 @@ struct BatchArgs {
     long long spin_limit;
 };
 
-// A member of a batch run with two steps per queue entry: its two-step
-// launch arguments (K = 2) by settling flag and launch counter modulo 6, and
-// its work.
+// A member of a batch run with K = 2 or 3 steps per queue entry: its K-step
+// launch arguments by settling flag and launch counter modulo 6, and its work.
 template <typename T>
 struct BatchScen2 {
     FusedArgs<T> a2[2][6];  // [resolve][launch counter % 6]
-    int items;              // two-step work items per launch
+    int items;              // K-step work items per launch
     int first;              // offset of this member's (1 + items) entries within a launch
 };
 
-// A two-step batch run: every member makes `nlaunch` two-step launches with
+// A K-step batch run: every member makes `nlaunch` K-step launches with
 // counters l0 .. l0 + nlaunch - 1, the last of which only settles (checks, and
-// if needed redoes, the previous launch's speculated step).  Queue layout and
+// if needed redoes, the previous launch's speculated steps).  Queue layout and
 // hand-over as in BatchArgs.
 template <typename T>
 struct Batch2Args {
@@ -271,9 +270,11 @@ hipError_t launch_enter_fused(const StepArgs<T>& single, long long target, int k
 template <typename T>
 hipError_t launch_leave_fused(const StepArgs<T>& single, const FusedArgs<T>& af,
                               long long launches, hipStream_t s);
-// A persistent batch launch with two steps per queue entry (flood_fused.hip).
+// A persistent batch launch with k = 2 or 3 steps per queue entry
+// (flood_fused.hip).
 template <typename T>
-hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int device, hipStream_t s, int* blocks_out);
+hipError_t launch_batch2(const Batch2Args<T>& b, int cpt, int k, int device, hipStream_t s,
+                         int* blocks_out);
 
 int strip_width(int cpt);                 // output columns per work item for cells-per-lane cpt
 int strip_width_fused(int cpt, int k);    // the same for k steps per launch

@@ -2071,7 +2071,7 @@ struct fl_batch {
     unsigned long long* d_sync = nullptr;   // [0] queue head, [1..] per-member done counts
     int* d_error = nullptr;
     int last_blocks = 0;
-    int fuse = 1, cpt2 = 0, rows2 = 0;   // steps per queue entry and the two-step tiling
+    int fuse = 1, cpt2 = 0, rows2 = 0;   // steps per queue entry and the multi-step tiling
     void* d_scen2 = nullptr;
     size_t scen2_bytes = 0;
     std::vector<int> member_xcd;    // XCD each member runs on (planning scratch, sized at create)
@@ -2273,30 +2273,32 @@ fl_status batch_launch_noalloc(fl_batch* b, long long nsteps) {
     return batch_execute<T>(b, nsteps, 0, nullptr, ba, hs, d_scen, d_sync, d_error);
 }
 
-// Can the members run two steps per queue entry?  They need the multi-step
-// buffers (committed after fl_set_fusion(ctx, 2 or 3, ...)) and no active tiles.
+// Can the members run several steps per queue entry?  They need the
+// multi-step buffers (committed after fl_set_fusion(ctx, 2 or 3, ...)) and no
+// active tiles.
 fl_status batch_check_two_step(fl_batch* b) {
     for (fl_ctx* c : b->members) {
         if (!c->d_part2[0])
-            return bfail(b, FL_ESTATE, "two steps per queue entry: every member must be committed "
-                                       "after fl_set_fusion(ctx, 2 or 3, ...)");
+            return bfail(b, FL_ESTATE, "several steps per queue entry: every member must be "
+                                       "committed after fl_set_fusion(ctx, 2 or 3, ...)");
         if (c->active)
-            return bfail(b, FL_EINVAL, "two steps per queue entry: members with active tiles run "
-                                       "one step per entry");
+            return bfail(b, FL_EINVAL, "several steps per queue entry: members with active tiles "
+                                       "run one step per entry");
     }
     return FL_OK;
 }
 
-// nsteps steps of every member with two steps per queue entry: the members'
-// single-step state (budget folded) becomes their two-step clock, as in
-// fused_steps_t; a round of batched two-step launches (about nsteps/2 plus one
-// that settles) follows, further rounds only if redos or one-step launches
+// nsteps steps of every member with K = 2 or 3 steps per queue entry: the
+// members' single-step state (budget folded) becomes their multi-step clock,
+// as in fused_steps_t; a round of batched K-step launches (about nsteps/K plus
+// one that settles) follows, further rounds only if redos or shorter launches
 // left a member short; finally every member's state becomes its single-step
 // state again.
 template <typename T>
 fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
     fl_status st = batch_check_two_step(b);
     if (st) return st;
+    const int K = b->fuse;
     const int S = (int)b->members.size();
     for (fl_ctx* c : b->members) BHIP_TRY(b, hipStreamSynchronize(c->stream));
     for (fl_ctx* c : b->members) {
@@ -2328,10 +2330,10 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
             const int m = b->order[k];
             if (b->member_xcd[m] != x) continue;
             fl_ctx* c = b->members[m];
-            const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, 2);
+            const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, K);
             for (int res = 0; res < 2; ++res)
                 for (int ph = 0; ph < 6; ++ph)
-                    scen[idx].a2[res][ph] = make_args_fused_tl<T>(c, ph, res, tl, 2, freeze);
+                    scen[idx].a2[res][ph] = make_args_fused_tl<T>(c, ph, res, tl, K, freeze);
             scen[idx].items = tl.nstrips * tl.nchunks;
             scen[idx].first = first;
             first += 1 + scen[idx].items;
@@ -2361,7 +2363,7 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         BHIP_TRY(b, hipEventRecord(e0.e, b->stream));
     }
     std::vector<FusedClock> slot(S);
-    long long lc = 0, want = (nsteps + 1) / 2;
+    long long lc = 0, want = (nsteps + K - 1) / K;
     for (int round = 0;; ++round) {
         BHIP_TRY(b, launch_fill_bytes(reinterpret_cast<unsigned char*>(b->d_sync),
                                       (long long)(sizeof(unsigned long long) * (S + kMaxXcc)), 0,
@@ -2370,7 +2372,7 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
                                       b->stream));
         ba.l0 = lc;
         ba.nlaunch = want + 1;   // the last launch only settles
-        BHIP_TRY(b, launch_batch2<T>(ba, b->cpt2, b->device, b->stream, &b->last_blocks));
+        BHIP_TRY(b, launch_batch2<T>(ba, b->cpt2, K, b->device, b->stream, &b->last_blocks));
         lc += want + 1;
         if (ms) BHIP_TRY(b, hipEventRecord(e1.e, b->stream));
         int error = 0;
@@ -2382,20 +2384,20 @@ fl_status batch2_launch(fl_batch* b, long long nsteps, int freeze, float* ms) {
         if (error) return bfail(b, FL_EHIP, "fl_batch_run: a wait for a member's previous launch timed out");
         long long short_by = 0;
         for (int m = 0; m < S; ++m) {
-            if (slot[m].pending) return bfail(b, FL_EHIP, "two-step batch: unsettled member state");
+            if (slot[m].pending) return bfail(b, FL_EHIP, "multi-step batch: unsettled member state");
             short_by = std::max(short_by, nsteps - slot[m].vsteps);
         }
         if (short_by <= 0) break;
-        if (round >= 64) return bfail(b, FL_EHIP, "two-step batch: no progress");
+        if (round >= 64) return bfail(b, FL_EHIP, "multi-step batch: no progress");
         want = short_by;   // enough even if every launch makes one step
     }
     if (ms) BHIP_TRY(b, hipEventElapsedTime(ms, e0.e, e1.e));
     for (int m = 0; m < S; ++m) {
         fl_ctx* c = b->members[m];
-        const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, 2);
+        const Tiling tl = tiling_fused_of(c, b->cpt2, b->rows2, K);
         long long n2 = c->nstep + nsteps;
         n2 += (n2 ^ (long long)slot[m].cur) & 1;
-        BHIP_TRY(b, launch_leave_fused<T>(make_args<T>(c, n2), make_args_fused_tl<T>(c, 0, 0, tl, 2, 0),
+        BHIP_TRY(b, launch_leave_fused<T>(make_args<T>(c, n2), make_args_fused_tl<T>(c, 0, 0, tl, K, 0),
                                           lc, b->stream));
         c->nstep = n2;
     }
@@ -2411,7 +2413,7 @@ fl_status batch_run(fl_batch* b, long long nsteps, int freeze, float* ms) {
         return FL_OK;
     }
     BHIP_TRY(b, hipSetDevice(b->device));
-    if (b->fuse == 2 && nsteps >= 2)
+    if (b->fuse >= 2 && nsteps >= 2)
         return b->prec == FL_F64 ? batch2_launch<double>(b, nsteps, freeze, ms)
                                  : batch2_launch<float>(b, nsteps, freeze, ms);
     return b->prec == FL_F64 ? batch_launch<double>(b, nsteps, freeze, ms)
@@ -2492,12 +2494,12 @@ fl_status fl_batch_set_tiling(fl_batch* b, int32_t cells_per_lane, int32_t rows_
 fl_status fl_batch_set_fusion(fl_batch* b, int32_t steps_per_entry, int32_t cells_per_lane,
                               int32_t rows_per_item) {
     if (!b) return FL_EINVAL;
-    if (steps_per_entry != 1 && steps_per_entry != 2)
-        return bfail(b, FL_EINVAL, "fl_batch_set_fusion: steps_per_entry must be 1 or 2");
+    if (steps_per_entry < 1 || steps_per_entry > 3)
+        return bfail(b, FL_EINVAL, "fl_batch_set_fusion: steps_per_entry must be 1, 2 or 3");
     if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2)
         return bfail(b, FL_EINVAL, "fl_batch_set_fusion: cells_per_lane must be 0, 1 or 2");
     if (rows_per_item < 0) return bfail(b, FL_EINVAL, "fl_batch_set_fusion: rows_per_item < 0");
-    if (steps_per_entry == 2) {
+    if (steps_per_entry >= 2) {
         fl_status st = batch_check_two_step(b);
         if (st) return st;
     }
@@ -2536,14 +2538,14 @@ fl_status fl_batch_time(fl_batch* b, int64_t nsteps, double* elapsed_ms) {
 fl_status fl_batch_autotune(fl_batch* b, const int32_t* candidates, int32_t ncand, int32_t trial_steps,
                             int32_t* best, double* best_ms) {
     if (!b || !candidates || ncand < 1 || trial_steps < 1) return FL_EINVAL;
-    const bool two = b->fuse == 2;
+    const bool two = b->fuse >= 2;
     int& cpt_ref = two ? b->cpt2 : b->cpt;
     int& rows_ref = two ? b->rows2 : b->rows;
     const int cpt0 = cpt_ref, rows0 = rows_ref;
     double best_t = 1e300;
     int bc = -1;
     for (int k = 0; k < ncand; ++k) {
-        fl_status st = two ? fl_batch_set_fusion(b, 2, candidates[2 * k], candidates[2 * k + 1])
+        fl_status st = two ? fl_batch_set_fusion(b, b->fuse, candidates[2 * k], candidates[2 * k + 1])
                            : fl_batch_set_tiling(b, candidates[2 * k], candidates[2 * k + 1]);
         if (!st && two && candidates[2 * k] == 0)
             st = bfail(b, FL_EINVAL, "fl_batch_autotune: cells_per_lane must be 1 or 2");

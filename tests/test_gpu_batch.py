@@ -179,12 +179,13 @@ def _basin():
                     (EAST, 0, ny, 1e-3), dt_max=1.0)
 
 
+@pytest.mark.parametrize("k", [2, 3])
 @pytest.mark.parametrize("prec,tiling", [("f32", (2, 32)), ("f32", (1, 8)), ("f32", (2, 5)),
                                          ("f64", (1, 16)), ("f64", (2, 7))])
-def test_two_step_batch_members_equal_single_runs(prec, tiling):
-    """Two steps per queue entry: each member ends as the same scenario stepped
-    alone one step per launch (odd step counts, a member whose CFL bound
-    becomes active, every side pair)."""
+def test_multi_step_batch_members_equal_single_runs(prec, tiling, k):
+    """Two or three steps per queue entry: each member ends as the same scenario
+    stepped alone one step per launch (step counts that are no multiple of k, a
+    member whose CFL bound becomes active, every side pair)."""
     scs = _scenarios() + [_basin()]
     chunks = [151, 150]
     ref = []
@@ -194,10 +195,10 @@ def test_two_step_batch_members_equal_single_runs(prec, tiling):
             f.step(n)
         ref.append(_state(f))
         f.close()
-    members = [fl.from_scenario(sc, prec, fusion=2) for sc in scs]
+    members = [fl.from_scenario(sc, prec, fusion=k) for sc in scs]
     b = fl.Batch(members)
-    b.set_fusion(2, *tiling)
-    print("CASE two-step batch", prec, tiling, flush=True)
+    b.set_fusion(k, *tiling)
+    print("CASE multi-step batch", k, prec, tiling, flush=True)
     for n in chunks:
         b.run(n)
     b.close()
@@ -207,14 +208,15 @@ def test_two_step_batch_members_equal_single_runs(prec, tiling):
     assert ref[-1][3].last_dt < 1.0   # the basin's bound became active
 
 
-def test_two_step_batch_autotune_and_interleaving():
-    """The two-step batch autotuner leaves states untouched; batched two-step
+@pytest.mark.parametrize("k", [2, 3])
+def test_multi_step_batch_autotune_and_interleaving(k):
+    """The multi-step batch autotuner leaves states untouched; batched multi-step
     runs, one-step batch runs and the members' own steps interleave."""
     scs = _scenarios()
     ref = [run_gpu(sc, 260, "f32") for sc in scs]
-    members = [fl.from_scenario(sc, "f32", fusion=2) for sc in scs]
+    members = [fl.from_scenario(sc, "f32", fusion=k) for sc in scs]
     b = fl.Batch(members)
-    b.set_fusion(2)
+    b.set_fusion(k)
     best, _ = b.autotune([(2, 32), (1, 16), (2, 8)], 6)
     assert best in [(2, 32), (1, 16), (2, 8)]
     b.run(100)
@@ -222,7 +224,7 @@ def test_two_step_batch_autotune_and_interleaving():
         f.step(21)
     b.set_fusion(1)
     b.run(39)
-    b.set_fusion(2, *best)
+    b.set_fusion(k, *best)
     b.run(100)
     b.close()
     for sc, f, (h0, qx0, qy0, r0) in zip(scs, members, ref):
@@ -238,8 +240,12 @@ def test_two_step_batch_refusals():
     with pytest.raises(fl.FloodError) as e:
         b.set_fusion(2)
     assert e.value.status == fl.FL_ESTATE
-    with pytest.raises(fl.FloodError):
+    with pytest.raises(fl.FloodError) as e:
         b.set_fusion(3)
+    assert e.value.status == fl.FL_ESTATE
+    with pytest.raises(fl.FloodError) as e:
+        b.set_fusion(4)
+    assert e.value.status == fl.FL_EINVAL
     b.close()
     act = [fl.from_scenario(sc, "f32", fusion=2, active_tiles=True) for sc in scs]
     b = fl.Batch(act)
