@@ -4,7 +4,8 @@
 (each its own DEM, a uniform Manning n in [0.02, 0.08] stored as a field, and
 a triangular hydrograph peaking at 50-800 m^3/s), 5000 CFL steps each, FP32,
 all in ONE persistent batch launch with the tiling the benchmark's batch
-autotuner picks.  A size-stratified subset of six members, the smallest and
+autotuner picks (one step per queue entry; with three steps per entry every
+member ends bit for bit the same).  A size-stratified subset of six members, the smallest and
 the largest included, is compared cell by cell with the oracle run on the same
 float32 inputs: max|dh| <= 1e-3 m (the FP32 gate), the member's FP64 volume
 budget <= 1e-6 of the volume that entered, and its clock.
@@ -44,6 +45,21 @@ def test_ensemble_64_members_5000_steps_one_launch_against_oracle():
     for f in members:
         r = f.get_report()
         assert r.steps == STEPS and r.budget_error() <= 1e-6
+    # the benchmark's fastest batch configuration, three steps per queue entry,
+    # gives every member bit for bit the state checked against the oracle below
+    from bench import BATCH2_TILINGS
+    members3 = [fl.from_scenario(sc, "f32", fusion=3) for sc in scs]
+    b3 = fl.Batch(members3)
+    b3.set_fusion(3)
+    best3, _ = b3.autotune(BATCH2_TILINGS, 20)
+    print(f"CASE ensemble gate: three steps per queue entry, tiling {best3}", flush=True)
+    b3.run(STEPS)
+    b3.close()
+    for s, (f, g) in enumerate(zip(members, members3)):
+        r, r3 = f.get_report(), g.get_report()
+        assert np.array_equal(f.get_depth(), g.get_depth()), f"member {s}"
+        assert r3.steps == r.steps and r3.t == r.t and r3.v_in == r.v_in, f"member {s}"
+        g.close()
     for s in pick:
         sc, f = scs[s], members[s]
         h = f.get_depth()
