@@ -162,7 +162,7 @@ SMALL_GRID_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
 # ... and by the batch autotuner on the 64-member ensemble, one step per queue
 # entry and two (the two-step tiling)
 BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32)]
-BATCH2_TILINGS = [(2, 32), (2, 64), (2, 128), (1, 64)]
+BATCH2_TILINGS = [(2, 32), (2, 64), (2, 96), (2, 128), (1, 64)]
 
 
 def progress(msg: str):

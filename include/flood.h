@@ -431,7 +431,7 @@ fl_status fl_batch_set_tiling(fl_batch *batch, int32_t cells_per_lane, int32_t r
  * those of stepping each member alone.  Every member must have been committed
  * after fl_set_fusion(ctx, 2 or 3, ...) (ESTATE otherwise) and run without
  * active tiles (EINVAL).  cells_per_lane (1 or 2; 0: 2 in FP32, 1 in FP64)
- * and rows_per_item (>= 1; 0: 32) are the multi-step tiling, which
+ * and rows_per_item (>= 1; 0: 64) are the multi-step tiling, which
  * fl_batch_autotune then tunes.  fl_batch_run_noalloc always runs one step
  * per entry.  EINVAL: other values. */
 fl_status fl_batch_set_fusion(fl_batch *batch, int32_t steps_per_entry, int32_t cells_per_lane,

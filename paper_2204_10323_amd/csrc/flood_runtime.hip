@@ -2505,7 +2505,7 @@ fl_status fl_batch_set_fusion(fl_batch* b, int32_t steps_per_entry, int32_t cell
     }
     b->fuse = steps_per_entry;
     b->cpt2 = cells_per_lane ? cells_per_lane : (b->prec == FL_F64 ? 1 : 2);
-    b->rows2 = rows_per_item ? rows_per_item : 32;
+    b->rows2 = rows_per_item ? rows_per_item : 64;
     return FL_OK;
 }
 
