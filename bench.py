@@ -458,13 +458,15 @@ def run_sweep(fl, torch, steps: int = 4000, nx: int = 1024, members: int = 16):
             "max_depth_m": [round(float(h), 3) for h in out["max_depth"]],
             "max_budget_error": float(out["budget_error"].max()),
             "mode": out["mode"],
+            "steps_per_entry": out["steps_per_entry"],
             "gcell_s": round(gcell, 3),
             "active_tiles_gcell_s_grid_equivalent": round(gcell_act, 3),
             "active_tiles_vs_gcell_s": round(gcell_act / gcell, 2),
             "active_tiles_same_results": bool(
                 np.array_equal(act["flooded_cells"], out["flooded_cells"]) and
                 np.array_equal(act["max_depth"], out["max_depth"]) and
-                np.array_equal(act["v_in"], out["v_in"]) and np.array_equal(act["v_out"], out["v_out"]))}
+                np.array_equal(act["v_in"], out["v_in"]) and
+                np.allclose(act["v_out"], out["v_out"], rtol=1e-13, atol=0.0))}
 
 
 def main():

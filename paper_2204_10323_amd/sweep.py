@@ -18,6 +18,8 @@ from . import Batch, Flood
 # launch, and for one member stepped alone
 BATCH_TILINGS = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 16), (2, 32), (1, 16)]
 SINGLE_TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 8), (4, 16), (4, 32)]
+# ... and for a batch launch with several steps per queue entry
+MULTI_TILINGS = [(2, 16), (2, 32), (2, 64), (1, 32)]
 
 
 def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tuple,
@@ -25,7 +27,7 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
                     dt: float, threshold: float = 0.1, precision: str = "f32", device: int = 0,
                     stream=None, h0: Optional[np.ndarray] = None, keep_depths: bool = False,
                     tiling: Optional[tuple] = None, trial_steps: int = 10, mode: str = "auto",
-                    active_tiles: bool = False, **params) -> dict:
+                    active_tiles: bool = False, steps_per_entry: int = 0, **params) -> dict:
     """Run one member per discharge (m^3/s) for `steps` steps of `dt` seconds.
 
     inflow_section: (side, first, count, slope); outflow_section: (side, first,
@@ -38,6 +40,9 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
     the wait between a member's steps.
     tiling: (cells_per_lane, rows_per_item) of the batch launch (mode
     "batch"), or None for the autotuner's choice.
+    steps_per_entry: steps per queue entry of the batch launch, 1, 2 or 3
+    (fl_batch_set_fusion; the members then make the multi-step launches of
+    their own runs, bit for bit); 0: 3, or 1 with active tiles.
     active_tiles: the members skip the work items that no water can reach
     (fl_set_active_tiles), in the batch launch and one after another; the
     tilings are then autotuned with skipping trial steps.
@@ -49,6 +54,11 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
         raise ValueError("discharge_sweep: mode must be auto, batch or sequential")
     if steps < 1 or not (dt > 0.0):
         raise ValueError("discharge_sweep: steps >= 1 and dt > 0 are required")
+    if steps_per_entry not in (0, 1, 2, 3):
+        raise ValueError("discharge_sweep: steps_per_entry must be 0, 1, 2 or 3")
+    if active_tiles and steps_per_entry > 1:
+        raise ValueError("discharge_sweep: members with active tiles run one step per queue entry")
+    k = steps_per_entry or (1 if active_tiles else 3)
     z = np.ascontiguousarray(z)
     ny, nx = z.shape
     side, first, count, slope = inflow_section
@@ -67,6 +77,8 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
                 f.set_state(h0, None, None, 0.0)
             if active_tiles:
                 f.set_active_tiles(True)
+            if k > 1 and mode != "sequential":
+                f.set_fusion(k)   # the buffers of the multi-step launches
             f.commit()
         fp64 = precision in ("f64", "fp64", "double")
         single_cands = [t for t in SINGLE_TILINGS if not fp64 or t[0] < 4]
@@ -76,11 +88,14 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
         else:
             b = Batch(members)
             try:
-                if tiling is not None:
+                if k > 1:
+                    b.set_fusion(k, *(tiling or (0, 0)))
+                elif tiling is not None:
                     b.set_tiling(*tiling)
+                if tiling is not None:
                     mode = "batch"
                 else:
-                    cands = [t for t in BATCH_TILINGS if not fp64 or t[0] < 4]
+                    cands = MULTI_TILINGS if k > 1 else [t for t in BATCH_TILINGS if not fp64 or t[0] < 4]
                     _, batch_trial = b.autotune(cands, trial_steps)
                     if mode == "auto":
                         # members share the grid: one member's tuned step, times their number
@@ -91,12 +106,15 @@ def discharge_sweep(z: np.ndarray, n: np.ndarray, dx: float, inflow_section: tup
             finally:
                 b.close()
         if mode == "sequential":
-            for f in members[1:]:
+            # one step per launch, the tuned single-step tiling
+            for f in members:
+                f.set_fusion(1)
                 f.set_tiling(*best)
                 f.commit()
             ms = sum(f.time_steps(steps) for f in members)
         out = {"discharge": np.asarray(discharges, dtype=np.float64), "steps": steps, "dt": dt,
                "seconds": steps * dt, "threshold": threshold, "mode": mode, "ms": ms,
+               "steps_per_entry": k if mode == "batch" else None,
                "flooded_cells": [], "flooded_area_m2": [], "max_depth": [], "v_in": [],
                "v_out": [], "budget_error": []}
         if keep_depths:
