@@ -49,3 +49,21 @@ def test_torch_host_tensors():
     assert dev == 0 and p.value == o.data_ptr()
     with pytest.raises(ValueError):
         fl._as_output(torch.zeros((3, 4), dtype=torch.float64), np.float32, (3, 4), "out")
+
+
+def test_discharge_sweep_argument_checks():
+    """The sweep helper refuses bad settings before it creates a context."""
+    import numpy as np
+    import pytest
+    from paper_2204_10323_amd.sweep import discharge_sweep
+    z = np.zeros((8, 8), np.float32)
+    n = np.full((8, 8), 0.03, np.float32)
+    sec = (0, 2, 3, 1e-3)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, sec, None, [1.0], 10, 0.1, mode="fast")
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, sec, None, [1.0], 0, 0.1)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, sec, None, [1.0], 10, 0.1, steps_per_entry=4)
+    with pytest.raises(ValueError):
+        discharge_sweep(z, n, 1.0, sec, None, [1.0], 10, 0.1, steps_per_entry=3, active_tiles=True)
