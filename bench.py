@@ -351,13 +351,13 @@ def run_active(fl, torch, sc, warmup: int, steps: int, full_value: float, full_d
                sample_every: int = 50):
     """The same workload with active-tile skipping.  On the state after the
     warm-up, outside the timed region, the autotuners pick the single-step
-    tiling and then one or two steps per launch, both by skipping trial steps.
+    tiling and then one or three steps per launch, both by skipping trial steps.
     Reports the time per step, the work items computed (read back every
     `sample_every` steps in a second, untimed run) and whether the final depth
     equals that of the run that computes every item."""
     cells = sc.nx * sc.ny
     stream = torch.cuda.current_stream().cuda_stream
-    f = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True, fusion=2)
+    f = fl.from_scenario(sc, "f32", device=0, stream=stream, active_tiles=True, fusion=3)
     f.step(warmup)
     best, _ = f.autotune(ACTIVE_TILINGS, 20)
     spl, _ = f.autotune_fusion(20)

@@ -269,8 +269,8 @@ fl_status fl_set_tiling(fl_ctx *ctx, int32_t cells_per_lane, int32_t rows_per_it
  * context's stream before it returns; a count of 1 still makes a
  * single-step launch.  fl_advance, fl_autotune and reverse mode use
  * single-step launches, batches one, two or three steps per queue entry
- * (fl_batch_set_fusion).  Active tiles allow at most 2, 4 cells per lane only
- * 2 (fl_commit: EINVAL otherwise).  Takes effect at the next fl_commit.
+ * (fl_batch_set_fusion).  4 cells per lane allow at most 2 (fl_commit:
+ * EINVAL otherwise).  Takes effect at the next fl_commit.
  * EINVAL: steps_per_launch not 1, 2 or 3, an unsupported tiling. */
 fl_status fl_set_fusion(fl_ctx *ctx, int32_t steps_per_launch, int32_t cells_per_lane,
                         int32_t rows_per_item);
@@ -300,40 +300,39 @@ typedef enum { FL_BOUNDARY_SECTION = 0, FL_BOUNDARY_CELL_AREA = 1 } fl_boundary;
 fl_status fl_set_variant(fl_ctx *ctx, int32_t friction, int32_t boundary);
 
 /* Active-tile skipping (wet-region skipping) for fl_step, fl_time_steps,
- * fl_advance and the forward of reverse mode, with one or two steps per
- * launch.  A launch does not recompute a work item when no water can reach
+ * fl_advance and the forward of reverse mode, with one, two or three steps
+ * per launch.  A launch does not recompute a work item when no water can reach
  * it: every face between two cells without water is dry in eq. (3) (its
  * water-surface height above the higher bed is <= 0), so no water moves, and
  * the outflow of eq. (5) is zero for an empty edge cell.  One step per launch
  * skips an item when the item and the four items that share an edge with it
  * held no water (h <= 0), kept their depths and carried no discharge in the
- * step before, and the item itself also in the step before that.  Two steps
- * per launch reach two cells further, so they look at the 3 x 3 items around
- * it, by launch (a launch that redoes a guessed second step skips exactly
- * what the launch it replaces skipped).  Items behind an inflow face (eq. 6)
+ * step before, and the item itself also in the step before that.  Two or
+ * three steps per launch reach two or three cells further, so they look at
+ * the 3 x 3 items around it, by launch (a launch that redoes a guessed later
+ * step skips exactly what the launch it replaces skipped).  Items behind an inflow face (eq. 6)
  * are always computed.  Each item records one flag byte per step or launch
  * (three kept).  Results are the values of computing every item (a zero may
  * differ in sign; after a non-finite depth, which stops the clock, the states
  * may differ).  Work scales with the wet area (a flood on a mostly dry DEM)
  * instead of the grid.  Another path that moves the state (batches, frozen
- * tiling trials, the reverse sweep, switching between one and two steps per
- * launch) marks the flags stale; the next skipping launch then computes
+ * tiling trials, the reverse sweep, switching between one and several steps
+ * per launch) marks the flags stale; the next skipping launch then computes
  * every item for two launches.  fl_autotune and fl_autotune_fusion time
  * skipping trial steps.
  * on: 0 off; 1 on, each work item of a single-step launch makes the skip
  * test itself (one wave per item); 2 on, single-step launches first select
  * the items to compute (one thread per item, an ordered list) and a
  * persistent grid computes the list, which is faster when few items hold
- * water.  fl_autotune times both and keeps the faster with the tiling.  Two
- * steps per launch and batches always use the per-item test.  Takes effect
- * at the next fl_commit, which fails with EINVAL for two steps per launch
- * with 1-row work items and for three steps per launch.  EINVAL: on not 0, 1
- * or 2. */
+ * water.  fl_autotune times both and keeps the faster with the tiling.
+ * Several steps per launch and batches always use the per-item test.  Takes
+ * effect at the next fl_commit, which fails with EINVAL for k steps per
+ * launch with work items of fewer than k rows.  EINVAL: on not 0, 1 or 2. */
 fl_status fl_set_active_tiles(fl_ctx *ctx, int32_t on);
 
 /* Work items the next launch computes under active-tile skipping
  * (*next_items) and work items of a launch (*total_items): those of the
- * two-step kernel after a two-step run, else of the single-step kernel.
+ * multi-step kernel after a multi-step run, else of the single-step kernel.
  * Synchronises.  ESTATE: not committed with active tiles on (mode 1 or 2).
  * EINVAL: a NULL output. */
 fl_status fl_active_items(fl_ctx *ctx, int64_t *next_items, int64_t *total_items);

@@ -361,7 +361,7 @@ class Flood:
         return (best[0], best[1]), ms.value
 
     def autotune_fusion(self, trial_steps: int = 20):
-        """Keep one or two steps per launch, whichever frozen trials find faster
+        """Keep one step or the committed k steps per launch, whichever frozen trials find faster
         (fl_autotune_fusion); needs a commit after set_fusion(2 or 3)."""
         spl = C.c_int32()
         ms = C.c_double()

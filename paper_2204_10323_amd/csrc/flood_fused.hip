@@ -507,12 +507,12 @@ __device__ __forceinline__ void inflow_consts(const StepArgs<T>& a, double t, St
     }
 }
 
-// Must item (s, c) be computed by a launch that writes generation gen
-// (active-tile skipping)?  Over two steps a cell depends on the cells up to
-// two away, which lie in the item and the 8 items around it (items are at
-// least two cells tall and wide), so it may be skipped when those nine items
-// were dry and unchanged in generation gen - 1, and the item itself also in
-// gen - 2 (its output buffer still holds that state).  A redo reads the same
+// Must item (s, c) be computed by a launch of K = 2 or 3 steps that writes
+// generation gen (active-tile skipping)?  Over K steps a cell depends on the
+// cells up to K away, which lie in the item and the 8 items around it (items
+// are at least K cells tall and wide), so it may be skipped when those nine
+// items were dry and unchanged in generation gen - 1, and the item itself also
+// in gen - 2 (its output buffer still holds that state).  A redo reads the same
 // slots as the launch it replaces and so skips the same items, whose output
 // buffer that launch left untouched.  Items whose loaded region meets an
 // inflow face are always computed.
@@ -538,7 +538,7 @@ __device__ __forceinline__ bool item_needed2(const StepArgs<T>& a, int s, int c,
 // GA: row pointers typed global (they come from memory in the batch kernel).
 template <typename T, int CPT, int K, bool ACT, bool GA>
 __device__ __forceinline__ void fused_tile(const FusedArgs<T>& A, const FusedPlan& P, int item) {
-    static_assert(!ACT || K == 2, "active tiles: two steps per launch");
+    static_assert(!ACT || K <= 3, "active tiles: two or three steps per launch");
     const StepArgs<T>& a = A.a;
     constexpr int WL = 64 * CPT, WO = WL - 4 * K;
     const int s = item % a.nstrips, c = item / a.nstrips;
@@ -767,13 +767,9 @@ static hipError_t launch_fused_k(const FusedArgs<T>& a, hipStream_t s) {
     const unsigned blocks = (unsigned)(1 + (items + 3) / 4);
     if (a.a.act) {
         // the flags of every item must fit in a slot; the skip test needs
-        // items at least two rows tall and two steps per launch
-        if constexpr (K == 2) {
-            if (items > a.a.act_stride || a.a.rows < 2) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_fused<T, CPT, 2, true>), dim3(blocks), dim3(256), 0, s, a);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        // items at least K rows tall
+        if (items > a.a.act_stride || a.a.rows < K) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_fused<T, CPT, K, true>), dim3(blocks), dim3(256), 0, s, a);
     } else {
         hipLaunchKernelGGL((k_fused<T, CPT, K, false>), dim3(blocks), dim3(256), 0, s, a);
     }

@@ -621,8 +621,6 @@ fl_status do_commit(fl_ctx* c) {
     if (c->variant && (c->fuse >= 2 || c->active))
         return fail(c, FL_EINVAL,
                     "fl_commit: method variants run one step per launch without active tiles");
-    if (c->active && c->fuse >= 3)
-        return fail(c, FL_EINVAL, "fl_commit: active tiles run one or two steps per launch");
     if (c->ws && c->ws_bytes < workspace_bytes(nx, ny, c->prec, c->fuse >= 2, c->active != 0))
         return fail(c, FL_EINVAL, "fl_commit: the bound workspace is smaller than fl_workspace_bytes");
     if (c->cpt == 0) c->cpt = (c->prec == FL_F64) ? 2 : 4;
@@ -760,9 +758,9 @@ fl_status do_commit(fl_ctx* c) {
         if (c->cpt2 == 4 && c->fuse_k != 2)
             return fail(c, FL_EINVAL, "fl_commit: 4 cells per lane run two steps per launch at most");
         c->rows2 = c->rows2_req ? c->rows2_req : default_rows_fused(nx, ny, c->cpt2, c->fuse_k);
-        if (c->active && c->rows2 < 2)
+        if (c->active && c->rows2 < c->fuse_k)
             return fail(c, FL_EINVAL,
-                        "fl_commit: active tiles with two steps per launch need items of >= 2 rows");
+                        "fl_commit: active tiles with k steps per launch need items of >= k rows");
         const Tiling t2 = tiling_fused_of(c, c->cpt2, c->rows2, c->fuse_k);
         c->nstrips2 = t2.nstrips;
         c->nchunks2 = t2.nchunks;
@@ -1231,8 +1229,8 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
     if (!c->committed || !c->active)
         return fail(c, FL_ESTATE, "fl_active_items needs a context committed with active tiles on");
     HIP_TRY(c, hipSetDevice(c->device));
-    if (c->fuse == 2 && c->fuse_k == 2 && c->act_mode == 2 && c->act_at == c->nstep) {
-        // the next two-step launch: the rule of the two-step kernel's skip test
+    if (c->fuse >= 2 && c->fuse_k >= 2 && c->act_mode == 2 && c->act_at == c->nstep) {
+        // the next multi-step launch: the rule of the multi-step kernel's skip test
         const int ns = c->nstrips2, nc = c->nchunks2;
         const long long items = (long long)ns * nc;
         *total_items = items;
@@ -1246,7 +1244,8 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
         HIP_TRY(c, hipMemcpyAsync(f2.data(), c->d_act + ((g + 1) % 3) * c->act_stride, (size_t)items,
                                   hipMemcpyDeviceToHost, c->stream));  // generation g - 2
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        const int wl = 64 * c->cpt2, wo = strip_width_fused(c->cpt2, 2);
+        const int K = c->fuse_k, r = 2 * K;
+        const int wl = 64 * c->cpt2, wo = strip_width_fused(c->cpt2, K);
         const int f0 = c->in_first, fe = c->in_first + c->in_count;
         long long need = 0;
         for (int cc = 0; cc < nc; ++cc)
@@ -1256,12 +1255,12 @@ fl_status fl_active_items(fl_ctx* c, int64_t* next_items, int64_t* total_items) 
                 bool in = false;
                 if (c->in_count > 0) {
                     switch (c->in_side) {
-                    case FL_WEST: in = ss == 0 && j0 - 4 < fe && j1 + 4 > f0; break;
+                    case FL_WEST: in = ss == 0 && j0 - r < fe && j1 + r > f0; break;
                     case FL_EAST:
-                        in = c->nx - 1 >= c0 && c->nx - 1 < c0 + wl && j0 - 4 < fe && j1 + 4 > f0;
+                        in = c->nx - 1 >= c0 && c->nx - 1 < c0 + wl && j0 - r < fe && j1 + r > f0;
                         break;
-                    case FL_SOUTH: in = j0 <= 4 && c0 < fe && c0 + wl > f0; break;
-                    default: in = j1 + 3 >= c->ny && c0 < fe && c0 + wl > f0; break;
+                    case FL_SOUTH: in = j0 <= r && c0 < fe && c0 + wl > f0; break;
+                    default: in = j1 + r - 1 >= c->ny && c0 < fe && c0 + wl > f0; break;
                     }
                 }
                 bool act = in || f2[(size_t)cc * ns + ss];

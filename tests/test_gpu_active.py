@@ -231,45 +231,51 @@ def test_reverse_mode_forward_with_active_tiles():
         assert np.array_equal(np.asarray(a), np.asarray(b))
 
 
-def test_two_steps_per_launch_needs_two_row_items():
+@pytest.mark.parametrize("k", [2, 3])
+def test_k_steps_per_launch_need_k_row_items(k):
     sc = config_d1()
-    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 1), active_tiles=True, commit=False)
+    f = fl.from_scenario(sc, "f32", fusion=(k, 2, k - 1), active_tiles=True, commit=False)
     assert fl.lib().fl_commit(f.ctx) == fl.FL_EINVAL
-    f.set_fusion(2, 2, 2)
+    f.set_fusion(k, 2, k)
     f.commit()
     f.step(6)
     f.close()
 
 
-# ------------------------------------------------ with two steps per launch
+# ------------------------------------------- with two or three steps per launch
+@pytest.mark.parametrize("k", [2, 3])
 @pytest.mark.parametrize("prec,cpt", [("f32", 1), ("f32", 2), ("f32", 4), ("f64", 1), ("f64", 2)])
-def test_two_step_valley256_2000_steps(prec, cpt):
-    """Two steps per launch with skipping against one step per launch that
-    computes everything (the two paths give the same bits)."""
+def test_multi_step_valley256_2000_steps(prec, cpt, k):
+    """Two or three steps per launch with skipping against one step per launch
+    that computes everything (the two paths give the same bits)."""
+    if cpt == 4 and k == 3:
+        pytest.skip("4 cells per lane run two steps per launch at most")
     sc = config_d1()
-    print(f"CASE two-step valley256 active tiles {prec} cpt={cpt}", flush=True)
+    print(f"CASE {k}-step valley256 active tiles {prec} cpt={cpt}", flush=True)
     chunks = [1, 50, 449, 1500]
     ref = _run(sc, prec, chunks, False, (cpt if cpt < 4 or prec == "f32" else 2, 8))
-    got = _run(sc, prec, chunks, True, fusion=(2, cpt, 8))
+    got = _run(sc, prec, chunks, True, fusion=(k, cpt, 8))
     _same(got, ref, f"{prec} cpt={cpt}", other_decomposition=True)
 
 
+@pytest.mark.parametrize("k", [2, 3])
 @pytest.mark.parametrize("seed", range(8))
-def test_two_step_patchy_grids(seed):
+def test_multi_step_patchy_grids(seed, k):
     rng = np.random.default_rng(3000 + seed)
     nx, ny = int(rng.integers(20, 300)), int(rng.integers(10, 120))
     sc = patchy(nx, ny, 4000 + seed)
     cpt = [1, 2][seed % 2]
-    rows = [2, 3, 5, 8][seed % 4]
+    rows = max(k, [2, 3, 5, 8][seed % 4])
     chunks = [1, 2, 7, 30, 3, 61]
     for prec in ("f32", "f64"):
-        print(f"CASE two-step patchy {nx}x{ny} seed {seed} {prec} cpt={cpt} rows={rows}", flush=True)
+        print(f"CASE {k}-step patchy {nx}x{ny} seed {seed} {prec} cpt={cpt} rows={rows}", flush=True)
         ref = _run(sc, prec, chunks, False, (1, 4))
-        got = _run(sc, prec, chunks, True, fusion=(2, cpt, rows))
+        got = _run(sc, prec, chunks, True, fusion=(k, cpt, rows))
         _same(got, ref, f"two-step patchy {nx}x{ny} {prec}", other_decomposition=True)
 
 
-def test_two_step_cfl_becomes_active_with_skipping():
+@pytest.mark.parametrize("k", [2, 3])
+def test_multi_step_cfl_becomes_active_with_skipping(k):
     """A basin filled from one side: the speculated dt of the second step
     turns wrong, launches redo, then make one step each; meanwhile most of the
     basin is dry and skipped."""
@@ -282,18 +288,19 @@ def test_two_step_cfl_becomes_active_with_skipping():
                   (WEST, 20, 8, 1e-3, ts, qs), (EAST, 0, ny, 1e-3), dt_max=1.0)
     chunks = [150, 151, 40]
     ref = _run(sc, "f32", chunks, False, (1, 4))
-    got = _run(sc, "f32", chunks, True, fusion=(2, 1, 4))
+    got = _run(sc, "f32", chunks, True, fusion=(k, 1, 4))
     _same(got, ref, "basin", other_decomposition=True)
     assert ref[-1][3].last_dt < sc.dt_max
 
 
-def test_two_step_and_single_step_skipping_interleaved():
+@pytest.mark.parametrize("k", [2, 3])
+def test_multi_step_and_single_step_skipping_interleaved(k):
     """fl_step(1) (single-step launch), fl_advance (single-step launches) and
-    two-step runs, all skipping, hand the state to each other."""
+    multi-step runs, all skipping, hand the state to each other."""
     sc = patchy(200, 90, 12)
     seq = [1, 9, 2.0, 40, 1, 1, 33, 3.5, 20]
     ref = _run(sc, "f32", seq, False, (1, 4))
-    got = _run(sc, "f32", seq, True, (2, 8), fusion=(2, 2, 8))
+    got = _run(sc, "f32", seq, True, (2, 8), fusion=(k, 2, 8))
     _same(got, ref, "interleaved", other_decomposition=True)
 
 
@@ -316,40 +323,44 @@ def test_workspace_holds_the_flags():
     assert np.array_equal(h, ref)
 
 
-def test_two_step_short_calls_keep_their_flags():
-    """Many short two-step calls in a row: the flags carry over from one call
+@pytest.mark.parametrize("k", [2, 3])
+def test_multi_step_short_calls_keep_their_flags(k):
+    """Many short multi-step calls in a row: the flags carry over from one call
     to the next (nothing else moved the state), and the state stays that of
     computing everything."""
     sc = patchy(240, 100, 21)
     chunks = [4] * 25 + [3, 6, 2]
     ref = _run(sc, "f32", chunks, False, (1, 4))
-    got = _run(sc, "f32", chunks, True, fusion=(2, 2, 8))
+    got = _run(sc, "f32", chunks, True, fusion=(k, 2, 8))
     _same(got, ref, "short calls", other_decomposition=True)
 
 
-def test_two_step_dry_closed_grid_computes_nothing():
+@pytest.mark.parametrize("k", [2, 3])
+def test_multi_step_dry_closed_grid_computes_nothing(k):
     nx, ny = 300, 64
     z = synth._f32(np.random.default_rng(3).uniform(0, 1, (ny, nx)))
     n = np.full((ny, nx), 0.03, np.float32)
     sc = Scenario("dry", nx, ny, 1.0, z, n, np.zeros_like(z), None, None, dt_max=0.05)
-    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 8), active_tiles=True)
+    f = fl.from_scenario(sc, "f32", fusion=(k, 2, 8), active_tiles=True)
     f.step(10)
     nxt, tot = f.active_items()
-    assert tot == -(-(nx - 2) // 120) * (ny // 8) and nxt == 0, (nxt, tot)
+    w = 128 - 4 * k
+    assert tot == -(-(nx - (2 * k - 2)) // w) * (ny // 8) and nxt == 0, (nxt, tot)
     f.step(10)
     assert f.active_items()[0] == 0
     assert f.get_report().steps == 20 and not f.get_depth().any()
     f.close()
 
 
-def test_autotune_fusion_with_active_tiles_keeps_the_bits():
+@pytest.mark.parametrize("k", [2, 3])
+def test_autotune_fusion_with_active_tiles_keeps_the_bits(k):
     sc = patchy(200, 90, 33)
     ref = _run(sc, "f32", [60], False, (2, 8))
-    f = fl.from_scenario(sc, "f32", fusion=(2, 2, 8), cells_per_lane=2, rows_per_item=8,
+    f = fl.from_scenario(sc, "f32", fusion=(k, 2, 8), cells_per_lane=2, rows_per_item=8,
                          active_tiles=True)
     f.step(20)
     spl, ms = f.autotune_fusion(10)
-    assert spl in (1, 2) and ms > 0
+    assert spl in (1, k) and ms > 0
     f.step(40)
     h = f.get_depth()
     qx, qy = f.get_discharge()
