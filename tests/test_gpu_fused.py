@@ -212,13 +212,15 @@ def test_autotune_fusion_picks_multi_step_on_the_benchmark_grid():
 
 
 def test_three_steps_refusals():
-    """Three steps per launch: not with active tiles, not at 4 cells per lane;
-    steps per launch above 3 are refused."""
+    """Three steps per launch: not at 4 cells per lane, and with active tiles
+    not with items of fewer than three rows; steps per launch above 3 are
+    refused."""
     sc = config_d1()
     f = fl.Flood(sc.nx, sc.ny, sc.dx, "f32")
     with pytest.raises(fl.FloodError):
         f.set_fusion(4)
     f.close()
-    for kw in (dict(fusion=(3, 4, 0)), dict(fusion=3, active_tiles=True)):
+    for kw in (dict(fusion=(3, 4, 0)), dict(fusion=(3, 2, 2), active_tiles=True)):
         with pytest.raises(fl.FloodError):
             fl.from_scenario(sc, "f32", **kw).close()
+    fl.from_scenario(sc, "f32", fusion=3, active_tiles=True).close()
